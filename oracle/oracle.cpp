@@ -1,0 +1,734 @@
+// Oracle: a plain, slow, serial FP64 CPU evaluation of the thermochemical
+// source terms and the analytical chemical-kinetic Jacobian of Curtis,
+// Niemeyer & Sung (pyJac v2, arXiv:1809.01029), Sec. 2.2.
+//
+// THIS IS TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the
+// CPU-baseline leg of the benchmark load it.  It shares no code with the GPU
+// library: it parses the mechanism description itself, evaluates everything
+// with dense loops in the order the formulas are written, and uses no tables
+// derived by the library.
+//
+// Everything is templated on the scalar type S:
+//   * double                 - the values;
+//   * std::complex<double>   - complex-step derivatives (a check of the
+//                              hand-derived Jacobian, exact to rounding);
+//   * Scaled                 - value plus an "absolute-term" scale: every
+//                              addition or subtraction adds the magnitudes
+//                              of its operands, products and quotients
+//                              multiply them, functions take the magnitude of
+//                              their value.  The scale equals |value| when
+//                              nothing cancels and grows by the amount of
+//                              cancellation otherwise; parity tolerances are
+//                              relative to it.
+//
+// Units: SI with kmol.  R_u = 8314.462618 J/(kmol K), P_ref = 101325 Pa.
+// State vector (Sec. 2.2): Phi = (T, V, n_1..n_{Ns-1}) for constant pressure
+// (parameter P) and (T, P, n_1..n_{Ns-1}) for constant volume (parameter V);
+// the last species is the bath gas, closed by the ideal-gas law.
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace {
+
+const double RU = 8314.462618;
+const double PREF = 101325.0;
+const double LN10 = 2.302585092994045684;
+
+enum { FORM_CONP = 0, FORM_CONV = 1 };
+enum { T_ELEM = 0, T_THREEBODY = 1, T_LINDEMANN = 2, T_TROE = 3 };
+
+struct Species {
+    double W;
+    int comp[4];
+    double tlow, tmid, thigh;
+    double alo[7], ahi[7];
+};
+
+struct Reaction {
+    int type;
+    bool rev;
+    std::vector<std::pair<int, int>> reac, prod;   // (species, coefficient)
+    double lnA, b, theta;
+    double lnA0 = 0, b0 = 0, theta0 = 0;            // low-pressure limit
+    double alpha = 0, T3 = 0, T1 = 0, T2 = 0;       // Troe
+    std::vector<std::pair<int, double>> eff;        // (species, efficiency)
+};
+
+struct Mech {
+    int ns = 0;
+    std::vector<Species> sp;
+    std::vector<Reaction> rx;
+};
+
+// ---------------------------------------------------------------------------
+// scalar types
+
+struct Scaled {
+    double v, s;
+    Scaled() : v(0), s(0) {}
+    Scaled(double x) : v(x), s(std::fabs(x)) {}
+    Scaled(double x, double sc) : v(x), s(sc) {}
+};
+inline Scaled operator+(Scaled a, Scaled b) { return Scaled(a.v + b.v, a.s + b.s); }
+inline Scaled operator-(Scaled a, Scaled b) { return Scaled(a.v - b.v, a.s + b.s); }
+inline Scaled operator-(Scaled a) { return Scaled(-a.v, a.s); }
+inline Scaled operator*(Scaled a, Scaled b) { return Scaled(a.v * b.v, a.s * b.s); }
+// A quotient multiplies the amplifications of numerator and denominator,
+// s(a/b) = (s_a/|b|) (s_b/|b|), as a product does: s(ab) = s_a s_b.  With
+// operands that carry no cancellation both give |value|.
+inline Scaled operator/(Scaled a, Scaled b) {
+    double ab = std::fabs(b.v);
+    return Scaled(a.v / b.v, (a.s / ab) * (b.s / ab));
+}
+inline Scaled& operator+=(Scaled& a, Scaled b) { a = a + b; return a; }
+inline Scaled& operator-=(Scaled& a, Scaled b) { a = a - b; return a; }
+inline Scaled exp(Scaled a) { double e = std::exp(a.v); return Scaled(e, e); }
+inline Scaled log(Scaled a) { double l = std::log(a.v); return Scaled(l, std::fabs(l) + a.s / std::fabs(a.v)); }
+inline Scaled log10(Scaled a) { double l = std::log10(a.v); return Scaled(l, std::fabs(l) + a.s / (LN10 * std::fabs(a.v))); }
+
+inline double re(double x) { return x; }
+inline double re(const std::complex<double>& x) { return x.real(); }
+inline double re(const Scaled& x) { return x.v; }
+
+using std::exp;
+using std::log;
+using std::log10;
+
+// The closure needs the exactly rounded sum of the species moles
+// (s = RN(sum_k n_k)), so that it does not depend on a summation order.
+// Quad precision (113-bit significand) gives it except for exact ties.
+inline double rn_sum(const double* v, int n) {
+    __float128 acc = 0;
+    for (int k = 0; k < n; ++k) acc += (__float128)v[k];
+    return (double)acc;
+}
+inline double exact_sum(const double* v, int n) { return rn_sum(v, n); }
+inline Scaled exact_sum(const Scaled* v, int n) {
+    std::vector<double> x(n);
+    for (int k = 0; k < n; ++k) x[k] = v[k].v;
+    return Scaled(rn_sum(x.data(), n));
+}
+inline std::complex<double> exact_sum(const std::complex<double>* v, int n) {
+    std::vector<double> x(n);
+    double im = 0;
+    for (int k = 0; k < n; ++k) { x[k] = v[k].real(); im += v[k].imag(); }
+    return std::complex<double>(rn_sum(x.data(), n), im);
+}
+
+// ---------------------------------------------------------------------------
+// description parsing
+
+int type_code(const std::string& t) {
+    if (t == "ELEM") return T_ELEM;
+    if (t == "THREEBODY") return T_THREEBODY;
+    if (t == "LINDEMANN") return T_LINDEMANN;
+    if (t == "TROE") return T_TROE;
+    return -1;
+}
+
+bool parse(const char* path, Mech& m) {
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string tok;
+    int ver;
+    if (!(f >> tok >> ver) || tok != "PJMECH" || ver != 1) return false;
+    int ns;
+    if (!(f >> tok >> ns) || tok != "SPECIES" || ns < 2) return false;
+    m.ns = ns;
+    m.sp.resize(ns);
+    for (int k = 0; k < ns; ++k) {
+        Species& s = m.sp[k];
+        int idx;
+        std::string name;
+        if (!(f >> tok >> idx >> name >> s.W) || tok != "SP" || idx != k) return false;
+        for (int e = 0; e < 4; ++e) f >> s.comp[e];
+        f >> s.tlow >> s.tmid >> s.thigh;
+        for (int c = 0; c < 7; ++c) f >> s.alo[c];
+        for (int c = 0; c < 7; ++c) f >> s.ahi[c];
+        if (!f) return false;
+    }
+    int nr;
+    if (!(f >> tok >> nr) || tok != "REACTIONS" || nr < 0) return false;
+    m.rx.resize(nr);
+    f >> tok;
+    for (int i = 0; i < nr; ++i) {
+        Reaction& r = m.rx[i];
+        int idx, rev, n;
+        std::string typ;
+        if (tok != "RX" || !(f >> idx >> typ >> rev >> n) || idx != i) return false;
+        r.type = type_code(typ);
+        if (r.type < 0) return false;
+        r.rev = rev != 0;
+        for (int a = 0; a < n; ++a) { int s, nu; f >> s >> nu; r.reac.push_back({s, nu}); }
+        f >> n;
+        for (int a = 0; a < n; ++a) { int s, nu; f >> s >> nu; r.prod.push_back({s, nu}); }
+        f >> r.lnA >> r.b >> r.theta;
+        while (f >> tok) {
+            if (tok == "LOW") f >> r.lnA0 >> r.b0 >> r.theta0;
+            else if (tok == "TROE") f >> r.alpha >> r.T3 >> r.T1 >> r.T2;
+            else if (tok == "EFF") {
+                f >> n;
+                for (int a = 0; a < n; ++a) { int s; double al; f >> s >> al; r.eff.push_back({s, al}); }
+            } else break;
+        }
+        if (!f) return false;
+    }
+    return tok == "END";
+}
+
+// ---------------------------------------------------------------------------
+// species thermodynamics: NASA 7-coefficient polynomials (Sec. 2.2, the
+// temperature source term uses H, U, Cp and Cv of each species)
+
+template <class S>
+struct Thermo {
+    S cp;      // Cp / R
+    S h;       // H / (R T)
+    S s;       // S / R
+    S dcp;     // d(Cp/R)/dT
+    S dh;      // d(H/(R T))/dT
+    S ds;      // d(S/R)/dT
+};
+
+template <class S>
+Thermo<S> species_thermo(const Species& sp, S T) {
+    const double* a = re(T) < sp.tmid ? sp.alo : sp.ahi;
+    S T2 = T * T, T3 = T2 * T, T4 = T3 * T;
+    Thermo<S> t;
+    t.cp = S(a[0]) + S(a[1]) * T + S(a[2]) * T2 + S(a[3]) * T3 + S(a[4]) * T4;
+    t.h = S(a[0]) + S(a[1]) * T / S(2.0) + S(a[2]) * T2 / S(3.0) + S(a[3]) * T3 / S(4.0)
+          + S(a[4]) * T4 / S(5.0) + S(a[5]) / T;
+    t.s = S(a[0]) * log(T) + S(a[1]) * T + S(a[2]) * T2 / S(2.0) + S(a[3]) * T3 / S(3.0)
+          + S(a[4]) * T4 / S(4.0) + S(a[6]);
+    t.dcp = S(a[1]) + S(2.0 * a[2]) * T + S(3.0 * a[3]) * T2 + S(4.0 * a[4]) * T3;
+    t.dh = S(a[1]) / S(2.0) + S(2.0 * a[2]) * T / S(3.0) + S(3.0 * a[3]) * T2 / S(4.0)
+           + S(4.0 * a[4]) * T3 / S(5.0) - S(a[5]) / T2;
+    t.ds = S(a[0]) / T + S(a[1]) + S(a[2]) * T + S(a[3]) * T2 + S(a[4]) * T3;
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// the thermochemical state and its concentrations
+
+template <class S>
+struct State {
+    S T, V, P;
+    std::vector<S> C;     // [C]_k for all Ns species, kmol/m^3
+    std::vector<S> n;     // moles of all Ns species
+};
+
+// [C]_k = n_k / V (Sec. 2.2); the bath gas from the ideal gas law P V = n R T:
+// n_Ns = P V / (R T) - RN(sum_{k<Ns} n_k).
+template <class S>
+State<S> make_state(const Mech& m, int form, const S* x, S param) {
+    State<S> st;
+    int ns = m.ns;
+    st.T = x[0];
+    if (form == FORM_CONP) { st.V = x[1]; st.P = param; }
+    else { st.P = x[1]; st.V = param; }
+    S ntot = (st.P * st.V) / (S(RU) * st.T);
+    S sum = exact_sum(x + 2, ns - 1);
+    st.n.resize(ns);
+    st.C.resize(ns);
+    for (int k = 0; k < ns - 1; ++k) st.n[k] = x[2 + k];
+    st.n[ns - 1] = ntot - sum;
+    for (int k = 0; k < ns; ++k) st.C[k] = st.n[k] / st.V;
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// reaction rates (Sec. 2.2: wdot_k = sum_i nu_ki R_i c_i)
+
+template <class S>
+struct RxnEval {
+    S kf, kr, c, Rf, Rr, q;
+    // derivatives, used by the Jacobian
+    S dkf_dT, dkr_dT;
+    S dc_dT;                    // at fixed concentrations
+    std::vector<S> dc_dC;       // dc/d[C]_m, all species
+    std::vector<S> dRf_dC, dRr_dC;
+    S dRf_dT, dRr_dT;
+    std::vector<S> dq_dC;       // dq/d[C]_m at fixed T
+    S dq_dT;                    // dq/dT at fixed concentrations
+};
+
+template <class S>
+S arrhenius(double lnA, double b, double theta, S T) {
+    return exp(S(lnA) + S(b) * log(T) - S(theta) / T);
+}
+
+template <class S>
+S ipow(S x, int nu) {
+    S r(1.0);
+    for (int a = 0; a < nu; ++a) r = r * x;
+    return r;
+}
+
+// product of [C]^nu over a side of the reaction, and its derivative by [C]_m
+template <class S>
+S mass_action(const std::vector<std::pair<int, int>>& side, const std::vector<S>& C) {
+    S p(1.0);
+    for (auto& e : side) p = p * ipow(C[e.first], e.second);
+    return p;
+}
+template <class S>
+S mass_action_d(const std::vector<std::pair<int, int>>& side, const std::vector<S>& C, int m) {
+    S d(0.0);
+    for (size_t a = 0; a < side.size(); ++a) {
+        if (side[a].first != m) continue;
+        int nu = side[a].second;
+        S t = S((double)nu) * ipow(C[m], nu - 1);
+        for (size_t b = 0; b < side.size(); ++b)
+            if (b != a) t = t * ipow(C[side[b].first], side[b].second);
+        d = d + t;
+    }
+    return d;
+}
+
+template <class S>
+RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
+                         const std::vector<Thermo<S>>& th, bool with_derivs) {
+    int ns = m.ns;
+    RxnEval<S> e;
+    S T = st.T;
+    e.kf = arrhenius(r.lnA, r.b, r.theta, T);
+    e.dkf_dT = e.kf * (S(r.b) / T + S(r.theta) / (T * T));
+
+    // reverse rate constant from the equilibrium constant:
+    //   ln Kc = -sum_k nu_k G_k/(R T) + (sum_k nu_k) ln(P_ref / (R T))
+    S sum_nu_g(0.0), sum_nu_dg(0.0);
+    int sum_nu = 0;
+    for (auto& p : r.reac) {
+        sum_nu_g = sum_nu_g - S((double)p.second) * (th[p.first].h - th[p.first].s);
+        sum_nu_dg = sum_nu_dg - S((double)p.second) * (th[p.first].dh - th[p.first].ds);
+        sum_nu -= p.second;
+    }
+    for (auto& p : r.prod) {
+        sum_nu_g = sum_nu_g + S((double)p.second) * (th[p.first].h - th[p.first].s);
+        sum_nu_dg = sum_nu_dg + S((double)p.second) * (th[p.first].dh - th[p.first].ds);
+        sum_nu += p.second;
+    }
+    if (r.rev) {
+        S lnKc = -sum_nu_g + S((double)sum_nu) * log(S(PREF) / (S(RU) * T));
+        S Kc = exp(lnKc);
+        S dlnKc_dT = -sum_nu_dg - S((double)sum_nu) / T;
+        e.kr = e.kf / Kc;
+        e.dkr_dT = e.dkf_dT / Kc - e.kf * (Kc * dlnKc_dT) / (Kc * Kc);
+    } else {
+        e.kr = S(0.0);
+        e.dkr_dT = S(0.0);
+    }
+
+    // falloff reactions use the high-pressure limit as k_f
+    e.Rf = e.kf * mass_action(r.reac, st.C);
+    e.Rr = r.rev ? e.kr * mass_action(r.prod, st.C) : S(0.0);
+
+    // pressure modification
+    std::vector<double> alpha(ns, 1.0);
+    for (auto& p : r.eff) alpha[p.first] = p.second;
+    S M(0.0);
+    if (r.type != T_ELEM)
+        for (int k = 0; k < ns; ++k) M = M + S(alpha[k]) * st.C[k];
+
+    e.dc_dC.assign(ns, S(0.0));
+    e.dc_dT = S(0.0);
+    if (r.type == T_ELEM) {
+        e.c = S(1.0);
+    } else if (r.type == T_THREEBODY) {
+        e.c = M;
+        for (int k = 0; k < ns; ++k) e.dc_dC[k] = S(alpha[k]);
+    } else {
+        S k0 = arrhenius(r.lnA0, r.b0, r.theta0, T);
+        S dk0_dT = k0 * (S(r.b0) / T + S(r.theta0) / (T * T));
+        S Pr = k0 * M / e.kf;
+        S dPr_dT = M * (dk0_dT * e.kf - k0 * e.dkf_dT) / (e.kf * e.kf);
+        S F(1.0), dF_dPr(0.0), dF_dT(0.0);
+        if (r.type == T_TROE) {
+            S Fcent = S(1.0 - r.alpha) * exp(-T / S(r.T3)) + S(r.alpha) * exp(-T / S(r.T1))
+                      + exp(-S(r.T2) / T);
+            S dFcent_dT = -S(1.0 - r.alpha) / S(r.T3) * exp(-T / S(r.T3))
+                          - S(r.alpha) / S(r.T1) * exp(-T / S(r.T1))
+                          + S(r.T2) / (T * T) * exp(-S(r.T2) / T);
+            S L = log10(Fcent);
+            S cc = S(-0.4) - S(0.67) * L;
+            S nn = S(0.75) - S(1.27) * L;
+            S A = log10(Pr) + cc;
+            S B = nn - S(0.14) * A;
+            S f = A / B;
+            S expo = L / (S(1.0) + f * f);       // log10 F
+            F = exp(S(LN10) * expo);
+            // d f / d log10(Pr) and d f / d L
+            S df_dlP = (B - A * S(-0.14)) / (B * B);
+            S dA_dL = S(-0.67);
+            S dB_dL = S(-1.27) - S(0.14) * dA_dL;
+            S df_dL = (dA_dL * B - A * dB_dL) / (B * B);
+            S dexpo_df = -L * S(2.0) * f / ((S(1.0) + f * f) * (S(1.0) + f * f));
+            S dexpo_dL = S(1.0) / (S(1.0) + f * f) + dexpo_df * df_dL;
+            // dF/dPr = F ln10 dexpo/df df/dlP dlP/dPr, dlP/dPr = 1/(Pr ln10)
+            dF_dPr = F * dexpo_df * df_dlP / Pr;
+            // dF/dT at fixed Pr, through Fcent: dL/dT = dFcent/dT / (Fcent ln10)
+            dF_dT = F * S(LN10) * dexpo_dL * dFcent_dT / (Fcent * S(LN10));
+        }
+        // c = F Pr / (1 + Pr), written as F / (1 + 1/Pr): the same value, but its
+        // complex-step derivative carries no cancellation when Pr >> 1
+        e.c = F / (S(1.0) + S(1.0) / Pr);
+        S dc_dPr = F / ((S(1.0) + Pr) * (S(1.0) + Pr)) + Pr / (S(1.0) + Pr) * dF_dPr;
+        e.dc_dT = dc_dPr * dPr_dT + Pr / (S(1.0) + Pr) * dF_dT;
+        for (int k = 0; k < ns; ++k) e.dc_dC[k] = dc_dPr * k0 * S(alpha[k]) / e.kf;
+    }
+    e.q = e.c * (e.Rf - e.Rr);
+    if (!with_derivs) return e;
+
+    e.dRf_dC.assign(ns, S(0.0));
+    e.dRr_dC.assign(ns, S(0.0));
+    for (int k = 0; k < ns; ++k) {
+        e.dRf_dC[k] = e.kf * mass_action_d(r.reac, st.C, k);
+        if (r.rev) e.dRr_dC[k] = e.kr * mass_action_d(r.prod, st.C, k);
+    }
+    e.dRf_dT = e.dkf_dT * mass_action(r.reac, st.C);
+    e.dRr_dT = r.rev ? e.dkr_dT * mass_action(r.prod, st.C) : S(0.0);
+    e.dq_dC.assign(ns, S(0.0));
+    for (int k = 0; k < ns; ++k)
+        e.dq_dC[k] = e.dc_dC[k] * (e.Rf - e.Rr) + e.c * (e.dRf_dC[k] - e.dRr_dC[k]);
+    e.dq_dT = e.dc_dT * (e.Rf - e.Rr) + e.c * (e.dRf_dT - e.dRr_dT);
+    return e;
+}
+
+template <class S>
+int net_nu(const Reaction& r, int k) {
+    int nu = 0;
+    for (auto& p : r.reac) if (p.first == k) nu -= p.second;
+    for (auto& p : r.prod) if (p.first == k) nu += p.second;
+    return nu;
+}
+
+// ---------------------------------------------------------------------------
+// source terms
+
+template <class S>
+struct Eval {
+    State<S> st;
+    std::vector<Thermo<S>> th;
+    std::vector<RxnEval<S>> rx;
+    std::vector<S> wdot;          // all Ns species
+    std::vector<S> e, chat;       // H or U, Cp or Cv  (J/kmol, J/(kmol K))
+    S N, D, Tdot, Omega, Sdot;
+    std::vector<S> f;             // d Phi / dt
+};
+
+template <class S>
+Eval<S> evaluate(const Mech& m, int form, const S* x, S param, bool with_derivs) {
+    Eval<S> ev;
+    int ns = m.ns, nr = (int)m.rx.size();
+    ev.st = make_state(m, form, x, param);
+    S T = ev.st.T;
+    ev.th.resize(ns);
+    for (int k = 0; k < ns; ++k) ev.th[k] = species_thermo(m.sp[k], T);
+    ev.rx.resize(nr);
+    for (int i = 0; i < nr; ++i) ev.rx[i] = eval_reaction(m, m.rx[i], ev.st, ev.th, with_derivs);
+
+    ev.wdot.assign(ns, S(0.0));
+    for (int k = 0; k < ns; ++k)
+        for (int i = 0; i < nr; ++i) {
+            int nu = net_nu<S>(m.rx[i], k);
+            if (nu) ev.wdot[k] = ev.wdot[k] + S((double)nu) * ev.rx[i].q;
+        }
+
+    // temperature source term: dT/dt = -sum_k e_k wdot_k / sum_k [C]_k chat_k
+    ev.e.resize(ns);
+    ev.chat.resize(ns);
+    for (int k = 0; k < ns; ++k) {
+        S H = S(RU) * T * ev.th[k].h;
+        S Cp = S(RU) * ev.th[k].cp;
+        if (form == FORM_CONP) { ev.e[k] = H; ev.chat[k] = Cp; }
+        else { ev.e[k] = H - S(RU) * T; ev.chat[k] = Cp - S(RU); }
+    }
+    ev.N = S(0.0);
+    ev.D = S(0.0);
+    for (int k = 0; k < ns; ++k) {
+        ev.N = ev.N + ev.e[k] * ev.wdot[k];
+        ev.D = ev.D + ev.st.C[k] * ev.chat[k];
+    }
+    ev.Tdot = -ev.N / ev.D;
+
+    // volume / pressure source term from d(PV = nRT)/dt with the bath gas
+    // closed by conservation of mass: dn_Ns/dt = -sum_{k<Ns} W_k/W_Ns dn_k/dt
+    double Wb = m.sp[ns - 1].W;
+    ev.Omega = S(0.0);
+    for (int k = 0; k < ns - 1; ++k)
+        ev.Omega = ev.Omega + S(1.0 - m.sp[k].W / Wb) * ev.wdot[k];
+    if (form == FORM_CONP)
+        ev.Sdot = ev.st.V * ev.Tdot / T + ev.st.V * S(RU) * T * ev.Omega / ev.st.P;
+    else
+        ev.Sdot = ev.st.P * ev.Tdot / T + S(RU) * T * ev.Omega;
+
+    ev.f.resize(ns + 1);
+    ev.f[0] = ev.Tdot;
+    ev.f[1] = ev.Sdot;
+    for (int k = 0; k < ns - 1; ++k) ev.f[2 + k] = ev.st.V * ev.wdot[k];
+    return ev;
+}
+
+// ---------------------------------------------------------------------------
+// analytical Jacobian J[i][j] = d(dPhi_i/dt)/dPhi_j (Sec. 2.2), by the chain
+// rule through the concentrations.
+
+template <class S>
+void jacobian(const Mech& m, int form, const S* x, S param, S* J) {
+    int ns = m.ns, nr = (int)m.rx.size(), N = ns + 1, bath = ns - 1;
+    Eval<S> ev = evaluate(m, form, x, param, true);
+    const State<S>& st = ev.st;
+    S T = st.T, V = st.V, P = st.P;
+
+    // dC[k][j] = d[C]_k / dPhi_j; nz marks the entries that are not
+    // identically zero (the others are skipped in the chain rule below).
+    std::vector<S> dC((size_t)ns * N, S(0.0));
+    std::vector<char> nz((size_t)ns * N, 0);
+    auto set = [&](int k, int j, S v) { dC[(size_t)k * N + j] = v; nz[(size_t)k * N + j] = 1; };
+    auto dc = [&](int k, int j) -> S { return dC[(size_t)k * N + j]; };
+    S sumC(0.0);
+    for (int k = 0; k < ns - 1; ++k) sumC = sumC + st.C[k];
+    set(bath, 0, -(P / (S(RU) * T)) / T);
+    if (form == FORM_CONP) {
+        for (int k = 0; k < ns - 1; ++k) set(k, 1, -st.C[k] / V);
+        set(bath, 1, sumC / V);
+    } else {
+        set(bath, 1, S(1.0) / (S(RU) * T));
+    }
+    for (int j = 0; j < ns - 1; ++j) {
+        set(j, 2 + j, S(1.0) / V);
+        set(bath, 2 + j, -S(1.0) / V);
+    }
+
+    // dq_i/dPhi_j = sum_k dq_i/d[C]_k d[C]_k/dPhi_j (+ dq_i/dT at fixed [C] for j = T)
+    std::vector<S> dq((size_t)nr * N, S(0.0));
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < N; ++j) {
+            S acc = (j == 0) ? ev.rx[i].dq_dT : S(0.0);
+            for (int k = 0; k < ns; ++k)
+                if (nz[(size_t)k * N + j]) acc = acc + ev.rx[i].dq_dC[k] * dc(k, j);
+            dq[(size_t)i * N + j] = acc;
+        }
+
+    // dwdot_k/dPhi_j for every species, bath gas included
+    std::vector<S> dw((size_t)ns * N, S(0.0));
+    for (int k = 0; k < ns; ++k)
+        for (int i = 0; i < nr; ++i) {
+            int nu = net_nu<S>(m.rx[i], k);
+            if (!nu) continue;
+            for (int j = 0; j < N; ++j)
+                dw[(size_t)k * N + j] = dw[(size_t)k * N + j] + S((double)nu) * dq[(size_t)i * N + j];
+        }
+
+    // temperature row
+    std::vector<S> dTdot(N);
+    for (int j = 0; j < N; ++j) {
+        S dN(0.0), dD(0.0);
+        for (int k = 0; k < ns; ++k) {
+            dN = dN + ev.e[k] * dw[(size_t)k * N + j];
+            if (nz[(size_t)k * N + j]) dD = dD + ev.chat[k] * dc(k, j);
+        }
+        if (j == 0) {
+            for (int k = 0; k < ns; ++k) {
+                // de_k/dT from the polynomial: H = R T h(T) -> dH/dT = R (h + T dh/dT);
+                // U = H - R T -> dU/dT = dH/dT - R.  dchat_k/dT = R dcp/dT.
+                S dH = S(RU) * (ev.th[k].h + T * ev.th[k].dh);
+                S de = (form == FORM_CONP) ? dH : dH - S(RU);
+                dN = dN + de * ev.wdot[k];
+                dD = dD + st.C[k] * S(RU) * ev.th[k].dcp;
+            }
+        }
+        dTdot[j] = -(dN * ev.D - ev.N * dD) / (ev.D * ev.D);
+    }
+
+    // Omega = sum_{k<Ns} (1 - W_k/W_Ns) wdot_k
+    double Wb = m.sp[bath].W;
+    std::vector<S> dOm(N, S(0.0));
+    for (int j = 0; j < N; ++j)
+        for (int k = 0; k < ns - 1; ++k)
+            dOm[j] = dOm[j] + S(1.0 - m.sp[k].W / Wb) * dw[(size_t)k * N + j];
+
+    for (int j = 0; j < N; ++j) {
+        S dT_j = (j == 0) ? S(1.0) : S(0.0);
+        S dS_j = (j == 1) ? S(1.0) : S(0.0);
+        J[0 * N + j] = dTdot[j];
+        if (form == FORM_CONP) {
+            // dV/dt = V Tdot / T + V R T Omega / P
+            J[1 * N + j] = dS_j * (ev.Tdot / T + S(RU) * T * ev.Omega / P)
+                           + V * (dTdot[j] / T - ev.Tdot * dT_j / (T * T))
+                           + V * S(RU) * (dT_j * ev.Omega + T * dOm[j]) / P;
+        } else {
+            // dP/dt = P Tdot / T + R T Omega
+            J[1 * N + j] = dS_j * ev.Tdot / T
+                           + P * (dTdot[j] / T - ev.Tdot * dT_j / (T * T))
+                           + S(RU) * (dT_j * ev.Omega + T * dOm[j]);
+        }
+        for (int k = 0; k < ns - 1; ++k) {
+            // dn_k/dt = V wdot_k
+            S dV_j = (form == FORM_CONP && j == 1) ? S(1.0) : S(0.0);
+            J[(2 + k) * N + j] = V * dw[(size_t)k * N + j] + dV_j * ev.wdot[k];
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// structural sparsity pattern (Sec. 3.4): the temperature and state-parameter
+// rows and columns are dense; species row k has column j when some reaction
+// with a non-zero net coefficient of k has a rate of progress that depends on
+// [C]_j (j a reactant, a product of a reversible reaction, or a third body
+// with an efficiency other than the bath gas's); a rate that depends on the
+// bath gas makes the row dense.  The diagonal is always present.
+
+void pattern(const Mech& m, unsigned char* P) {
+    int ns = m.ns, N = ns + 1, bath = ns - 1;
+    std::memset(P, 0, (size_t)N * N);
+    for (int j = 0; j < N; ++j) { P[0 * N + j] = 1; P[1 * N + j] = 1; P[j * N + 0] = 1; P[j * N + 1] = 1; P[j * N + j] = 1; }
+    for (const Reaction& r : m.rx) {
+        std::vector<char> dep(ns, 0);
+        for (auto& p : r.reac) dep[p.first] = 1;
+        if (r.rev) for (auto& p : r.prod) dep[p.first] = 1;
+        if (r.type != T_ELEM) {
+            std::vector<double> alpha(ns, 1.0);
+            for (auto& p : r.eff) alpha[p.first] = p.second;
+            for (int k = 0; k < ns; ++k) if (alpha[k] != alpha[bath]) dep[k] = 1;
+            if (alpha[bath] != 1.0) dep[bath] = 1;
+        }
+        for (int k = 0; k < ns - 1; ++k) {
+            if (net_nu<double>(r, k) == 0) continue;
+            for (int j = 0; j < ns - 1; ++j)
+                if (dep[j] || dep[bath]) P[(size_t)(2 + k) * N + 2 + j] = 1;
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C interface (ctypes)
+
+extern "C" {
+
+void* ora_load(const char* path) {
+    Mech* m = new Mech();
+    if (!parse(path, *m)) { delete m; return nullptr; }
+    return m;
+}
+
+void ora_free(void* h) { delete static_cast<Mech*>(h); }
+
+int ora_ns(void* h) { return static_cast<Mech*>(h)->ns; }
+int ora_nr(void* h) { return (int)static_cast<Mech*>(h)->rx.size(); }
+
+void ora_thermo(void* h, int k, double T, double* out /* cp, h, s, dcp, dh, ds */) {
+    const Mech& m = *static_cast<Mech*>(h);
+    Thermo<double> t = species_thermo(m.sp[k], T);
+    out[0] = t.cp; out[1] = t.h; out[2] = t.s; out[3] = t.dcp; out[4] = t.dh; out[5] = t.ds;
+}
+
+// Sub-components at one state: per reaction kf, kr, c, Rf, Rr, q (6*nr),
+// then wdot (ns), then C (ns), then (Tdot, Sdot, N, D, Omega).
+void ora_components(void* h, int form, const double* x, double param, double* out) {
+    const Mech& m = *static_cast<Mech*>(h);
+    Eval<double> ev = evaluate(m, form, x, param, false);
+    int nr = (int)m.rx.size(), ns = m.ns;
+    for (int i = 0; i < nr; ++i) {
+        const RxnEval<double>& r = ev.rx[i];
+        double* o = out + 6 * i;
+        o[0] = r.kf; o[1] = r.kr; o[2] = r.c; o[3] = r.Rf; o[4] = r.Rr; o[5] = r.q;
+    }
+    for (int k = 0; k < ns; ++k) out[6 * nr + k] = ev.wdot[k];
+    for (int k = 0; k < ns; ++k) out[6 * nr + ns + k] = ev.st.C[k];
+    double* t = out + 6 * nr + 2 * ns;
+    t[0] = ev.Tdot; t[1] = ev.Sdot; t[2] = ev.N; t[3] = ev.D; t[4] = ev.Omega;
+}
+
+// Source terms for n states, state rows of length N (row-major), optional scales.
+void ora_source(void* h, int form, long n, const double* x, const double* param,
+                double* f, double* scale) {
+    const Mech& m = *static_cast<Mech*>(h);
+    int N = m.ns + 1;
+    for (long s = 0; s < n; ++s) {
+        const double* xs = x + s * N;
+        if (scale) {
+            std::vector<Scaled> xx(N);
+            for (int i = 0; i < N; ++i) xx[i] = Scaled(xs[i]);
+            Eval<Scaled> ev = evaluate(m, form, xx.data(), Scaled(param[s]), false);
+            for (int i = 0; i < N; ++i) { f[s * N + i] = ev.f[i].v; scale[s * N + i] = ev.f[i].s; }
+        } else {
+            Eval<double> ev = evaluate(m, form, xs, param[s], false);
+            for (int i = 0; i < N; ++i) f[s * N + i] = ev.f[i];
+        }
+    }
+}
+
+// Analytical Jacobian, dense row-major N*N per state, optional scales.
+void ora_jacobian(void* h, int form, long n, const double* x, const double* param,
+                  double* J, double* scale) {
+    const Mech& m = *static_cast<Mech*>(h);
+    int N = m.ns + 1;
+    size_t NN = (size_t)N * N;
+    for (long s = 0; s < n; ++s) {
+        const double* xs = x + s * N;
+        if (scale) {
+            std::vector<Scaled> xx(N), JJ(NN);
+            for (int i = 0; i < N; ++i) xx[i] = Scaled(xs[i]);
+            jacobian(m, form, xx.data(), Scaled(param[s]), JJ.data());
+            for (size_t e = 0; e < NN; ++e) { J[s * NN + e] = JJ[e].v; scale[s * NN + e] = JJ[e].s; }
+        } else {
+            jacobian(m, form, xs, param[s], J + s * NN);
+        }
+    }
+}
+
+// Complex-step Jacobian: column j = Im f(Phi + i h_j e_j) / h_j with
+// h_j = hrel * max(|Phi_j|, 1e-300).
+void ora_jacobian_cs(void* h, int form, long n, const double* x, const double* param,
+                     double hrel, double* J) {
+    const Mech& m = *static_cast<Mech*>(h);
+    int N = m.ns + 1;
+    typedef std::complex<double> C;
+    for (long s = 0; s < n; ++s) {
+        const double* xs = x + s * N;
+        for (int j = 0; j < N; ++j) {
+            std::vector<C> xx(N);
+            for (int i = 0; i < N; ++i) xx[i] = C(xs[i], 0.0);
+            double hj = hrel * std::fmax(std::fabs(xs[j]), 1e-300);
+            xx[j] = C(xs[j], hj);
+            Eval<C> ev = evaluate(m, form, xx.data(), C(param[s], 0.0), false);
+            for (int i = 0; i < N; ++i) J[(size_t)s * N * N + (size_t)i * N + j] = ev.f[i].imag() / hj;
+        }
+    }
+}
+
+// Central finite-difference Jacobian with step h_j = rel * max(|Phi_j|, 1e-300).
+void ora_jacobian_fd(void* h, int form, long n, const double* x, const double* param,
+                     double rel, double* J) {
+    const Mech& m = *static_cast<Mech*>(h);
+    int N = m.ns + 1;
+    for (long s = 0; s < n; ++s) {
+        const double* xs = x + s * N;
+        for (int j = 0; j < N; ++j) {
+            std::vector<double> xp(xs, xs + N), xm(xs, xs + N);
+            double hj = rel * std::fmax(std::fabs(xs[j]), 1e-300);
+            xp[j] += hj;
+            xm[j] -= hj;
+            Eval<double> ep = evaluate(m, form, xp.data(), param[s], false);
+            Eval<double> em = evaluate(m, form, xm.data(), param[s], false);
+            for (int i = 0; i < N; ++i)
+                J[(size_t)s * N * N + (size_t)i * N + j] = (ep.f[i] - em.f[i]) / (xp[j] - xm[j]);
+        }
+    }
+}
+
+void ora_pattern(void* h, unsigned char* P) { pattern(*static_cast<Mech*>(h), P); }
+
+}  // extern "C"

@@ -1,0 +1,512 @@
+"""Pins of the CPU oracle to facts other than itself.
+
+Each test checks the oracle against something the paper or the mathematics
+fixes: closed forms on hand-built micro-mechanisms, conservation of elements,
+mass and energy, the ideal-gas law, a constructed detailed-balance
+equilibrium, textbook limits of the falloff forms, thermodynamic identities,
+and complex-step / central-difference derivatives of the source terms for the
+analytical Jacobian.  A dropped term, a wrong sign, a wrong index or a
+transposed operand anywhere in the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_01029_amd import synth
+from conftest import TINY_SEEDS, tiny_file, workload_file
+
+R = 8314.462618
+PREF = 101325.0
+ATM = 101325.0
+
+
+# ---------------------------------------------------------------------------
+# hand-built micro-mechanisms
+
+def const_cp_species(cp, h298, s298):
+    """NASA-7 rows for a species of constant Cp/R: H/R(298.15) = h298,
+    S/R(298.15) = s298 (same polynomial in both ranges)."""
+    a6 = h298 - cp * 298.15
+    a7 = s298 - cp * math.log(298.15)
+    row = np.array([cp, 0, 0, 0, 0, a6, a7], dtype=float)
+    return row
+
+
+def micro(species, reactions):
+    """species: list of (name, comp(C,H,O,N), cp, h298, s298); last is the bath."""
+    comp = np.array([s[1] for s in species], dtype=np.int64)
+    W = comp @ np.array(synth.ATOMIC_WEIGHTS)
+    rows = np.array([const_cp_species(*s[2:]) for s in species])
+    return synth.Mechanism(names=[s[0] for s in species], W=W, comp=comp,
+                           tmid=np.full(len(species), 1000.0), a_lo=rows.copy(),
+                           a_hi=rows.copy(), reactions=reactions)
+
+
+def write(m, tmp_path, name):
+    p = str(tmp_path / f"{name}.pjm")
+    synth.write_mechanism(m, p)
+    return oracle.Oracle(p)
+
+
+def state_vec(T, V, moles):
+    return np.array([T, V] + list(moles), dtype=float)
+
+
+SPECIES_ABC = [("A", (0, 1, 0, 0), 2.5, 2.6e4, 14.0),
+               ("B", (0, 0, 1, 0), 2.5, 3.0e4, 19.0),
+               ("C", (0, 1, 1, 0), 3.5, 4.5e3, 22.0),
+               ("N2", (0, 0, 0, 2), 3.5, 0.0, 23.0)]
+
+
+def g_RT(sp, T):
+    cp, h298, s298 = sp[2:]
+    a6 = h298 - cp * 298.15
+    a7 = s298 - cp * math.log(298.15)
+    h = cp + a6 / T
+    s = cp * math.log(T) + a7
+    return h - s
+
+
+# ---------------------------------------------------------------------------
+# thermodynamics
+
+def test_thermo_monatomic_closed_form(tmp_path):
+    # A monatomic ideal gas has Cp = 5/2 R exactly; then H = 5/2 R T + H0 and
+    # S = 5/2 R ln T + S0.
+    m = micro(SPECIES_ABC, [synth.Reaction("ELEM", True, [(0, 1), (1, 1)], [(2, 1)], 20.0, 0.0, 0.0)])
+    o = write(m, tmp_path, "mono")
+    a6 = 2.6e4 - 2.5 * 298.15
+    a7 = 14.0 - 2.5 * math.log(298.15)
+    for T in (300.0, 999.0, 1000.0, 2500.0):
+        cp, h, s, dcp, dh, ds = o.thermo(0, T)
+        assert cp == 2.5 and dcp == 0.0
+        assert h == pytest.approx(2.5 + a6 / T, rel=1e-15)
+        assert s == pytest.approx(2.5 * math.log(T) + a7, rel=1e-15)
+        assert dh == pytest.approx(-a6 / T ** 2, rel=1e-14)
+        assert ds == pytest.approx(2.5 / T, rel=1e-15)
+
+
+def test_thermo_identities_generated(mech_dir):
+    # For any species: dH/dT = Cp and dS/dT = Cp/T (H = R T h, S = R s).  The
+    # oracle's own derivative outputs must match central differences of its
+    # values, and the identities must hold on those differences.
+    m, path = workload_file("ns53", mech_dir)
+    o = oracle.Oracle(path)
+    for k in (0, 7, 23, 52):
+        for T in (650.0, 1400.0, 2100.0):
+            dT = 1e-3
+            p = o.thermo(k, T + dT)
+            q = o.thermo(k, T - dT)
+            c = o.thermo(k, T)
+            fd = (p - q) / (2 * dT)
+            assert fd[0] == pytest.approx(c[3], rel=1e-6, abs=1e-12)
+            assert fd[1] == pytest.approx(c[4], rel=1e-6, abs=1e-12)
+            assert fd[2] == pytest.approx(c[5], rel=1e-6, abs=1e-12)
+            # d(T h)/dT = cp  and  ds/dT = cp / T
+            dTh = ((T + dT) * p[1] - (T - dT) * q[1]) / (2 * dT)
+            assert dTh == pytest.approx(c[0], rel=1e-7)
+            assert fd[2] == pytest.approx(c[0] / T, rel=1e-7)
+
+
+@pytest.mark.parametrize("name", ["ns13", "ns111"])
+def test_thermo_continuity_at_tmid(name, mech_dir):
+    # The generator promises Cp, H and S continuous at 1000 K.
+    m, path = workload_file(name, mech_dir)
+    o = oracle.Oracle(path)
+    below = np.nextafter(1000.0, 0.0)
+    for k in range(m.n_species):
+        lo = o.thermo(k, below)[:3]
+        hi = o.thermo(k, 1000.0)[:3]
+        np.testing.assert_allclose(lo, hi, rtol=1e-11, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# rate constants, equilibrium, rates of progress
+
+def _abc(tmp_path, rtype="ELEM", rev=True, low=None, troe=None, eff=(), lnA=30.0, b=0.7, th=5000.0):
+    rx = synth.Reaction(rtype, rev, [(0, 1), (1, 1)], [(2, 1)], lnA, b, th, low=low, troe=troe,
+                        eff=list(eff))
+    m = micro(SPECIES_ABC, [rx])
+    return m, write(m, tmp_path, f"abc_{rtype}_{int(rev)}")
+
+
+def _abc_state(T=1300.0, V=1.0, nA=0.02, nB=0.015, nC=0.04, P=3 * ATM):
+    return state_vec(T, V, [nA, nB, nC]), P
+
+
+def test_arrhenius_equilibrium_rop_closed_form(tmp_path):
+    m, o = _abc(tmp_path)
+    x, P = _abc_state()
+    T, V = x[0], x[1]
+    c = o.components(x, P, "conp")
+    kf = math.exp(30.0) * T ** 0.7 * math.exp(-5000.0 / T)
+    assert c["kf"][0] == pytest.approx(kf, rel=1e-13)
+    # A + B = C: Kc = Kp (P_ref / (R T))^(-1), Kp = exp(-(gC - gA - gB))
+    dg = g_RT(SPECIES_ABC[2], T) - g_RT(SPECIES_ABC[0], T) - g_RT(SPECIES_ABC[1], T)
+    Kc = math.exp(-dg) * (R * T / PREF)
+    assert c["kr"][0] == pytest.approx(kf / Kc, rel=1e-12)
+    CA, CB, CC = x[2] / V, x[3] / V, x[4] / V
+    assert c["Rf"][0] == pytest.approx(kf * CA * CB, rel=1e-13)
+    assert c["Rr"][0] == pytest.approx(kf / Kc * CC, rel=1e-12)
+    q = kf * CA * CB - kf / Kc * CC
+    assert c["q"][0] == pytest.approx(q, rel=1e-11)
+    np.testing.assert_allclose(c["wdot"], [-q, -q, q, 0.0], rtol=1e-11, atol=0)
+    # bath gas from P V = n R T
+    ntot = P * V / (R * T)
+    assert c["C"][3] == pytest.approx((ntot - (x[2] + x[3] + x[4])) / V, rel=1e-14)
+
+
+def test_irreversible_has_no_reverse_rate(tmp_path):
+    m, o = _abc(tmp_path, rev=False)
+    x, P = _abc_state()
+    c = o.components(x, P, "conp")
+    assert c["kr"][0] == 0.0 and c["Rr"][0] == 0.0
+    assert c["q"][0] == pytest.approx(c["kf"][0] * x[2] * x[3], rel=1e-14)
+
+
+def test_rate_constant_special_case_b_theta_zero(tmp_path):
+    # b = 0 and Ea = 0 give k = A exactly (up to exp(log A) rounding)
+    m, o = _abc(tmp_path, lnA=math.log(3.7e11), b=0.0, th=0.0)
+    x, P = _abc_state()
+    assert o.components(x, P)["kf"][0] == pytest.approx(3.7e11, rel=1e-14)
+
+
+def test_third_body_closed_form(tmp_path):
+    eff = [(0, 2.5), (2, 0.6)]
+    m, o = _abc(tmp_path, rtype="THREEBODY", eff=eff)
+    x, P = _abc_state()
+    V = x[1]
+    c = o.components(x, P)
+    C = c["C"]
+    M = 2.5 * C[0] + 1.0 * C[1] + 0.6 * C[2] + 1.0 * C[3]
+    assert c["c"][0] == pytest.approx(M, rel=1e-14)
+    assert c["q"][0] == pytest.approx(M * (c["Rf"][0] - c["Rr"][0]), rel=1e-13)
+    # all efficiencies one: [M] is the total concentration P / (R T)
+    m1, o1 = _abc(tmp_path, rtype="THREEBODY", eff=[])
+    c1 = o1.components(x, P)
+    assert c1["c"][0] == pytest.approx(P / (R * x[0]), rel=1e-13)
+    del V
+
+
+def test_lindemann_closed_form_and_limits(tmp_path):
+    low = (40.0, -0.5, 2000.0)
+    m, o = _abc(tmp_path, rtype="LINDEMANN", low=low)
+    x, P = _abc_state()
+    T = x[0]
+    c = o.components(x, P)
+    M = P / (R * T)
+    kinf = math.exp(30.0) * T ** 0.7 * math.exp(-5000.0 / T)
+    k0 = math.exp(40.0) * T ** -0.5 * math.exp(-2000.0 / T)
+    # Lindemann: effective forward constant k0 kinf [M] / (kinf + k0 [M])
+    keff = k0 * kinf * M / (kinf + k0 * M)
+    assert c["c"][0] * c["kf"][0] == pytest.approx(keff, rel=1e-13)
+    # Pr -> infinity: c -> 1 ; Pr -> 0: c -> Pr
+    for P_, lim in ((1e12 * ATM, "hi"), (1e-12 * ATM, "lo")):
+        ntot = P_ * 1.0 / (R * 1300.0)
+        xs = state_vec(1300.0, 1.0, [0.2 * ntot, 0.3 * ntot, 0.1 * ntot])[None]
+        cc = o.components(xs[0], P_)
+        Mx = P_ / (R * xs[0, 0])
+        kinf_ = math.exp(30.0) * xs[0, 0] ** 0.7 * math.exp(-5000.0 / xs[0, 0])
+        k0_ = math.exp(40.0) * xs[0, 0] ** -0.5 * math.exp(-2000.0 / xs[0, 0])
+        Pr = k0_ * Mx / kinf_
+        if lim == "hi":
+            assert Pr > 1e8 and cc["c"][0] == pytest.approx(1.0, rel=10 / Pr)
+        else:
+            assert Pr < 1e-8 and cc["c"][0] / Pr == pytest.approx(1.0, rel=10 * Pr + 1e-12)
+
+
+def _troe_setup(tmp_path, troe, Pr_target, T=1200.0, P=2 * ATM, name="troe"):
+    # kinf = A_inf, k0 = A0 (b = theta = 0) so that Pr = A0 [M] / A_inf is set exactly
+    M = P / (R * T)
+    Ainf = 1e13
+    A0 = Pr_target * Ainf / M
+    rx = synth.Reaction("TROE", True, [(0, 1), (1, 1)], [(2, 1)], math.log(Ainf), 0.0, 0.0,
+                        low=(math.log(A0), 0.0, 0.0), troe=troe)
+    m = micro(SPECIES_ABC, [rx])
+    o = write(m, tmp_path, name)
+    x = state_vec(T, 1.0, [0.01, 0.02, 0.03])
+    c = o.components(x, P)
+    Pr = A0 * M / Ainf
+    F = c["c"][0] * (1 + Pr) / Pr
+    return F, Pr, T
+
+
+def test_troe_reduces_to_lindemann(tmp_path):
+    # alpha = 1, T* -> infinity, T** -> infinity: Fcent = 1, so F = 1
+    F, Pr, T = _troe_setup(tmp_path, (1.0, 300.0, 1e300, 1e300), 0.7)
+    assert F == pytest.approx(1.0, rel=1e-14)
+
+
+def test_troe_center_and_width(tmp_path):
+    # Troe broadening: log10 F = log10 Fc / (1 + f^2), f = (log10 Pr + c)/(n - 0.14 (log10 Pr + c)),
+    # c = -0.4 - 0.67 log10 Fc, n = 0.75 - 1.27 log10 Fc.  At log10 Pr = -c, F = Fc
+    # (the center); where f = 1, log10 F = log10 Fc / 2 (the half width).
+    troe = (0.35, 800.0, 2500.0, 4000.0)
+    T = 1200.0
+    Fc = (1 - 0.35) * math.exp(-T / 800.0) + 0.35 * math.exp(-T / 2500.0) + math.exp(-4000.0 / T)
+    L = math.log10(Fc)
+    cc = -0.4 - 0.67 * L
+    nn = 0.75 - 1.27 * L
+    F, Pr, _ = _troe_setup(tmp_path, troe, 10 ** (-cc), T=T, name="troe_c")
+    assert F == pytest.approx(Fc, rel=1e-12)
+    F, Pr, _ = _troe_setup(tmp_path, troe, 10 ** (nn / 1.14 - cc), T=T, name="troe_w")
+    assert math.log10(F) == pytest.approx(L / 2, rel=1e-11)
+    # both limits: f -> -1/0.14, so log10 F -> log10 Fc / (1 + 1/0.14^2); the
+    # approach is slow (f = -7.0 at Pr = 1e-280), so only the trend is pinned
+    lim = L / (1 + 1 / 0.14 ** 2)
+    for Pr_t in (1e-280, 1e280):
+        F, Pr, _ = _troe_setup(tmp_path, troe, Pr_t, T=T, name="troe_l")
+        assert math.log10(F) == pytest.approx(lim, rel=8e-2)
+
+
+# ---------------------------------------------------------------------------
+# conservation and consistency of the source terms
+
+def _tiny_states(m, n=6, seed=0, form="conp"):
+    st = synth.make_states(m, n, seed)
+    return st, synth.pack_state(st, form, "C")
+
+
+def _rop_abs_scale(o, m, comps):
+    """sum_i |nu_ki q_i| per species (magnitude of what enters wdot_k)."""
+    nu = np.zeros((m.n_species, m.n_reactions))
+    for i, r in enumerate(m.reactions):
+        for s, v in r.reac:
+            nu[s, i] -= v
+        for s, v in r.prod:
+            nu[s, i] += v
+    return np.abs(nu) @ (np.abs(comps["Rf"]) + np.abs(comps["Rr"])) * np.abs(comps["c"]).max(), nu
+
+
+@pytest.mark.parametrize("seed", TINY_SEEDS)
+def test_element_and_mass_conservation(seed, mech_dir):
+    m, path = tiny_file(seed, mech_dir, bath_reactions=1, bath_efficiency=True)
+    o = oracle.Oracle(path)
+    st, (x, p) = _tiny_states(m)
+    for s in range(x.shape[0]):
+        c = o.components(x[s], p[s])
+        mag = np.abs(c["c"]) @ np.zeros(0) if False else None
+        nu = np.zeros((m.n_species, m.n_reactions))
+        for i, r in enumerate(m.reactions):
+            for sp, v in r.reac:
+                nu[sp, i] -= v
+            for sp, v in r.prod:
+                nu[sp, i] += v
+        absw = np.abs(nu) @ np.abs(c["q"])
+        for e in range(4):
+            tot = m.comp[:, e] @ c["wdot"]
+            assert abs(tot) <= 1e-12 * (m.comp[:, e] @ absw) + 1e-300
+        assert abs(m.W @ c["wdot"]) <= 1e-12 * (m.W @ absw)
+        del mag
+
+
+@pytest.mark.parametrize("form", ["conp", "conv"])
+@pytest.mark.parametrize("seed", TINY_SEEDS[:3])
+def test_energy_conservation(form, seed, mech_dir):
+    # Adiabatic: CONP conserves sum n_k H_k, CONV conserves sum n_k U_k:
+    #   sum_k e_k dn_k/dt + (sum_k n_k chat_k) dT/dt = 0, all species (bath included).
+    m, path = tiny_file(seed, mech_dir, bath_reactions=1)
+    o = oracle.Oracle(path)
+    st, (x, p) = _tiny_states(m, form=form)
+    for s in range(x.shape[0]):
+        c = o.components(x[s], p[s], form)
+        T = x[s, 0]
+        V = x[s, 1] if form == "conp" else p[s]
+        n = c["C"] * V
+        th = np.array([o.thermo(k, T) for k in range(m.n_species)])
+        H = R * T * th[:, 1]
+        Cp = R * th[:, 0]
+        e, ch = (H, Cp) if form == "conp" else (H - R * T, Cp - R)
+        dndt = V * c["wdot"]
+        lhs = e @ dndt + (n @ ch) * c["Tdot"]
+        nu = np.zeros((m.n_species, m.n_reactions))
+        for i, r in enumerate(m.reactions):
+            for sp, v in r.reac:
+                nu[sp, i] -= v
+            for sp, v in r.prod:
+                nu[sp, i] += v
+        mag = np.abs(e) @ (V * np.abs(nu) @ (np.abs(c["c"]) * (np.abs(c["Rf"]) + np.abs(c["Rr"]))))
+        assert abs(lhs) <= 1e-12 * mag
+
+
+@pytest.mark.parametrize("form", ["conp", "conv"])
+@pytest.mark.parametrize("seed", TINY_SEEDS[:3])
+def test_ideal_gas_consistency(form, seed, mech_dir):
+    # d(PV)/dt = R d(nT)/dt with dn/dt summed over every species from the
+    # reactions (bath gas included), checked against dV/dt (CONP) or dP/dt (CONV).
+    m, path = tiny_file(seed, mech_dir, bath_reactions=1)
+    o = oracle.Oracle(path)
+    st, (x, p) = _tiny_states(m, form=form)
+    f = o.source(x, p, form)
+    for s in range(x.shape[0]):
+        c = o.components(x[s], p[s], form)
+        T = x[s, 0]
+        V = x[s, 1] if form == "conp" else p[s]
+        P = p[s] if form == "conp" else x[s, 1]
+        n = c["C"].sum() * V
+        dndt = V * c["wdot"].sum()
+        rhs = R * T * dndt + n * R * c["Tdot"]
+        lhs = P * f[s, 1] if form == "conp" else V * f[s, 1]
+        mag = R * T * V * np.abs(c["q"]).sum() * 10 + abs(n * R * c["Tdot"]) + abs(lhs)
+        assert abs(lhs - rhs) <= 1e-11 * mag
+        assert f[s, 0] == c["Tdot"]
+
+
+def test_conp_and_conv_agree_on_rates(mech_dir):
+    m, path = workload_file("ns13", mech_dir)
+    o = oracle.Oracle(path)
+    st = synth.make_states(m, 8, 77)
+    xp, pp = synth.pack_state(st, "conp", "C")
+    xv, pv = synth.pack_state(st, "conv", "C")
+    for s in range(8):
+        a = o.components(xp[s], pp[s], "conp")
+        b = o.components(xv[s], pv[s], "conv")
+        np.testing.assert_allclose(a["q"], b["q"], rtol=1e-13, atol=0)
+        np.testing.assert_allclose(a["wdot"], b["wdot"], rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("seed", TINY_SEEDS)
+def test_detailed_balance_equilibrium(seed, mech_dir, tmp_path):
+    # ln([C]_k R T / P_ref) = -g_k + sum_E lambda_E e_kE makes every
+    # element-balanced reversible reaction sit at equilibrium: q_i = 0, so
+    # wdot = 0 and dT/dt = 0.
+    m, _ = tiny_file(seed, mech_dir)
+    for r in m.reactions:
+        r.rev = True
+    o = write(m, tmp_path, f"eq{seed}")
+    rng = np.random.default_rng(seed)
+    for T in (800.0, 1500.0, 2100.0):
+        g = np.array([o.thermo(k, T)[1] - o.thermo(k, T)[2] for k in range(m.n_species)])
+        lam = rng.uniform(-2, 2, size=4)
+        # put the bath gas near the top of the mixture
+        lam[3] = (g[-1] + math.log(0.5)) / 2.0
+        C = PREF / (R * T) * np.exp(-g + m.comp @ lam)
+        V = 1.0
+        P = C.sum() * R * T
+        x = state_vec(T, V, C[:-1] * V)
+        c = o.components(x, P)
+        assert np.all(np.abs(c["q"]) <= 1e-10 * np.abs(c["c"]) * np.abs(c["Rf"]) + 1e-300)
+        f, sc = o.source(x[None], np.array([P]), "conp", scale=True)
+        assert np.all(np.abs(f) <= 1e-9 * sc + 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# analytical Jacobian
+
+def _check_cs(o, x, p, form, tol=1e-12):
+    J, Js = o.jacobian(x, p, form, scale=True)
+    Jc = o.jacobian_cs(x, p, form)
+    err = np.abs(J - Jc)
+    assert np.all(err <= tol * Js + 1e-300), float(np.max(err / (Js + 1e-300)))
+    return J, Js, Jc
+
+
+@pytest.mark.parametrize("form", ["conp", "conv"])
+@pytest.mark.parametrize("seed", TINY_SEEDS)
+@pytest.mark.parametrize("bath", [False, True])
+def test_jacobian_matches_complex_step_tiny(form, seed, bath, mech_dir):
+    kw = dict(bath_reactions=1, bath_efficiency=True) if bath else {}
+    m, path = tiny_file(seed, mech_dir, **kw)
+    o = oracle.Oracle(path)
+    st, (x, p) = _tiny_states(m, n=5, seed=seed, form=form)
+    J, Js, Jc = _check_cs(o, x, p, form)
+    # pattern soundness: every derivative that is not identically zero is in the pattern
+    P = o.pattern()
+    assert not np.any((Jc != 0) & ~P[None])
+    assert not np.any((J != 0) & ~P[None])
+
+
+@pytest.mark.parametrize("form", ["conp", "conv"])
+@pytest.mark.parametrize("name,n", [("ns13", 16), ("ns53", 2)])
+def test_jacobian_matches_complex_step_workloads(form, name, n, mech_dir):
+    m, path = workload_file(name, mech_dir)
+    o = oracle.Oracle(path)
+    w = synth.WORKLOADS[name]
+    st = synth.make_states(m, n, w.state_seed, T_range=w.T_range, P_range_atm=w.P_range_atm)
+    x, p = synth.pack_state(st, form, "C")
+    J, Js, Jc = _check_cs(o, x, p, form)
+    assert not np.any((Jc != 0) & ~o.pattern()[None])
+
+
+@pytest.mark.parametrize("form", ["conp", "conv"])
+def test_jacobian_matches_central_differences(form, mech_dir):
+    m, path = tiny_file(TINY_SEEDS[0], mech_dir, bath_reactions=1)
+    o = oracle.Oracle(path)
+    st, (x, p) = _tiny_states(m, n=4, seed=3, form=form)
+    # keep the bath gas well away from zero so that the +-h steps stay physical
+    J, Js = o.jacobian(x, p, form, scale=True)
+    for rel in (1e-6,):
+        Jf = o.jacobian_fd(x, p, form, rel=rel)
+        f, fs = o.source(x, p, form, scale=True)
+        h = rel * np.maximum(np.abs(x), 1e-300)
+        # truncation O(h^2) plus rounding eps*|f|/h of the differences
+        tol = 1e-6 * Js + 4e-16 * fs[:, :, None] / h[:, None, :]
+        assert np.all(np.abs(J - Jf) <= tol)
+
+
+def test_pattern_of_hand_mechanism(tmp_path):
+    # species A, B, C, D, E, bath N2 (index 5).  Reactions:
+    #   0: A + B => C          (irreversible: C is not a column of rows A, B, C)
+    #   1: C + D <=> E         (reversible, third body, efficiency on A)
+    sp = [("A", (0, 1, 0, 0), 2.5, 1e3, 20.0), ("B", (0, 0, 1, 0), 2.5, 1e3, 20.0),
+          ("C", (0, 1, 1, 0), 3.5, 1e3, 20.0), ("D", (1, 0, 0, 0), 2.5, 1e3, 20.0),
+          ("E", (1, 1, 1, 0), 4.0, 1e3, 20.0), ("N2", (0, 0, 0, 2), 3.5, 0.0, 20.0)]
+    rx = [synth.Reaction("ELEM", False, [(0, 1), (1, 1)], [(2, 1)], 20.0, 0.0, 0.0),
+          synth.Reaction("THREEBODY", True, [(2, 1), (3, 1)], [(4, 1)], 20.0, 0.0, 0.0,
+                         eff=[(0, 3.0)])]
+    o = write(micro(sp, rx), tmp_path, "pat")
+    N = 7
+    E = np.zeros((N, N), dtype=bool)
+    E[0:2, :] = True
+    E[:, 0:2] = True
+    E[np.arange(N), np.arange(N)] = True
+    idx = {"A": 2, "B": 3, "C": 4, "D": 5, "E": 6}
+    for r in "ABC":
+        for c in "AB":
+            E[idx[r], idx[c]] = True
+    for r in "CDE":
+        for c in "CDEA":
+            E[idx[r], idx[c]] = True
+    np.testing.assert_array_equal(o.pattern(), E)
+    # the bath gas as a reactant makes the rows of that reaction's species dense
+    rx2 = rx + [synth.Reaction("ELEM", True, [(5, 1)], [(3, 1), (3, 1)], 20.0, 0.0, 0.0)]
+    o2 = write(micro(sp, rx2), tmp_path, "pat2")
+    E2 = E.copy()
+    E2[idx["D"], 2:] = True
+    np.testing.assert_array_equal(o2.pattern(), E2)
+
+
+def test_scale_bounds_value(mech_dir):
+    m, path = workload_file("ns13", mech_dir)
+    o = oracle.Oracle(path)
+    st = synth.make_states(m, 8, 5)
+    x, p = synth.pack_state(st, "conp", "C")
+    f, fs = o.source(x, p, "conp", scale=True)
+    assert np.all(fs >= np.abs(f) * (1 - 1e-15))
+    J, Js = o.jacobian(x, p, "conp", scale=True)
+    assert np.all(Js >= np.abs(J) * (1 - 1e-15))
+    # no cancellation -> scale equals the magnitude: one irreversible reaction
+    sp = SPECIES_ABC
+    rx = [synth.Reaction("ELEM", False, [(0, 1), (1, 1)], [(2, 1)], 25.0, 0.3, 1000.0)]
+    import tempfile, os
+    with tempfile.TemporaryDirectory() as d:
+        pth = os.path.join(d, "irr.pjm")
+        synth.write_mechanism(micro(sp, rx), pth)
+        o2 = oracle.Oracle(pth)
+        xx, P = _abc_state()
+        f2, s2 = o2.source(xx[None], np.array([P]), "conp", scale=True)
+        np.testing.assert_allclose(s2[0, 2:], np.abs(f2[0, 2:]), rtol=1e-15)
+
+
+def test_closure_uses_exactly_rounded_sum(tmp_path):
+    # n_Ns = fl(fl(P V) / fl(R T)) - RN(sum n_k): independent of summation order
+    m, o = _abc(tmp_path)
+    T, V, P = 1234.5, 0.7, 4.2 * ATM
+    moles = [0.1, 1e-17, -0.1 + 3e-18]
+    x = state_vec(T, V, moles)
+    c = o.components(x, P)
+    exact = math.fsum(moles)
+    nb = (P * V) / (R * T) - exact
+    assert c["C"][3] == nb / V
