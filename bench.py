@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark: states/s for thermochemical source terms + sparse Jacobian (FP64).
+
+One step is one fused pass of the whole hot path (bath-gas closure, species
+thermodynamics, rate constants, pressure modification, equilibrium constants,
+rates of progress, production rates, source terms, analytical Jacobian on the
+CSR pattern) over one batch of synthetic states already resident in HBM.  The
+default workload is the 111-species / 784-reaction synthetic mechanism at
+262,144 states, constant pressure, layout F.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import tempfile
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "states/sec for source terms and sparse Jacobian (FP64, % of roofline)"
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ns111")
+    ap.add_argument("--n-states", type=int, default=0, help="override the workload's state count")
+    ap.add_argument("--form", default="conp", choices=["conp", "conv"])
+    ap.add_argument("--layout", default="F", choices=["F", "C"])
+    ap.add_argument("--cpu-sample", type=int, default=2048, help="states timed on the CPU oracle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); states are independent, "
+              "so more GPUs would each run this same benchmark on their own share.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1809_01029_amd import api, synth
+
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    n = args.n_states or w.n_states
+    tmp = tempfile.mkdtemp(prefix="pjbench_")
+    path = os.path.join(tmp, f"{args.workload}.pjm")
+    t0 = time.time()
+    m = synth.workload_mechanism(args.workload)
+    synth.write_mechanism(m, path)
+    st = synth.make_states(m, n, w.state_seed, T_range=w.T_range, P_range_atm=w.P_range_atm)
+    x, p = synth.pack_state(st, args.form, args.layout)
+    log(f"inputs: {args.workload} Ns={m.n_species} Nr={m.n_reactions} n={n} ({time.time() - t0:.1f}s)")
+
+    mech = api.load_mechanism(path)
+    N, nnz = mech.N, mech.nnz
+    xs = torch.from_numpy(x).cuda()
+    ps = torch.from_numpy(p).cuda()
+    dstate = torch.empty_like(xs)
+    jshape = (nnz, n) if args.layout == "F" else (n, nnz)
+    jac = torch.empty(jshape, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        api.eval_jacobian_sparse(mech, xs, ps, args.form, args.layout, out=jac, dstate=dstate,
+                                 stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    ms = ms_total / args.steps
+    value = n / (ms * 1e-3)
+    log(f"timed {args.steps} steps: {ms:.4f} ms/step, {value:.4e} states/s")
+
+    # algorithmic HBM bytes per state: state + parameter in, source terms and
+    # CSR values out (mechanism tables and intermediates excluded)
+    bytes_state = 8 * (N + 1) + 8 * N + 8 * nnz
+    achieved = bytes_state * n / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_state": bytes_state}
+
+    variants = {}
+    if not args.no_variants:
+        def timeit(fn, k=5):
+            fn()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(k):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / k
+        out_src = torch.empty_like(xs)
+        t = timeit(lambda: api.eval_source(mech, xs, ps, args.form, args.layout, out=out_src, stream=stream))
+        variants["source_only"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3)}
+        del out_src
+        if N * N * n * 8 < 60e9:
+            dshape = (N, N, n) if args.layout == "F" else (n, N, N)
+            dj = torch.empty(dshape, dtype=torch.float64, device="cuda")
+            t = timeit(lambda: api.eval_jacobian_dense(mech, xs, ps, args.form, args.layout, out=dj,
+                                                       dstate=dstate, stream=stream), k=3)
+            variants["dense_jacobian"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3),
+                                          "hbm_GBps": (8 * (2 * N + 1) + 8 * N * N) * n / (t * 1e-3) / 1e9}
+            del dj
+        other = "conv" if args.form == "conp" else "conp"
+        x2, p2 = synth.pack_state(st, other, args.layout)
+        xs2, ps2 = torch.from_numpy(x2).cuda(), torch.from_numpy(p2).cuda()
+        t = timeit(lambda: api.eval_jacobian_sparse(mech, xs2, ps2, other, args.layout, out=jac,
+                                                    dstate=dstate, stream=stream))
+        variants[f"{other}_sparse"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3)}
+        del xs2, ps2
+        ol = "C" if args.layout == "F" else "F"
+        x3, p3 = synth.pack_state(st, args.form, ol)
+        xs3, ps3 = torch.from_numpy(x3).cuda(), torch.from_numpy(p3).cuda()
+        jac3 = torch.empty((nnz, n) if ol == "F" else (n, nnz), dtype=torch.float64, device="cuda")
+        d3 = torch.empty_like(xs3)
+        t = timeit(lambda: api.eval_jacobian_sparse(mech, xs3, ps3, args.form, ol, out=jac3, dstate=d3,
+                                                    stream=stream))
+        variants[f"layout_{ol}_sparse"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3)}
+        del xs3, ps3, jac3, d3
+        log(f"variants: {json.dumps(variants)}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        k = min(args.cpu_sample, n)
+        xc, pc = synth.pack_state(st, args.form, "C")
+        xc, pc = np.ascontiguousarray(xc[:k]), pc[:k]
+        o = oracle.Oracle(path)
+        t0 = time.perf_counter()
+        o.source(xc, pc, args.form)
+        o.jacobian(xc, pc, args.form)
+        dt = time.perf_counter() - t0
+        cpu = {"value": k / dt, "unit": "states/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {k} of the {n} {args.workload} states: source terms + analytical "
+                         f"Jacobian (dense, holding the CSR values), serial FP64 oracle, {dt:.1f} s"}
+        log(f"cpu oracle: {cpu['value']:.2f} states/s on {k} states")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "states/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: synthetic {m.n_species} species / {m.n_reactions} "
+                               f"reactions, {n} states, {args.form.upper()}, layout {args.layout}, "
+                               f"fused source terms + sparse CSR Jacobian",
+                   "n_species": m.n_species, "n_reactions": m.n_reactions, "n_states": n, "nnz": nnz,
+                   "form": args.form, "layout": args.layout,
+                   "waves_per_state": mech.waves_per_state(True)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * pjac.h - C-ABI of the MI355X (gfx950) library that evaluates thermochemical
+ * source terms and the analytical sparse / dense chemical-kinetic Jacobian for
+ * very many independent thermochemical states, after Curtis, Niemeyer & Sung,
+ * "Using SIMD and SIMT vectorization to evaluate sparse chemical kinetic
+ * Jacobian matrices and thermochemical source terms" (pyJac v2,
+ * arXiv:1809.01029).
+ *
+ * Problem statement (paper Sec. 2.2).  For a mechanism with Ns species (the
+ * last one the bath gas) the state vector has N = Ns + 1 entries:
+ *     constant pressure (CONP): Phi = (T, V, n_1 .. n_{Ns-1}),  parameter P
+ *     constant volume   (CONV): Phi = (T, P, n_1 .. n_{Ns-1}),  parameter V
+ * with T in K, V in m^3, P in Pa and n_k in kmol.  The bath gas moles follow
+ * from the ideal-gas law, n_Ns = P V / (R T) - sum_{k<Ns} n_k, where the sum
+ * is the exactly rounded sum of the n_k.  The source terms are
+ *     dT/dt  = -sum_k e_k wdot_k / sum_k [C]_k chat_k     (e = H or U, chat = Cp or Cv)
+ *     dn_k/dt = V wdot_k,   wdot_k = sum_i nu_ki c_i R_i   (Sec. 2.2)
+ *     CONP: dV/dt = V/T dT/dt + V R T / P * Omega
+ *     CONV: dP/dt = P/T dT/dt + R T * Omega,   Omega = sum_{k<Ns} (1 - W_k/W_Ns) wdot_k
+ * and the Jacobian is J[i][j] = d(dPhi_i/dt)/dPhi_j (Sec. 2.2), stored either
+ * on a fixed per-mechanism CSR pattern (Sec. 3.4) or dense.
+ * Units: SI with kmol, R = 8314.462618 J/(kmol K), reference pressure 101325 Pa.
+ *
+ * Layouts (Sec. 2.1, data ordering):
+ *   PJ_LAYOUT_C  state-major: state[s*N + i], dstate[s*N + i],
+ *                CSR values jac[s*nnz + e], dense jac[s*N*N + i*N + j]
+ *   PJ_LAYOUT_F  variable-major (each variable of all states contiguous):
+ *                state[i*n + s], dstate[i*n + s], CSR values jac[e*n + s],
+ *                dense jac[s + n*(i + N*j)]  (Fortran order of (state, row, col))
+ * param[s] is one value per state in both layouts.
+ *
+ * Conventions.
+ *   - Every d_* pointer is device memory owned by the caller; the library never
+ *     frees it.  The mechanism handle and the pattern arrays it hands out are
+ *     owned by the library until pj_mech_free.
+ *   - Evaluation calls are asynchronous on the given HIP stream and never
+ *     synchronise the host.  n_states == 0 is a no-op returning PJ_OK.
+ *   - Errors are status codes; pj_last_error() gives a thread-local message.
+ *     NULL pointers (with n_states > 0), n_states < 0, bad enums, a NULL
+ *     handle, a handle that was not uploaded, or a current HIP device other
+ *     than the one the mechanism was uploaded to give PJ_E_INVALID; a failed
+ *     launch gives PJ_E_DEVICE.
+ *   - Non-physical inputs (T <= 0, a negative bath gas) are not checked on the
+ *     device; NaN and inf propagate to the outputs.
+ */
+#ifndef PJAC_H
+#define PJAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pj_mech pj_mech; /* opaque, library-owned */
+
+/* HIP stream handle (hipStream_t); NULL is the default stream. */
+typedef void* pj_stream;
+
+typedef enum { PJ_CONP = 0, PJ_CONV = 1 } pj_form;
+typedef enum { PJ_LAYOUT_F = 0, PJ_LAYOUT_C = 1 } pj_layout;
+
+typedef enum {
+    PJ_OK = 0,
+    PJ_E_INVALID = 1,     /* bad argument */
+    PJ_E_PARSE = 2,       /* malformed mechanism description */
+    PJ_E_UNBALANCED = 3,  /* a reaction does not conserve elements */
+    PJ_E_DEVICE = 4,      /* HIP error (allocation, copy, launch) */
+    PJ_E_NOMEM = 5,       /* host allocation failed */
+    PJ_E_UNSUPPORTED = 6  /* mechanism outside what the kernels handle */
+} pj_status;
+
+/*
+ * Load a mechanism description (the text format written by the package's
+ * synthetic generator: species with NASA 7-coefficient thermodynamics,
+ * reactions of type elementary, third-body, Lindemann or Troe falloff;
+ * Sec. 2.2 "all modern reaction types", restricted to these four), check that
+ * every reaction conserves elements, derive the device tables and the CSR
+ * pattern of the Jacobian (Sec. 3.4), and upload them to the current HIP
+ * device.  Synchronous.  On success *out receives a handle; on failure *out is
+ * NULL and the status says why.
+ * Limits (PJ_E_UNSUPPORTED beyond them): at most 3 distinct species per
+ * reaction side, coefficients 1..3, at most 65534 Jacobian non-zeros, and the
+ * per-state working set must fit the device's LDS per workgroup.
+ */
+pj_status pj_mech_load(const char* desc_path, pj_mech** out);
+
+/*
+ * The two halves of pj_mech_load.  pj_mech_parse parses, validates and
+ * derives the CSR pattern on the host only (no device needed): the handle can
+ * be queried (sizes, pattern) and freed, but not evaluated.  pj_mech_upload
+ * derives the device tables and uploads them to the current HIP device
+ * (synchronous); PJ_E_INVALID if the mechanism was already uploaded.
+ */
+pj_status pj_mech_parse(const char* desc_path, pj_mech** out);
+pj_status pj_mech_upload(pj_mech* mech);
+
+/* Release a mechanism and its device tables.  NULL is accepted. */
+void pj_mech_free(pj_mech* mech);
+
+int pj_mech_n_species(const pj_mech* mech);   /* Ns, or -1 for NULL */
+int pj_mech_n_reactions(const pj_mech* mech); /* Nr, or -1 for NULL */
+int pj_mech_state_size(const pj_mech* mech);  /* N = Ns + 1, or -1 for NULL */
+
+/*
+ * The fixed CSR pattern of the Jacobian (Sec. 3.4): row_ptr has N+1 entries,
+ * col_idx has nnz entries with ascending columns in each row.  Rows and
+ * columns 0 (T) and 1 (V or P) are dense; species row k holds column j when a
+ * reaction with a non-zero net coefficient of k has a rate of progress that
+ * depends on [C]_j (j a reactant, a product of a reversible reaction, or a
+ * third body whose efficiency differs from the bath gas's); a rate that
+ * depends on the bath gas makes the row dense; the diagonal is always held.
+ * The arrays are host memory owned by the mechanism.
+ */
+pj_status pj_mech_jac_pattern(const pj_mech* mech, int64_t* nnz, const int32_t** row_ptr,
+                              const int32_t** col_idx);
+
+/*
+ * Source terms dPhi/dt (Sec. 2.2) for n_states states.
+ * d_state: N*n doubles in `layout`; d_param: n doubles (P for CONP, V for
+ * CONV); d_dstate: N*n doubles written in the same layout as d_state.
+ */
+pj_status pj_eval_source(const pj_mech* mech, pj_form form, pj_layout layout, int64_t n_states,
+                         const double* d_state, const double* d_param, double* d_dstate,
+                         pj_stream stream);
+
+/*
+ * Analytical Jacobian on the CSR pattern (Sec. 3.4) plus, when
+ * d_dstate_or_null is not NULL, the source terms of the same states (one
+ * fused pass).  d_jac_vals: nnz*n doubles, [e*n + s] (F) or [s*nnz + e] (C).
+ */
+pj_status pj_eval_jacobian_sparse(const pj_mech* mech, pj_form form, pj_layout layout,
+                                  int64_t n_states, const double* d_state, const double* d_param,
+                                  double* d_jac_vals, double* d_dstate_or_null, pj_stream stream);
+
+/*
+ * Analytical Jacobian as a dense N x N matrix per state (entries outside the
+ * pattern are written as 0), plus optional fused source terms.
+ * d_jac: N*N*n doubles, [s + n*(i + N*j)] (F) or [s*N*N + i*N + j] (C).
+ */
+pj_status pj_eval_jacobian_dense(const pj_mech* mech, pj_form form, pj_layout layout,
+                                 int64_t n_states, const double* d_state, const double* d_param,
+                                 double* d_jac, double* d_dstate_or_null, pj_stream stream);
+
+/*
+ * Launch shape: waves_per_state workgroup waves cooperate on one state
+ * (1, 2 or 4; 0 restores the automatic choice).  With one wave per
+ * state every accumulation happens in a fixed order, so results are bitwise
+ * reproducible; with more, the order of LDS atomic additions across waves may
+ * vary between runs (results then agree to rounding).
+ */
+pj_status pj_mech_set_waves_per_state(pj_mech* mech, int waves_per_state);
+int pj_mech_waves_per_state(const pj_mech* mech, int for_jacobian);
+
+/* Bytes of LDS one state needs for source terms (0) or the Jacobian (1). */
+int64_t pj_mech_lds_bytes(const pj_mech* mech, int for_jacobian);
+
+/* Thread-local description of the last error ("" if none). */
+const char* pj_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PJAC_H */

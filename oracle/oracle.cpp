@@ -508,13 +508,17 @@ void jacobian(const Mech& m, int form, const S* x, S param, S* J) {
         set(bath, 2 + j, -S(1.0) / V);
     }
 
-    // dq_i/dPhi_j = sum_k dq_i/d[C]_k d[C]_k/dPhi_j (+ dq_i/dT at fixed [C] for j = T)
+    // dq_i/dPhi_j = sum_k dq_i/d[C]_k d[C]_k/dPhi_j (+ dq_i/dT at fixed [C] for j = T),
+    // the sum taken over the k whose sensitivity is not identically zero
+    std::vector<std::vector<int>> colnz(N);
+    for (int j = 0; j < N; ++j)
+        for (int k = 0; k < ns; ++k)
+            if (nz[(size_t)k * N + j]) colnz[j].push_back(k);
     std::vector<S> dq((size_t)nr * N, S(0.0));
     for (int i = 0; i < nr; ++i)
         for (int j = 0; j < N; ++j) {
             S acc = (j == 0) ? ev.rx[i].dq_dT : S(0.0);
-            for (int k = 0; k < ns; ++k)
-                if (nz[(size_t)k * N + j]) acc = acc + ev.rx[i].dq_dC[k] * dc(k, j);
+            for (int k : colnz[j]) acc = acc + ev.rx[i].dq_dC[k] * dc(k, j);
             dq[(size_t)i * N + j] = acc;
         }
 

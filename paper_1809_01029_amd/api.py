@@ -1,0 +1,251 @@
+"""Python binding of the C-ABI in ``include/pjac.h`` (argument marshalling only).
+
+Every evaluation runs in the HIP kernels of ``libpjac.so``; this module only
+checks tensor shapes, dtypes and devices, allocates outputs with torch when
+the caller does not pass them, and hands raw device pointers and the current
+HIP stream to the library.  If the library has not been built the import of
+this module fails: there is no fallback.
+
+Layouts (paper Sec. 2.1): ``"F"`` keeps each variable of all states
+contiguous, ``"C"`` keeps each state contiguous.
+
+=========================  =====================  ======================
+array                      layout "F" shape       layout "C" shape
+=========================  =====================  ======================
+state, dstate              (N, n)                 (n, N)
+param                      (n,)                   (n,)
+sparse Jacobian values     (nnz, n)               (n, nnz)
+dense Jacobian             (N, N, n) as [j, i, s] (n, N, N) as [s, i, j]
+=========================  =====================  ======================
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpjac.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1809_01029_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_lib.pj_mech_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(_P)]
+_lib.pj_mech_load.restype = ctypes.c_int
+_lib.pj_mech_parse.argtypes = [ctypes.c_char_p, ctypes.POINTER(_P)]
+_lib.pj_mech_parse.restype = ctypes.c_int
+_lib.pj_mech_upload.argtypes = [_P]
+_lib.pj_mech_upload.restype = ctypes.c_int
+_lib.pj_mech_free.argtypes = [_P]
+_lib.pj_mech_free.restype = None
+for _f in ("pj_mech_n_species", "pj_mech_n_reactions", "pj_mech_state_size"):
+    getattr(_lib, _f).argtypes = [_P]
+    getattr(_lib, _f).restype = ctypes.c_int
+_lib.pj_mech_jac_pattern.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
+                                     ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))]
+_lib.pj_mech_jac_pattern.restype = ctypes.c_int
+_lib.pj_eval_source.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P]
+_lib.pj_eval_source.restype = ctypes.c_int
+_lib.pj_eval_jacobian_sparse.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P, _P]
+_lib.pj_eval_jacobian_sparse.restype = ctypes.c_int
+_lib.pj_eval_jacobian_dense.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P, _P]
+_lib.pj_eval_jacobian_dense.restype = ctypes.c_int
+_lib.pj_mech_set_waves_per_state.argtypes = [_P, ctypes.c_int]
+_lib.pj_mech_set_waves_per_state.restype = ctypes.c_int
+_lib.pj_mech_waves_per_state.argtypes = [_P, ctypes.c_int]
+_lib.pj_mech_waves_per_state.restype = ctypes.c_int
+_lib.pj_mech_lds_bytes.argtypes = [_P, ctypes.c_int]
+_lib.pj_mech_lds_bytes.restype = _I64
+_lib.pj_last_error.argtypes = []
+_lib.pj_last_error.restype = ctypes.c_char_p
+
+CONP, CONV = 0, 1
+LAYOUT_F, LAYOUT_C = 0, 1
+FORMS = {"conp": CONP, "conv": CONV}
+LAYOUTS = {"F": LAYOUT_F, "C": LAYOUT_C}
+STATUS = {0: "PJ_OK", 1: "PJ_E_INVALID", 2: "PJ_E_PARSE", 3: "PJ_E_UNBALANCED", 4: "PJ_E_DEVICE",
+          5: "PJ_E_NOMEM", 6: "PJ_E_UNSUPPORTED"}
+
+
+class PjError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.pj_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise PjError(st, where)
+
+
+def library() -> ctypes.CDLL:
+    return _lib
+
+
+class Mechanism:
+    """A mechanism description loaded by the library (pj_mech_load), or only
+    parsed on the host (``upload=False``, pj_mech_parse)."""
+
+    def __init__(self, path: str, upload: bool = True):
+        h = _P()
+        fn = _lib.pj_mech_load if upload else _lib.pj_mech_parse
+        _check(fn(os.fsencode(path), ctypes.byref(h)), "pj_mech_load" if upload else "pj_mech_parse")
+        self._h = h
+        self.path = path
+        self.n_species = _lib.pj_mech_n_species(h)
+        self.n_reactions = _lib.pj_mech_n_reactions(h)
+        self.N = _lib.pj_mech_state_size(h)
+        nnz = _I64()
+        rp = ctypes.POINTER(ctypes.c_int32)()
+        ci = ctypes.POINTER(ctypes.c_int32)()
+        _check(_lib.pj_mech_jac_pattern(h, ctypes.byref(nnz), ctypes.byref(rp), ctypes.byref(ci)),
+               "pj_mech_jac_pattern")
+        self.nnz = int(nnz.value)
+        self.row_ptr = np.ctypeslib.as_array(rp, shape=(self.N + 1,)).astype(np.int64)
+        self.col_idx = np.ctypeslib.as_array(ci, shape=(self.nnz,)).astype(np.int64)
+
+    def upload(self):
+        _check(_lib.pj_mech_upload(self._h), "pj_mech_upload")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def pattern_dense(self) -> np.ndarray:
+        P = np.zeros((self.N, self.N), dtype=bool)
+        rows = np.repeat(np.arange(self.N), np.diff(self.row_ptr))
+        P[rows, self.col_idx] = True
+        return P
+
+    def set_waves_per_state(self, w: int):
+        _check(_lib.pj_mech_set_waves_per_state(self._h, int(w)), "pj_mech_set_waves_per_state")
+
+    def waves_per_state(self, jacobian: bool = False) -> int:
+        return _lib.pj_mech_waves_per_state(self._h, 1 if jacobian else 0)
+
+    def lds_bytes(self, jacobian: bool = False) -> int:
+        return int(_lib.pj_mech_lds_bytes(self._h, 1 if jacobian else 0))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.pj_mech_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def load_mechanism(path: str) -> Mechanism:
+    return Mechanism(path, upload=True)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _need(t: torch.Tensor, shape: Tuple[int, ...], name: str, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if t.device.type != "cuda" or (device is not None and t.device != device):
+        raise ValueError(f"{name} must be on the mechanism's CUDA/HIP device")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _n_states(mech: Mechanism, state: torch.Tensor, layout: str) -> int:
+    if state.dim() != 2:
+        raise ValueError("state must be 2-D")
+    return int(state.shape[1] if layout == "F" else state.shape[0])
+
+
+def _state_shape(mech, n, layout):
+    return (mech.N, n) if layout == "F" else (n, mech.N)
+
+
+def eval_source(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, form: str = "conp",
+                layout: str = "F", out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """pj_eval_source: dPhi/dt for every state."""
+    n = _n_states(mech, state, layout)
+    _need(state, _state_shape(mech, n, layout), "state", None)
+    _need(param, (n,), "param", state.device)
+    if out is None:
+        out = torch.empty_like(state)
+    _need(out, _state_shape(mech, n, layout), "out", state.device)
+    _check(_lib.pj_eval_source(mech.handle, FORMS[form], LAYOUTS[layout], n, _ptr(state), _ptr(param),
+                               _ptr(out), _stream(stream)), "pj_eval_source")
+    return out
+
+
+def eval_jacobian_sparse(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, form: str = "conp",
+                         layout: str = "F", out: Optional[torch.Tensor] = None,
+                         dstate: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """pj_eval_jacobian_sparse: CSR values on the mechanism's pattern
+    (``mech.row_ptr``, ``mech.col_idx``); optionally fused source terms into
+    ``dstate``."""
+    n = _n_states(mech, state, layout)
+    _need(state, _state_shape(mech, n, layout), "state", None)
+    _need(param, (n,), "param", state.device)
+    shape = (mech.nnz, n) if layout == "F" else (n, mech.nnz)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=state.device)
+    _need(out, shape, "out", state.device)
+    if dstate is not None:
+        _need(dstate, _state_shape(mech, n, layout), "dstate", state.device)
+    _check(_lib.pj_eval_jacobian_sparse(mech.handle, FORMS[form], LAYOUTS[layout], n, _ptr(state),
+                                        _ptr(param), _ptr(out), _ptr(dstate), _stream(stream)),
+           "pj_eval_jacobian_sparse")
+    return out
+
+
+def eval_jacobian_dense(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, form: str = "conp",
+                        layout: str = "F", out: Optional[torch.Tensor] = None,
+                        dstate: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """pj_eval_jacobian_dense: the full N x N Jacobian of every state
+    (layout "C": [s, i, j]; layout "F": [j, i, s])."""
+    n = _n_states(mech, state, layout)
+    _need(state, _state_shape(mech, n, layout), "state", None)
+    _need(param, (n,), "param", state.device)
+    N = mech.N
+    shape = (N, N, n) if layout == "F" else (n, N, N)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=state.device)
+    _need(out, shape, "out", state.device)
+    if dstate is not None:
+        _need(dstate, _state_shape(mech, n, layout), "dstate", state.device)
+    _check(_lib.pj_eval_jacobian_dense(mech.handle, FORMS[form], LAYOUTS[layout], n, _ptr(state),
+                                       _ptr(param), _ptr(out), _ptr(dstate), _stream(stream)),
+           "pj_eval_jacobian_dense")
+    return out
+
+
+def dense_as_sij(jac: torch.Tensor, layout: str) -> torch.Tensor:
+    """View a dense Jacobian output as [state, row, col]."""
+    return jac if layout == "C" else jac.permute(2, 1, 0)
+
+
+def sparse_to_dense(mech: Mechanism, vals: np.ndarray, layout: str) -> np.ndarray:
+    """Host helper: CSR values (numpy, library layout) -> dense [s, i, j]."""
+    v = vals.T if layout == "F" else vals
+    n = v.shape[0]
+    out = np.zeros((n, mech.N, mech.N))
+    rows = np.repeat(np.arange(mech.N), np.diff(mech.row_ptr))
+    out[:, rows, mech.col_idx] = v
+    return out

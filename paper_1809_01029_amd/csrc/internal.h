@@ -1,0 +1,119 @@
+// Internal structures shared by the host mechanism compiler (mech.cpp), the
+// kernels (kernels.hip) and the C-ABI (api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pjac.h"
+
+namespace pj {
+
+constexpr double RU = 8314.462618;       // J/(kmol K)
+constexpr double PREF = 101325.0;        // Pa
+constexpr int MAXSIDE = 3;               // species per reaction side
+constexpr int NSLOT = 2 * MAXSIDE;       // reactant slots 0..2, product slots 3..5
+constexpr uint16_t NOSLOT = 0xFFFF;
+
+enum RxnKind : int { K_ELEM = 0, K_THREEBODY = 1, K_LINDEMANN = 2, K_TROE = 3 };
+
+// Bits of the per-reaction info word.
+//   bits 0..23 : coefficient of slot a (a < 6) in bits 4a..4a+3 (0 = empty slot)
+//   bits 24..25: kind (RxnKind)
+//   bit  26    : reversible
+//   bit  27    : the rate depends on the bath-gas concentration
+constexpr uint32_t INFO_REV = 1u << 26;
+constexpr uint32_t INFO_BATH = 1u << 27;
+__host__ __device__ inline int info_nu(uint32_t w, int a) { return (w >> (4 * a)) & 0xF; }
+__host__ __device__ inline int info_kind(uint32_t w) { return (w >> 24) & 0x3; }
+
+// Device tables of one mechanism.  Per-reaction arrays are indexed by the
+// reaction's position in the kernel order (sorted by kind) and padded to a
+// multiple of 64; "[a][i]" arrays are slot-major so that consecutive lanes
+// (consecutive reactions) read consecutive words.
+struct DevMech {
+    int ns, nr, nr_pad, N;
+    int nnz;            // CSR non-zeros
+    int n_dense_rows;   // species rows made dense by bath-gas dependent rates
+    int bath;           // ns - 1
+
+    // species (Ns entries, index k)
+    const double* th;   // [2 ranges][TH_N coefficients][ns]
+    const double* tmid; // [ns]
+    const double* wfac; // [ns] 1 - W_k / W_Ns (0 for the bath gas)
+
+    // reactions
+    const uint32_t* info;     // [nr_pad]
+    const uint16_t* sp;       // [6][nr_pad] species of slot a (ns = empty)
+    const double* arr;        // [3][nr_pad] lnA, b, Ea/R
+    const double* low;        // [3][nr_pad] lnA0, b0, Ea0/R (falloff)
+    const double* troe;       // [4][nr_pad] alpha, 1/T***, 1/T*, T**
+    const double* dnu;        // [nr_pad] sum of net coefficients
+    const double* domega;     // [nr_pad] sum_{k<Ns} nu_ki (1 - W_k/W_Ns)
+    const int32_t* eff_ptr;   // [nr_pad + 1]
+    const uint16_t* eff_sp;   // [n_eff]
+    const double* eff_am1;    // [n_eff] efficiency - 1
+
+    // Jacobian scatter tables (CSR slots; NOSLOT = none)
+    const uint16_t* rowbase;  // [6][nr_pad] row_ptr of the row of slot a's species
+    const uint16_t* slot;     // [36][nr_pad] slot (row of slot a, column of slot b)
+    const uint16_t* effslot;  // [n_eff][6] slot (row of slot a, column of the third body)
+    const int32_t* row_ptr;   // [N + 1]
+    const uint16_t* col_idx;  // [nnz]
+    const int32_t* dense_rows;// [n_dense_rows] species index k of bath-dense rows
+};
+
+// Thermodynamic coefficient rows per range (see mech.cpp for the layout).
+constexpr int TH_N = 18;
+
+struct Mechanism {
+    // host copy of the description
+    int ns = 0, nr = 0;
+    std::vector<double> W;
+    std::vector<int> comp;                 // [ns][4]
+    std::vector<double> tmid, alo, ahi;    // alo/ahi: [ns][7]
+    struct Rxn {
+        int kind;
+        bool rev;
+        std::vector<std::pair<int, int>> reac, prod;
+        double lnA, b, theta;
+        double lnA0 = 0, b0 = 0, theta0 = 0;
+        double alpha = 0, T3 = 1, T1 = 1, T2 = 0;
+        std::vector<std::pair<int, double>> eff;
+    };
+    std::vector<Rxn> rx;
+
+    // derived
+    std::vector<int> order;                // kernel position -> description index
+    std::vector<int32_t> row_ptr, col_idx; // CSR pattern
+    int nnz = 0;
+
+    // device
+    int device = -1;
+    void* dbuf = nullptr;
+    DevMech dm{};
+    int wps_src = 1, wps_jac = 1;          // waves per state
+    bool wps_user = false;
+    int64_t lds_src = 0, lds_jac = 0, lds_dense = 0;
+    int lds_max = 0;
+};
+
+// mech.cpp
+pj_status build_mechanism(const char* path, Mechanism& m, std::string& err);
+pj_status upload_mechanism(Mechanism& m, std::string& err);
+
+// kernels.hip
+enum Mode : int { MODE_SRC = 0, MODE_SPARSE = 1, MODE_DENSE = 2 };
+int64_t lds_bytes(const DevMech& dm, int mode);
+hipError_t launch(const DevMech& dm, int mode, int form, int layout, int64_t n, const double* state,
+                  const double* param, double* dstate, double* jac, int wps, int64_t lds,
+                  hipStream_t stream);
+
+}  // namespace pj
+
+struct pj_mech {
+    pj::Mechanism m;
+};

@@ -1,0 +1,531 @@
+// FP64 HIP kernels for gfx950: thermochemical source terms and the analytical
+// sparse / dense Jacobian (Curtis, Niemeyer & Sung, pyJac v2, Sec. 2.2 and
+// Sec. 3.4), one workgroup per state ("deep" vectorization, Sec. 2.1).
+//
+// Mapping.  A workgroup of `wps` waves evaluates one state at a time (a
+// grid-stride loop over states).  Its lanes split the species for the
+// thermodynamics and the reactions (sorted by kind, so a 64-reaction chunk
+// takes one code path) for the rates and the Jacobian sub-products.  The
+// per-state working set lives in LDS:
+//     C, G, H, CP, W   [Ns+1] each: concentrations, g = G/RT, h = H/RT,
+//                      chat/R, production rates; entry Ns is a sentinel
+//                      (C = 1, G = H = 0) that empty reaction slots point at
+//     J                [nnz]  CSR accumulator of the species rows
+//     B                [Ns]   per-row sum of the bath-gas partials
+//     TQ, SQ           [Ns+1] energy- and mole-weighted concentration partials
+// Reactions scatter into these with LDS FP64 atomics (ds_add_f64).  With one
+// wave per state the order of those additions is fixed by program order, so
+// the results are bitwise reproducible.
+//
+// Jacobian formulation.  With the third-body concentration written as
+// [M] = C_tot + sum_k (alpha_k - 1) [C]_k, C_tot = P/(R T), each reaction
+// provides Q_j = dq/d[C]_j at fixed T and C_tot, Q_M = dq/dC_tot, and
+// dq/dT at fixed concentrations.  The bath-gas closure then gives
+//     dq/dn_j = (Q_j - Q_Ns) / V,   dq/dT = q_T - C_tot/T (Q_Ns + Q_M),
+//     CONP  dq/dV = -(sum_{j<Ns} Q_j [C]_j - Q_Ns sum_{j<Ns} [C]_j) / V,
+//     CONV  dq/dP = (Q_Ns + Q_M) / (R T),
+// so species row k of J holds sum_i nu_ki (Q_ij - Q_iNs) in its species
+// columns and V sum_i nu_ki dq_i/dx in the T and V/P columns.  The T row
+// follows from differentiating dT/dt = -N/D and the V/P row from the ideal-gas
+// form of dV/dt or dP/dt; both need sum_i dE_i Q_ij and sum_i dOmega_i Q_ij,
+// accumulated in TQ and SQ.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace pj {
+
+namespace {
+
+constexpr double LN10 = 2.302585092994045684;
+
+struct dd {
+    double hi, lo;
+};
+
+// Error-free transformations (Knuth TwoSum, Dekker FastTwoSum)
+__device__ inline void two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+__device__ inline void fast_two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    e = b - (s - a);
+}
+// double-double addition (accurate variant)
+__device__ inline dd dd_add(dd a, dd b) {
+    double s, t, u, v;
+    two_sum(a.hi, b.hi, s, t);
+    two_sum(a.lo, b.lo, u, v);
+    t += u;
+    fast_two_sum(s, t, s, t);
+    t += v;
+    fast_two_sum(s, t, s, t);
+    return {s, t};
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of K per-thread values over the workgroup, in a fixed order; every
+// thread receives the totals.  red: LDS scratch of 16*K doubles.
+template <int K>
+__device__ inline void block_sum(double (&v)[K], double* red, int wave, int nwave) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = wave_sum(v[q]);
+    if (nwave == 1) return;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) red[wave * K + q] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < nwave; ++w) t += red[w * K + q];
+        v[q] = t;
+    }
+    __syncthreads();
+}
+
+__device__ inline dd block_dd_sum(dd a, double* red, int wave, int nwave) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        dd b{__shfl_xor(a.hi, o, 64), __shfl_xor(a.lo, o, 64)};
+        a = dd_add(a, b);
+    }
+    if (nwave == 1) return a;
+    if ((threadIdx.x & 63) == 0) { red[2 * wave] = a.hi; red[2 * wave + 1] = a.lo; }
+    __syncthreads();
+    dd t{0.0, 0.0};
+    for (int w = 0; w < nwave; ++w) t = dd_add(t, dd{red[2 * w], red[2 * w + 1]});
+    __syncthreads();
+    return t;
+}
+
+__device__ inline double cpow(double c, int nu) {
+    // c^nu for nu in 0..3
+    return nu == 0 ? 1.0 : nu == 1 ? c : nu == 2 ? c * c : c * c * c;
+}
+__device__ inline double dcpow(double c, int nu) {
+    // d(c^nu)/dc for nu in 0..3
+    return nu == 0 ? 0.0 : nu == 1 ? 1.0 : nu == 2 ? 2.0 * c : 3.0 * c * c;
+}
+
+}  // namespace
+
+int64_t lds_bytes(const DevMech& dm, int mode) {
+    int64_t d = 5 * (int64_t)(dm.ns + 1) + 16 * 8;
+    if (mode != MODE_SRC) d += dm.nnz + dm.ns + 2 * (int64_t)(dm.ns + 1);
+    if (mode == MODE_DENSE) d += dm.N;
+    return d * 8;
+}
+
+template <int FORM, int LAYOUT, int MODE>
+__global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
+                                                  const double* __restrict__ state,
+                                                  const double* __restrict__ param,
+                                                  double* __restrict__ dstate,
+                                                  double* __restrict__ jac) {
+    extern __shared__ double lds[];
+    constexpr bool JAC = MODE != MODE_SRC;
+    const int ns = dm.ns, N = dm.N, bath = dm.bath, nrp = dm.nr_pad, nnz = dm.nnz;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int wave = tid >> 6, nwave = nthr >> 6;
+
+    double* C = lds;
+    double* G = C + (ns + 1);
+    double* H = G + (ns + 1);
+    double* CP = H + (ns + 1);
+    double* W = CP + (ns + 1);
+    double* red = W + (ns + 1);
+    double* J = red + 16 * 8;
+    double* B = J + nnz;
+    double* TQ = B + ns;
+    double* SQ = TQ + (ns + 1);
+    double* ROW = SQ + (ns + 1);
+
+    for (long s = blockIdx.x; s < n; s += gridDim.x) {
+        auto X = [&](int i) -> double {
+            return LAYOUT == PJ_LAYOUT_F ? state[(long)i * n + s] : state[s * (long)N + i];
+        };
+        const double T = X(0);
+        const double Sv = X(1);
+        const double Q = param[s];
+        const double V = FORM == PJ_CONP ? Sv : Q;
+        const double P = FORM == PJ_CONP ? Q : Sv;
+        const double invT = 1.0 / T;
+        const double invV = 1.0 / V;
+
+        // ---- concentrations and the bath-gas closure (Sec. 2.2):
+        //      n_Ns = P V / (R T) - RN(sum_{k<Ns} n_k)
+        dd acc{0.0, 0.0};
+        for (int k = tid; k < ns - 1; k += nthr) {
+            double nk = X(2 + k);
+            acc = dd_add(acc, dd{nk, 0.0});
+            C[k] = nk / V;
+        }
+        for (int k = tid; k < ns + 1; k += nthr) W[k] = 0.0;
+        if (JAC) {
+            for (int e = tid; e < nnz; e += nthr) J[e] = 0.0;
+            for (int k = tid; k < ns; k += nthr) B[k] = 0.0;
+            for (int k = tid; k < ns + 1; k += nthr) { TQ[k] = 0.0; SQ[k] = 0.0; }
+        }
+        acc = block_dd_sum(acc, red, wave, nwave);
+        const double nsum = acc.hi;
+        const double ntot = (P * V) / (RU * T);
+        const double nbath = ntot - nsum;
+        if (tid == 0) {
+            C[bath] = nbath / V;
+            C[ns] = 1.0;
+            G[ns] = 0.0;
+            H[ns] = 0.0;
+            CP[ns] = 0.0;
+        }
+        __syncthreads();
+
+        const double lnT = log(T);
+        const double Ctot = P / (RU * T);
+        const double lnP0RT = log(PREF / (RU * T));
+
+        // ---- species thermodynamics (NASA-7)
+        double tsum[2] = {0.0, 0.0};   // D' = sum C chat/R, dD'/dT = sum C dCp/R/dT
+        for (int k = tid; k < ns; k += nthr) {
+            const int rg = T < dm.tmid[k] ? 0 : 1;
+            const double* c = dm.th + (size_t)rg * TH_N * ns + k;
+            auto a = [&](int q) { return c[(size_t)q * ns]; };
+            const double a0 = a(0), a1 = a(1);
+            double cp = a0 + T * (a1 + T * (a(2) + T * (a(3) + T * a(4))));
+            double h = a0 + T * (a(5) + T * (a(6) + T * (a(7) + T * a(8)))) + a(12) * invT;
+            double sr = a0 * lnT + T * (a1 + T * (a(9) + T * (a(10) + T * a(11)))) + a(13);
+            G[k] = h - sr;
+            H[k] = h;
+            double ch = FORM == PJ_CONP ? cp : cp - 1.0;
+            CP[k] = ch;
+            double ck = C[k];
+            tsum[0] += ck * ch;
+            if (JAC) tsum[1] += ck * (a1 + T * (a(14) + T * (a(15) + T * a(16))));
+        }
+        block_sum(tsum, red, wave, nwave);
+        const double Dp = tsum[0];
+        const double dDpdT = tsum[1];
+        __syncthreads();
+
+        // ---- reactions: rates of progress and Jacobian sub-products
+        double racc[4] = {0.0, 0.0, 0.0, 0.0};  // TT, TS, ST, SS
+        for (int p = tid; p < dm.nr; p += nthr) {
+            const uint32_t w = dm.info[p];
+            const int kind = info_kind(w);
+            const bool rev = (w & INFO_REV) != 0;
+            int spc[NSLOT], nu[NSLOT];
+#pragma unroll
+            for (int a = 0; a < NSLOT; ++a) {
+                spc[a] = dm.sp[(size_t)a * nrp + p];
+                nu[a] = info_nu(w, a);
+            }
+            const double lnA = dm.arr[p], bexp = dm.arr[nrp + p], th = dm.arr[2 * (size_t)nrp + p];
+            const double lnkf = lnA + bexp * lnT - th * invT;
+            double dG = 0.0, dH = 0.0;
+            double cf[NSLOT];
+#pragma unroll
+            for (int a = 0; a < NSLOT; ++a) {
+                const double sgn = a < MAXSIDE ? -(double)nu[a] : (double)nu[a];
+                dG += sgn * G[spc[a]];
+                dH += sgn * H[spc[a]];
+                cf[a] = C[spc[a]];
+            }
+            const double dnu = dm.dnu[p];
+            const double kf = exp(lnkf);
+            double fr[NSLOT];
+#pragma unroll
+            for (int a = 0; a < NSLOT; ++a) fr[a] = cpow(cf[a], nu[a]);
+            const double Pf = fr[0] * fr[1] * fr[2];
+            const double Pb = fr[3] * fr[4] * fr[5];
+            const double lnkr = lnkf + dG - dnu * lnP0RT;
+            const double kr = rev ? exp(lnkr) : 0.0;
+            const double Rf = kf * Pf;
+            const double Rr = kr * Pb;
+            const double R = Rf - Rr;
+
+            // pressure modification
+            double c = 1.0, dcdM = 0.0, dcdT = 0.0;
+            const int e0 = dm.eff_ptr[p], e1 = dm.eff_ptr[p + 1];
+            if (kind != K_ELEM) {
+                double M = Ctot;
+                for (int e = e0; e < e1; ++e) M += dm.eff_am1[e] * C[dm.eff_sp[e]];
+                if (kind == K_THREEBODY) {
+                    c = M;
+                    dcdM = 1.0;
+                } else {
+                    const double lnk0 = dm.low[p] + dm.low[nrp + p] * lnT - dm.low[2 * (size_t)nrp + p] * invT;
+                    const double rk = exp(lnk0 - lnkf);     // k0 / k_inf
+                    const double Pr = M * rk;
+                    double F = 1.0, dlF_dlP = 0.0, dlF_dT = 0.0;
+                    if (kind == K_TROE) {
+                        const double al = dm.troe[p], i3 = dm.troe[nrp + p];
+                        const double i1 = dm.troe[2 * (size_t)nrp + p], t2 = dm.troe[3 * (size_t)nrp + p];
+                        const double e3 = exp(-T * i3), e1x = exp(-T * i1), e2 = exp(-t2 * invT);
+                        const double Fc = (1.0 - al) * e3 + al * e1x + e2;
+                        const double L = log10(Fc);
+                        const double cc = -0.4 - 0.67 * L;
+                        const double nn = 0.75 - 1.27 * L;
+                        const double A = log10(Pr) + cc;
+                        const double Bd = nn - 0.14 * A;
+                        const double f = A / Bd;
+                        const double den = 1.0 + f * f;
+                        const double lF = L / den;
+                        F = exp(LN10 * lF);
+                        if (JAC) {
+                            const double g = -2.0 * L * f / (den * den);
+                            dlF_dlP = g * nn / (Bd * Bd);
+                            const double df_dL = (-0.67 * Bd + 1.1762 * A) / (Bd * Bd);
+                            const double dlF_dL = 1.0 / den + g * df_dL;
+                            const double dFc = -(1.0 - al) * i3 * e3 - al * i1 * e1x + t2 * invT * invT * e2;
+                            dlF_dT = dlF_dL * dFc / (Fc * LN10);
+                        }
+                    }
+                    const double ip = 1.0 / (1.0 + Pr);
+                    c = F * Pr * ip;
+                    if (JAC) {
+                        const double dc_dPr = F * ip * ip + F * ip * dlF_dlP;
+                        dcdM = dc_dPr * rk;
+                        const double dlnPr = (dm.low[nrp + p] + dm.low[2 * (size_t)nrp + p] * invT) * invT
+                                             - (bexp + th * invT) * invT;
+                        dcdT = dc_dPr * Pr * dlnPr + c * LN10 * dlF_dT;
+                    }
+                }
+            }
+            const double q = c * R;
+#pragma unroll
+            for (int a = 0; a < NSLOT; ++a) {
+                if (nu[a]) {
+                    const double sgn = a < MAXSIDE ? -(double)nu[a] : (double)nu[a];
+                    atomicAdd(&W[spc[a]], sgn * q);
+                }
+            }
+            if (!JAC) continue;
+
+            // concentration partials of q
+            const double dlnkf = (bexp + th * invT) * invT;
+            const double dlnkr = dlnkf - (dH - dnu) * invT;
+            double Qs[NSLOT];
+#pragma unroll
+            for (int a = 0; a < NSLOT; ++a) {
+                const double d = dcpow(cf[a], nu[a]);
+                if (a < MAXSIDE) {
+                    const double o = (a == 0 ? fr[1] * fr[2] : a == 1 ? fr[0] * fr[2] : fr[0] * fr[1]);
+                    Qs[a] = c * kf * d * o;
+                } else {
+                    const double o = (a == 3 ? fr[4] * fr[5] : a == 4 ? fr[3] * fr[5] : fr[3] * fr[4]);
+                    Qs[a] = rev ? -c * kr * d * o : 0.0;
+                }
+            }
+            const double QM = R * dcdM;
+            const double qT = c * (Rf * dlnkf - Rr * dlnkr) + R * dcdT;
+            double Qb = 0.0, sQC = 0.0;
+            if (w & INFO_BATH) {
+#pragma unroll
+                for (int a = 0; a < NSLOT; ++a)
+                    if (spc[a] == bath) Qb += Qs[a];
+                for (int e = e0; e < e1; ++e)
+                    if (dm.eff_sp[e] == bath) Qb += QM * dm.eff_am1[e];
+            }
+            if (FORM == PJ_CONP) {
+#pragma unroll
+                for (int a = 0; a < NSLOT; ++a)
+                    if (spc[a] < bath) sQC += Qs[a] * cf[a];
+                for (int e = e0; e < e1; ++e) {
+                    const int se = dm.eff_sp[e];
+                    if (se < bath) sQC += QM * dm.eff_am1[e] * C[se];
+                }
+            }
+            const double dqdT = qT - Ctot * invT * (Qb + QM);
+            const double dqdS = FORM == PJ_CONP ? -(sQC - Qb * (nsum * invV)) * invV
+                                                : (Qb + QM) / (RU * T);
+            const double dE = FORM == PJ_CONP ? dH : dH - dnu;
+            const double dOm = dm.domega[p];
+            racc[0] += dE * dqdT;
+            racc[1] += dE * dqdS;
+            racc[2] += dOm * dqdT;
+            racc[3] += dOm * dqdS;
+
+            // energy / mole weighted partials (T and V/P rows)
+#pragma unroll
+            for (int b = 0; b < NSLOT; ++b) {
+                if (nu[b] && (b < MAXSIDE || rev)) {
+                    atomicAdd(&TQ[spc[b]], dE * Qs[b]);
+                    atomicAdd(&SQ[spc[b]], dOm * Qs[b]);
+                }
+            }
+            for (int e = e0; e < e1; ++e) {
+                const double qe = QM * dm.eff_am1[e];
+                atomicAdd(&TQ[dm.eff_sp[e]], dE * qe);
+                atomicAdd(&SQ[dm.eff_sp[e]], dOm * qe);
+            }
+            // species rows
+#pragma unroll
+            for (int a = 0; a < NSLOT; ++a) {
+                if (!nu[a]) continue;
+                const uint16_t rb = dm.rowbase[(size_t)a * nrp + p];
+                if (rb == NOSLOT) continue;
+                const double sgn = a < MAXSIDE ? -(double)nu[a] : (double)nu[a];
+                atomicAdd(&J[rb], V * sgn * dqdT);
+                atomicAdd(&J[rb + 1], V * sgn * dqdS);
+#pragma unroll
+                for (int b = 0; b < NSLOT; ++b) {
+                    if (!(nu[b] && (b < MAXSIDE || rev))) continue;
+                    if (spc[b] == bath) {
+                        atomicAdd(&B[spc[a]], sgn * Qs[b]);
+                    } else {
+                        atomicAdd(&J[dm.slot[((size_t)a * NSLOT + b) * nrp + p]], sgn * Qs[b]);
+                    }
+                }
+                for (int e = e0; e < e1; ++e) {
+                    const double qe = sgn * QM * dm.eff_am1[e];
+                    if (dm.eff_sp[e] == bath) atomicAdd(&B[spc[a]], qe);
+                    else atomicAdd(&J[dm.effslot[(size_t)e * NSLOT + a]], qe);
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- source terms (Sec. 2.2)
+        double fsum[JAC ? 7 : 2];
+        fsum[0] = 0.0;  // N' = sum e_k/(RT) wdot_k
+        fsum[1] = 0.0;  // Omega
+        if (JAC) {
+            fsum[2] = 0.0;  // sum chat_k/R wdot_k
+#pragma unroll
+            for (int q = 0; q < 4; ++q) fsum[3 + q] = racc[q];
+        }
+        for (int k = tid; k < ns; k += nthr) {
+            const double wk = W[k];
+            const double ek = FORM == PJ_CONP ? H[k] : H[k] - 1.0;
+            fsum[0] += ek * wk;
+            fsum[1] += dm.wfac[k] * wk;
+            if (JAC) fsum[2] += CP[k] * wk;
+        }
+        block_sum(fsum, red, wave, nwave);
+        const double Np = fsum[0], Om = fsum[1];
+        const double Tdot = -T * Np / Dp;
+        const double Sdot = FORM == PJ_CONP ? V * Tdot * invT + V * RU * T * Om / P
+                                            : P * Tdot * invT + RU * T * Om;
+        if (dstate) {
+            for (int i = tid; i < N; i += nthr) {
+                const double v = i == 0 ? Tdot : i == 1 ? Sdot : V * W[i - 2];
+                if (LAYOUT == PJ_LAYOUT_F) dstate[(long)i * n + s] = v;
+                else dstate[s * (long)N + i] = v;
+            }
+        }
+        if (!JAC) {
+            __syncthreads();
+            continue;
+        }
+
+        // ---- Jacobian: T and V/P rows, closure of the species rows
+        {
+            const double Scw = fsum[2], TT = fsum[3], TS = fsum[4], ST = fsum[5], SS = fsum[6];
+            const double cpb = CP[bath];
+            const double Csum = nsum * invV;
+            const double dDdT = dDpdT - cpb * Ctot * invT;
+            const double dDdS = FORM == PJ_CONP ? -((Dp - cpb * C[bath]) - cpb * Csum) * invV
+                                                : cpb / (RU * T);
+            const double J00 = -(T * TT + Scw + Tdot * dDdT) / Dp;
+            const double J01 = -(T * TS + Tdot * dDdS) / Dp;
+            const double RTP = RU * T / P;
+            for (int j = tid; j < N; j += nthr) {
+                double j0, j1;
+                if (j == 0) {
+                    j0 = J00;
+                    j1 = FORM == PJ_CONP
+                             ? V * invT * J00 - V * Tdot * invT * invT + V * (RU / P) * Om + V * RTP * ST
+                             : P * invT * J00 - P * Tdot * invT * invT + RU * Om + RU * T * ST;
+                } else if (j == 1) {
+                    j0 = J01;
+                    j1 = FORM == PJ_CONP ? Tdot * invT + V * invT * J01 + RTP * Om + V * RTP * SS
+                                         : Tdot * invT + P * invT * J01 + RU * T * SS;
+                } else {
+                    const int k = j - 2;
+                    j0 = -(T * (TQ[k] - TQ[bath]) + Tdot * (CP[k] - cpb)) * invV / Dp;
+                    j1 = FORM == PJ_CONP ? V * invT * j0 + RTP * (SQ[k] - SQ[bath])
+                                         : P * invT * j0 + RU * T * (SQ[k] - SQ[bath]) * invV;
+                }
+                J[j] = j0;
+                J[N + j] = j1;
+            }
+            // bath-gas dependent rows are dense: subtract their bath partial
+            for (int d = 0; d < dm.n_dense_rows; ++d) {
+                const int k = dm.dense_rows[d];
+                const int r0 = dm.row_ptr[2 + k] + 2, r1 = dm.row_ptr[3 + k];
+                const double bk = B[k];
+                for (int e = r0 + tid; e < r1; e += nthr) J[e] -= bk;
+            }
+            if (FORM == PJ_CONP) {
+                // d(V wdot_k)/dV = wdot_k + V dwdot_k/dV
+                for (int k = tid; k < ns - 1; k += nthr) J[dm.row_ptr[2 + k] + 1] += W[k];
+            }
+        }
+        __syncthreads();
+
+        if (MODE == MODE_SPARSE) {
+            for (int e = tid; e < nnz; e += nthr) {
+                if (LAYOUT == PJ_LAYOUT_F) jac[(long)e * n + s] = J[e];
+                else jac[s * (long)nnz + e] = J[e];
+            }
+        } else {
+            for (int i = 0; i < N; ++i) {
+                for (int j = tid; j < N; j += nthr) ROW[j] = 0.0;
+                __syncthreads();
+                const int r0 = dm.row_ptr[i], r1 = dm.row_ptr[i + 1];
+                for (int e = r0 + tid; e < r1; e += nthr) ROW[dm.col_idx[e]] = J[e];
+                __syncthreads();
+                for (int j = tid; j < N; j += nthr) {
+                    if (LAYOUT == PJ_LAYOUT_F) jac[s + n * ((long)i + (long)N * j)] = ROW[j];
+                    else jac[s * (long)N * N + (long)i * N + j] = ROW[j];
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int FORM, int LAYOUT, int MODE>
+static hipError_t launch_t(const DevMech& dm, int64_t n, const double* state, const double* param,
+                           double* dstate, double* jac, int wps, int64_t lds, hipStream_t stream) {
+    auto k = pj_kernel<FORM, LAYOUT, MODE>;
+    if (lds > 65536) {
+        // allow the kernel the device's whole LDS per workgroup
+        int dev = 0, mx = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t grid = n < (1 << 30) ? n : (1 << 30);
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * wps), (size_t)lds, stream, dm, (long)n,
+                       state, param, dstate, jac);
+    return hipGetLastError();
+}
+
+hipError_t launch(const DevMech& dm, int mode, int form, int layout, int64_t n, const double* state,
+                  const double* param, double* dstate, double* jac, int wps, int64_t lds,
+                  hipStream_t stream) {
+#define PJ_CASE(F, L, M)                                                                   \
+    if (form == F && layout == L && mode == M)                                             \
+        return launch_t<F, L, M>(dm, n, state, param, dstate, jac, wps, lds, stream);
+#define PJ_MODES(F, L) PJ_CASE(F, L, MODE_SRC) PJ_CASE(F, L, MODE_SPARSE) PJ_CASE(F, L, MODE_DENSE)
+    PJ_MODES(PJ_CONP, PJ_LAYOUT_F)
+    PJ_MODES(PJ_CONP, PJ_LAYOUT_C)
+    PJ_MODES(PJ_CONV, PJ_LAYOUT_F)
+    PJ_MODES(PJ_CONV, PJ_LAYOUT_C)
+#undef PJ_MODES
+#undef PJ_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pj

@@ -1,0 +1,432 @@
+// Host mechanism compiler: parse and validate a mechanism description, derive
+// the Jacobian's CSR pattern (paper Sec. 3.4) and the static scatter tables
+// that replace the paper's run-time linear search of a CSR row (Sec. 3.4,
+// sparse index lookup), and upload everything to the device once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "internal.h"
+
+namespace pj {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// description parsing (one whitespace-separated token stream)
+
+struct Tokens {
+    std::vector<std::string> t;
+    size_t p = 0;
+    bool more() const { return p < t.size(); }
+    const std::string& peek() const { static std::string e; return p < t.size() ? t[p] : e; }
+    bool word(std::string& s) { if (p >= t.size()) return false; s = t[p++]; return true; }
+    bool integer(long& v) {
+        if (p >= t.size()) return false;
+        char* end = nullptr;
+        v = std::strtol(t[p].c_str(), &end, 10);
+        if (!end || *end) return false;
+        ++p;
+        return true;
+    }
+    bool real(double& v) {
+        if (p >= t.size()) return false;
+        char* end = nullptr;
+        v = std::strtod(t[p].c_str(), &end);
+        if (!end || *end) return false;
+        ++p;
+        return true;
+    }
+    bool expect(const char* w) { std::string s; return word(s) && s == w; }
+};
+
+pj_status parse_description(const char* path, Mechanism& m, std::string& err) {
+    std::ifstream f(path);
+    if (!f) { err = std::string("cannot open ") + path; return PJ_E_INVALID; }
+    Tokens tk;
+    std::string w;
+    while (f >> w) tk.t.push_back(w);
+    long v;
+    if (!tk.expect("PJMECH") || !tk.integer(v) || v != 1) { err = "not a PJMECH 1 description"; return PJ_E_PARSE; }
+    if (!tk.expect("SPECIES") || !tk.integer(v) || v < 2 || v > 60000) { err = "bad SPECIES record"; return PJ_E_PARSE; }
+    m.ns = (int)v;
+    m.W.resize(m.ns);
+    m.comp.resize((size_t)m.ns * 4);
+    m.tmid.resize(m.ns);
+    m.alo.resize((size_t)m.ns * 7);
+    m.ahi.resize((size_t)m.ns * 7);
+    for (int k = 0; k < m.ns; ++k) {
+        std::string name;
+        double tl, th;
+        if (!tk.expect("SP") || !tk.integer(v) || v != k || !tk.word(name) || !tk.real(m.W[k])) {
+            err = "bad SP record " + std::to_string(k);
+            return PJ_E_PARSE;
+        }
+        for (int e = 0; e < 4; ++e) {
+            if (!tk.integer(v) || v < 0) { err = "bad composition of species " + std::to_string(k); return PJ_E_PARSE; }
+            m.comp[(size_t)k * 4 + e] = (int)v;
+        }
+        if (!tk.real(tl) || !tk.real(m.tmid[k]) || !tk.real(th)) { err = "bad temperature ranges"; return PJ_E_PARSE; }
+        for (int c = 0; c < 7; ++c) if (!tk.real(m.alo[(size_t)k * 7 + c])) { err = "bad NASA coefficients"; return PJ_E_PARSE; }
+        for (int c = 0; c < 7; ++c) if (!tk.real(m.ahi[(size_t)k * 7 + c])) { err = "bad NASA coefficients"; return PJ_E_PARSE; }
+        if (!(m.W[k] > 0) || !(m.tmid[k] > 0)) { err = "non-positive weight or T_mid"; return PJ_E_PARSE; }
+    }
+    if (!tk.expect("REACTIONS") || !tk.integer(v) || v < 0 || v > 1000000) { err = "bad REACTIONS record"; return PJ_E_PARSE; }
+    m.nr = (int)v;
+    m.rx.resize(m.nr);
+    for (int i = 0; i < m.nr; ++i) {
+        Mechanism::Rxn& r = m.rx[i];
+        std::string kind;
+        long rev, n;
+        if (!tk.expect("RX") || !tk.integer(v) || v != i || !tk.word(kind) || !tk.integer(rev)) {
+            err = "bad RX record " + std::to_string(i);
+            return PJ_E_PARSE;
+        }
+        if (kind == "ELEM") r.kind = K_ELEM;
+        else if (kind == "THREEBODY") r.kind = K_THREEBODY;
+        else if (kind == "LINDEMANN") r.kind = K_LINDEMANN;
+        else if (kind == "TROE") r.kind = K_TROE;
+        else { err = "unknown reaction type " + kind; return PJ_E_PARSE; }
+        r.rev = rev != 0;
+        for (int side = 0; side < 2; ++side) {
+            auto& lst = side == 0 ? r.reac : r.prod;
+            if (!tk.integer(n) || n < 0 || n > 16) { err = "bad side of reaction " + std::to_string(i); return PJ_E_PARSE; }
+            for (long a = 0; a < n; ++a) {
+                long s, nu;
+                if (!tk.integer(s) || !tk.integer(nu) || s < 0 || s >= m.ns || nu <= 0) {
+                    err = "bad species/coefficient in reaction " + std::to_string(i);
+                    return PJ_E_PARSE;
+                }
+                bool merged = false;
+                for (auto& e : lst) if (e.first == s) { e.second += (int)nu; merged = true; }
+                if (!merged) lst.push_back({(int)s, (int)nu});
+            }
+        }
+        if (!tk.real(r.lnA) || !tk.real(r.b) || !tk.real(r.theta)) { err = "bad Arrhenius in reaction " + std::to_string(i); return PJ_E_PARSE; }
+        bool has_low = false, has_troe = false;
+        while (tk.more() && (tk.peek() == "LOW" || tk.peek() == "TROE" || tk.peek() == "EFF")) {
+            std::string kw;
+            tk.word(kw);
+            if (kw == "LOW") {
+                if (!tk.real(r.lnA0) || !tk.real(r.b0) || !tk.real(r.theta0)) { err = "bad LOW"; return PJ_E_PARSE; }
+                has_low = true;
+            } else if (kw == "TROE") {
+                if (!tk.real(r.alpha) || !tk.real(r.T3) || !tk.real(r.T1) || !tk.real(r.T2)) { err = "bad TROE"; return PJ_E_PARSE; }
+                has_troe = true;
+            } else {
+                if (!tk.integer(n) || n < 0) { err = "bad EFF"; return PJ_E_PARSE; }
+                for (long a = 0; a < n; ++a) {
+                    long s;
+                    double al;
+                    if (!tk.integer(s) || !tk.real(al) || s < 0 || s >= m.ns || al < 0) { err = "bad efficiency"; return PJ_E_PARSE; }
+                    r.eff.push_back({(int)s, al});
+                }
+            }
+        }
+        if ((r.kind == K_LINDEMANN || r.kind == K_TROE) != has_low) { err = "falloff reaction without LOW (or LOW on another type)"; return PJ_E_PARSE; }
+        if ((r.kind == K_TROE) != has_troe) { err = "TROE parameters do not match the reaction type"; return PJ_E_PARSE; }
+        if (r.kind == K_TROE && (!(r.T3 > 0) || !(r.T1 > 0))) { err = "Troe T*** and T* must be positive"; return PJ_E_PARSE; }
+        if (r.kind == K_ELEM && !r.eff.empty()) { err = "efficiencies on an elementary reaction"; return PJ_E_PARSE; }
+    }
+    if (!tk.expect("END") || tk.more()) { err = "missing END"; return PJ_E_PARSE; }
+    return PJ_OK;
+}
+
+pj_status validate(const Mechanism& m, std::string& err) {
+    for (int i = 0; i < m.nr; ++i) {
+        const auto& r = m.rx[i];
+        if (r.reac.empty() || r.prod.empty()) { err = "empty reaction side in reaction " + std::to_string(i); return PJ_E_UNSUPPORTED; }
+        if (r.reac.size() > MAXSIDE || r.prod.size() > MAXSIDE) {
+            err = "more than 3 species on one side of reaction " + std::to_string(i);
+            return PJ_E_UNSUPPORTED;
+        }
+        for (auto& a : r.reac) {
+            if (a.second > 3) { err = "coefficient above 3 in reaction " + std::to_string(i); return PJ_E_UNSUPPORTED; }
+            for (auto& b : r.prod)
+                if (a.first == b.first) { err = "species on both sides of reaction " + std::to_string(i); return PJ_E_UNSUPPORTED; }
+        }
+        for (auto& b : r.prod)
+            if (b.second > 3) { err = "coefficient above 3 in reaction " + std::to_string(i); return PJ_E_UNSUPPORTED; }
+        for (int e = 0; e < 4; ++e) {
+            long lhs = 0, rhs = 0;
+            for (auto& a : r.reac) lhs += (long)a.second * m.comp[(size_t)a.first * 4 + e];
+            for (auto& b : r.prod) rhs += (long)b.second * m.comp[(size_t)b.first * 4 + e];
+            if (lhs != rhs) { err = "reaction " + std::to_string(i) + " does not conserve elements"; return PJ_E_UNBALANCED; }
+        }
+    }
+    return PJ_OK;
+}
+
+// third-body efficiencies different from one, merged per species
+std::vector<std::pair<int, double>> enhanced(const Mechanism::Rxn& r) {
+    std::map<int, double> a;
+    for (auto& e : r.eff) a[e.first] = e.second;
+    std::vector<std::pair<int, double>> out;
+    for (auto& e : a) if (e.second != 1.0) out.push_back(e);
+    return out;
+}
+
+bool depends_on_bath(const Mechanism& m, const Mechanism::Rxn& r) {
+    int bath = m.ns - 1;
+    for (auto& a : r.reac) if (a.first == bath) return true;
+    if (r.rev) for (auto& b : r.prod) if (b.first == bath) return true;
+    if (r.kind != K_ELEM) for (auto& e : enhanced(r)) if (e.first == bath) return true;
+    return false;
+}
+
+// The Jacobian pattern (Sec. 3.4).
+void build_pattern(Mechanism& m) {
+    int ns = m.ns, N = ns + 1, bath = ns - 1;
+    std::vector<std::vector<char>> P(N, std::vector<char>(N, 0));
+    for (int i = 0; i < N; ++i) { P[0][i] = P[1][i] = P[i][0] = P[i][1] = P[i][i] = 1; }
+    for (const auto& r : m.rx) {
+        std::vector<int> deps;
+        for (auto& a : r.reac) deps.push_back(a.first);
+        if (r.rev) for (auto& b : r.prod) deps.push_back(b.first);
+        if (r.kind != K_ELEM) for (auto& e : enhanced(r)) deps.push_back(e.first);
+        bool dense = depends_on_bath(m, r);
+        auto row = [&](int k) {
+            if (k == bath) return;
+            if (dense) { for (int j = 2; j < N; ++j) P[2 + k][j] = 1; return; }
+            for (int j : deps) if (j != bath) P[2 + k][2 + j] = 1;
+        };
+        for (auto& a : r.reac) row(a.first);
+        for (auto& b : r.prod) row(b.first);
+    }
+    m.row_ptr.assign(N + 1, 0);
+    m.col_idx.clear();
+    for (int i = 0; i < N; ++i) {
+        for (int j = 0; j < N; ++j) if (P[i][j]) m.col_idx.push_back(j);
+        m.row_ptr[i + 1] = (int32_t)m.col_idx.size();
+    }
+    m.nnz = (int)m.col_idx.size();
+}
+
+int csr_find(const Mechanism& m, int row, int col) {
+    auto b = m.col_idx.begin() + m.row_ptr[row], e = m.col_idx.begin() + m.row_ptr[row + 1];
+    auto it = std::lower_bound(b, e, col);
+    return (it != e && *it == col) ? (int)(it - m.col_idx.begin()) : -1;
+}
+
+struct Section {
+    size_t off;
+    size_t bytes;
+};
+
+}  // namespace
+
+pj_status build_mechanism(const char* path, Mechanism& m, std::string& err) {
+    pj_status st = parse_description(path, m, err);
+    if (st != PJ_OK) return st;
+    st = validate(m, err);
+    if (st != PJ_OK) return st;
+    // kernel order: by kind, reversible elementary before irreversible, so
+    // that each 64-reaction chunk runs one code path
+    m.order.resize(m.nr);
+    for (int i = 0; i < m.nr; ++i) m.order[i] = i;
+    auto cls = [&](int i) { const auto& r = m.rx[i]; return r.kind == K_ELEM ? (r.rev ? 0 : 1) : r.kind + 1; };
+    std::stable_sort(m.order.begin(), m.order.end(), [&](int a, int b) { return cls(a) < cls(b); });
+    build_pattern(m);
+    if (m.nnz >= 65535) { err = "more than 65534 Jacobian non-zeros"; return PJ_E_UNSUPPORTED; }
+    return PJ_OK;
+}
+
+pj_status upload_mechanism(Mechanism& m, std::string& err) {
+    const int ns = m.ns, nr = m.nr, N = ns + 1, bath = ns - 1;
+    const int nr_pad = std::max(64, (nr + 63) / 64 * 64);
+    const double Wb = m.W[bath];
+
+    // ---- species tables
+    std::vector<double> th((size_t)2 * TH_N * ns, 0.0), tmid(ns), wfac(ns);
+    for (int k = 0; k < ns; ++k) {
+        for (int rg = 0; rg < 2; ++rg) {
+            const double* a = (rg == 0 ? m.alo.data() : m.ahi.data()) + (size_t)k * 7;
+            double row[TH_N] = {a[0], a[1], a[2], a[3], a[4],                 // Cp/R
+                                a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5,     // H/RT
+                                a[2] / 2, a[3] / 3, a[4] / 4,               // S/R
+                                a[5], a[6],
+                                2 * a[2], 3 * a[3], 4 * a[4],               // dCp/R/dT
+                                0.0};
+            for (int c = 0; c < TH_N; ++c) th[((size_t)rg * TH_N + c) * ns + k] = row[c];
+        }
+        tmid[k] = m.tmid[k];
+        wfac[k] = k == bath ? 0.0 : 1.0 - m.W[k] / Wb;
+    }
+
+    // ---- reaction tables (kernel order)
+    std::vector<uint32_t> info(nr_pad, 0);
+    std::vector<uint16_t> sp((size_t)NSLOT * nr_pad, (uint16_t)ns);
+    std::vector<double> arr((size_t)3 * nr_pad, 0.0), low((size_t)3 * nr_pad, 0.0),
+        troe((size_t)4 * nr_pad, 0.0), dnu(nr_pad, 0.0), domega(nr_pad, 0.0);
+    std::vector<int32_t> eff_ptr(nr_pad + 1, 0);
+    std::vector<uint16_t> eff_sp;
+    std::vector<double> eff_am1;
+    std::vector<uint16_t> rowbase((size_t)NSLOT * nr_pad, NOSLOT), slot((size_t)NSLOT * NSLOT * nr_pad, NOSLOT);
+    std::vector<uint16_t> effslot;
+    std::vector<char> dense_row(ns, 0);
+    for (int p = 0; p < nr_pad; ++p) {
+        eff_ptr[p] = (int32_t)eff_sp.size();
+        if (p >= nr) continue;
+        const auto& r = m.rx[m.order[p]];
+        int spa[NSLOT], nua[NSLOT];
+        for (int a = 0; a < NSLOT; ++a) { spa[a] = ns; nua[a] = 0; }
+        for (size_t a = 0; a < r.reac.size(); ++a) { spa[a] = r.reac[a].first; nua[a] = r.reac[a].second; }
+        for (size_t b = 0; b < r.prod.size(); ++b) { spa[3 + b] = r.prod[b].first; nua[3 + b] = r.prod[b].second; }
+        bool bathdep = depends_on_bath(m, r);
+        uint32_t w = 0;
+        for (int a = 0; a < NSLOT; ++a) w |= (uint32_t)nua[a] << (4 * a);
+        w |= (uint32_t)r.kind << 24;
+        if (r.rev) w |= INFO_REV;
+        if (bathdep) w |= INFO_BATH;
+        info[p] = w;
+        double sumnu = 0, om = 0;
+        for (int a = 0; a < NSLOT; ++a) {
+            sp[(size_t)a * nr_pad + p] = (uint16_t)spa[a];
+            if (!nua[a]) continue;
+            double nu = a < 3 ? -nua[a] : nua[a];
+            sumnu += nu;
+            om += nu * wfac[spa[a]];
+        }
+        dnu[p] = sumnu;
+        domega[p] = om;
+        arr[0 * (size_t)nr_pad + p] = r.lnA;
+        arr[1 * (size_t)nr_pad + p] = r.b;
+        arr[2 * (size_t)nr_pad + p] = r.theta;
+        if (r.kind == K_LINDEMANN || r.kind == K_TROE) {
+            low[0 * (size_t)nr_pad + p] = r.lnA0;
+            low[1 * (size_t)nr_pad + p] = r.b0;
+            low[2 * (size_t)nr_pad + p] = r.theta0;
+        }
+        if (r.kind == K_TROE) {
+            troe[0 * (size_t)nr_pad + p] = r.alpha;
+            troe[1 * (size_t)nr_pad + p] = 1.0 / r.T3;
+            troe[2 * (size_t)nr_pad + p] = 1.0 / r.T1;
+            troe[3 * (size_t)nr_pad + p] = r.T2;
+        }
+        // rows: species of the reaction other than the bath gas
+        for (int a = 0; a < NSLOT; ++a) {
+            if (!nua[a] || spa[a] == bath) continue;
+            rowbase[(size_t)a * nr_pad + p] = (uint16_t)m.row_ptr[2 + spa[a]];
+            if (bathdep) dense_row[spa[a]] = 1;
+            for (int b = 0; b < NSLOT; ++b) {
+                bool dep = nua[b] && (b < 3 || r.rev) && spa[b] != bath;
+                if (!dep) continue;
+                int s = csr_find(m, 2 + spa[a], 2 + spa[b]);
+                if (s < 0) { err = "internal: pattern misses a reaction entry"; return PJ_E_UNSUPPORTED; }
+                slot[((size_t)a * NSLOT + b) * nr_pad + p] = (uint16_t)s;
+            }
+        }
+        if (r.kind != K_ELEM) {
+            for (auto& e : enhanced(r)) {
+                eff_sp.push_back((uint16_t)e.first);
+                eff_am1.push_back(e.second - 1.0);
+                for (int a = 0; a < NSLOT; ++a) {
+                    uint16_t s = NOSLOT;
+                    if (nua[a] && spa[a] != bath && e.first != bath) {
+                        int f = csr_find(m, 2 + spa[a], 2 + e.first);
+                        if (f < 0) { err = "internal: pattern misses a third-body entry"; return PJ_E_UNSUPPORTED; }
+                        s = (uint16_t)f;
+                    }
+                    effslot.push_back(s);
+                }
+            }
+        }
+    }
+    eff_ptr[nr_pad] = (int32_t)eff_sp.size();
+    std::vector<int32_t> dense_rows;
+    for (int k = 0; k < ns; ++k) if (dense_row[k]) dense_rows.push_back(k);
+    std::vector<uint16_t> col16(m.col_idx.begin(), m.col_idx.end());
+    if (eff_sp.empty()) { eff_sp.push_back(0); eff_am1.push_back(0.0); effslot.assign(NSLOT, NOSLOT); }
+    if (dense_rows.empty()) dense_rows.push_back(-1);
+
+    // ---- one device buffer
+    size_t total = 0;
+    auto place = [&](size_t bytes) { size_t o = (total + 255) / 256 * 256; total = o + bytes; return o; };
+    size_t o_th = place(th.size() * 8), o_tmid = place(tmid.size() * 8), o_wfac = place(wfac.size() * 8);
+    size_t o_info = place(info.size() * 4), o_sp = place(sp.size() * 2), o_arr = place(arr.size() * 8);
+    size_t o_low = place(low.size() * 8), o_troe = place(troe.size() * 8), o_dnu = place(dnu.size() * 8);
+    size_t o_dom = place(domega.size() * 8), o_effp = place(eff_ptr.size() * 4);
+    size_t o_effs = place(eff_sp.size() * 2), o_effa = place(eff_am1.size() * 8);
+    size_t o_rowb = place(rowbase.size() * 2), o_slot = place(slot.size() * 2);
+    size_t o_effslot = place(effslot.size() * 2), o_rowp = place(m.row_ptr.size() * 4);
+    size_t o_col = place(col16.size() * 2), o_dr = place(dense_rows.size() * 4);
+    std::vector<unsigned char> host(total, 0);
+    auto put = [&](size_t off, const void* src, size_t bytes) { std::memcpy(host.data() + off, src, bytes); };
+    put(o_th, th.data(), th.size() * 8);
+    put(o_tmid, tmid.data(), tmid.size() * 8);
+    put(o_wfac, wfac.data(), wfac.size() * 8);
+    put(o_info, info.data(), info.size() * 4);
+    put(o_sp, sp.data(), sp.size() * 2);
+    put(o_arr, arr.data(), arr.size() * 8);
+    put(o_low, low.data(), low.size() * 8);
+    put(o_troe, troe.data(), troe.size() * 8);
+    put(o_dnu, dnu.data(), dnu.size() * 8);
+    put(o_dom, domega.data(), domega.size() * 8);
+    put(o_effp, eff_ptr.data(), eff_ptr.size() * 4);
+    put(o_effs, eff_sp.data(), eff_sp.size() * 2);
+    put(o_effa, eff_am1.data(), eff_am1.size() * 8);
+    put(o_rowb, rowbase.data(), rowbase.size() * 2);
+    put(o_slot, slot.data(), slot.size() * 2);
+    put(o_effslot, effslot.data(), effslot.size() * 2);
+    put(o_rowp, m.row_ptr.data(), m.row_ptr.size() * 4);
+    put(o_col, col16.data(), col16.size() * 2);
+    put(o_dr, dense_rows.data(), dense_rows.size() * 4);
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { err = "no HIP device"; return PJ_E_DEVICE; }
+    void* d = nullptr;
+    if (hipMalloc(&d, total) != hipSuccess) { err = "hipMalloc of the mechanism tables failed"; return PJ_E_DEVICE; }
+    if (hipMemcpy(d, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        err = "copy of the mechanism tables failed";
+        return PJ_E_DEVICE;
+    }
+    m.device = dev;
+    m.dbuf = d;
+    auto P = [&](size_t off) { return (const void*)((const unsigned char*)d + off); };
+    DevMech& dm = m.dm;
+    dm.ns = ns;
+    dm.nr = nr;
+    dm.nr_pad = nr_pad;
+    dm.N = N;
+    dm.nnz = m.nnz;
+    dm.n_dense_rows = dense_rows[0] < 0 ? 0 : (int)dense_rows.size();
+    dm.bath = bath;
+    dm.th = (const double*)P(o_th);
+    dm.tmid = (const double*)P(o_tmid);
+    dm.wfac = (const double*)P(o_wfac);
+    dm.info = (const uint32_t*)P(o_info);
+    dm.sp = (const uint16_t*)P(o_sp);
+    dm.arr = (const double*)P(o_arr);
+    dm.low = (const double*)P(o_low);
+    dm.troe = (const double*)P(o_troe);
+    dm.dnu = (const double*)P(o_dnu);
+    dm.domega = (const double*)P(o_dom);
+    dm.eff_ptr = (const int32_t*)P(o_effp);
+    dm.eff_sp = (const uint16_t*)P(o_effs);
+    dm.eff_am1 = (const double*)P(o_effa);
+    dm.rowbase = (const uint16_t*)P(o_rowb);
+    dm.slot = (const uint16_t*)P(o_slot);
+    dm.effslot = (const uint16_t*)P(o_effslot);
+    dm.row_ptr = (const int32_t*)P(o_rowp);
+    dm.col_idx = (const uint16_t*)P(o_col);
+    dm.dense_rows = (const int32_t*)P(o_dr);
+
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        lds_max = 65536;
+    m.lds_max = lds_max;
+    m.lds_src = lds_bytes(dm, MODE_SRC);
+    m.lds_jac = lds_bytes(dm, MODE_SPARSE);
+    m.lds_dense = lds_bytes(dm, MODE_DENSE);
+    if (m.lds_src > lds_max) { err = "source-term working set exceeds the LDS of one workgroup"; return PJ_E_UNSUPPORTED; }
+    return PJ_OK;
+}
+
+}  // namespace pj

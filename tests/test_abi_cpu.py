@@ -1,0 +1,129 @@
+"""C-ABI contract on the host (no GPU): symbols, host-side mechanism
+compilation (pattern) and error paths."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_01029_amd import synth
+from conftest import TINY_SEEDS, tiny_file, workload_file
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pjac.h")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1809_01029_amd import api as a
+    return a
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pj_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(api):
+    lib = api.library()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("name", list(synth.WORKLOADS))
+def test_pattern_matches_oracle_workloads(api, name, mech_dir):
+    m, path = workload_file(name, mech_dir)
+    mech = api.Mechanism(path, upload=False)
+    assert mech.n_species == m.n_species and mech.n_reactions == m.n_reactions
+    assert mech.N == m.n_species + 1
+    np.testing.assert_array_equal(mech.pattern_dense(), oracle.Oracle(path).pattern())
+    rp, ci = mech.row_ptr, mech.col_idx
+    assert rp[0] == 0 and rp[-1] == mech.nnz and np.all(np.diff(rp) > 0)
+    for i in range(mech.N):
+        assert np.all(np.diff(ci[rp[i]:rp[i + 1]]) > 0)
+
+
+@pytest.mark.parametrize("seed", TINY_SEEDS)
+@pytest.mark.parametrize("bath", [False, True])
+def test_pattern_matches_oracle_tiny(api, seed, bath, mech_dir):
+    kw = dict(bath_reactions=1, bath_efficiency=True) if bath else {}
+    m, path = tiny_file(seed, mech_dir, **kw)
+    mech = api.Mechanism(path, upload=False)
+    np.testing.assert_array_equal(mech.pattern_dense(), oracle.Oracle(path).pattern())
+
+
+def _write(tmp_path, text, name="m.pjm"):
+    p = tmp_path / name
+    p.write_text(text)
+    return str(p)
+
+
+def _status(api, path):
+    h = ctypes.c_void_p()
+    st = api.library().pj_mech_parse(os.fsencode(path), ctypes.byref(h))
+    if st == 0:
+        api.library().pj_mech_free(h)
+    else:
+        assert not h.value
+    return st
+
+
+def test_error_paths(api, tmp_path):
+    lib = api.library()
+    assert _status(api, str(tmp_path / "missing.pjm")) == 1          # PJ_E_INVALID
+    assert _status(api, _write(tmp_path, "hello world")) == 2         # PJ_E_PARSE
+    m = synth.make_mechanism(7, 10, 3, mix=synth.MixSpec(0.1, 0.2, 0.2), zipf=0.5)
+    good = synth.dumps(m)
+    assert _status(api, _write(tmp_path, good)) == 0
+    assert _status(api, _write(tmp_path, good.replace("END", ""))) == 2
+    # break the element balance of one reaction: change a product species
+    bad = synth.loads(good)
+    r = bad.reactions[0]
+    sp, nu = r.prod[0]
+    other = next(k for k in range(bad.n_species) if not np.array_equal(bad.comp[k], bad.comp[sp])
+                 and k not in [s for s, _ in r.reac + r.prod])
+    r.prod[0] = (other, nu)
+    assert _status(api, _write(tmp_path, synth.dumps(bad))) == 3      # PJ_E_UNBALANCED
+    # a species on both sides is outside what the kernels accept
+    # (adding one species to both sides keeps the balance)
+    both = synth.loads(good)
+    r = next(r for r in both.reactions if len(r.reac) < 3 and len(r.prod) < 3)
+    x = next(k for k in range(both.n_species) if k not in [s for s, _ in r.reac + r.prod])
+    r.reac = r.reac + [(x, 1)]
+    r.prod = r.prod + [(x, 1)]
+    assert _status(api, _write(tmp_path, synth.dumps(both))) == 6      # PJ_E_UNSUPPORTED
+    # NULL handling
+    assert lib.pj_mech_n_species(None) == -1
+    assert lib.pj_mech_state_size(None) == -1
+    lib.pj_mech_free(None)
+    h = ctypes.c_void_p()
+    assert lib.pj_mech_load(None, ctypes.byref(h)) == 1
+    assert lib.pj_mech_parse(os.fsencode(_write(tmp_path, good)), None) == 1
+
+
+def test_eval_argument_checks_without_device(api, tmp_path):
+    lib = api.library()
+    m = synth.make_mechanism(7, 10, 3, mix=synth.MixSpec(0.1, 0.2, 0.2), zipf=0.5)
+    mech = api.Mechanism(_write(tmp_path, synth.dumps(m)), upload=False)
+    dummy = ctypes.c_void_p(16)
+    # n_states == 0 is a no-op
+    assert lib.pj_eval_source(mech.handle, 0, 0, 0, None, None, None, None) == 0
+    # negative n, bad enums, NULL pointers, NULL handle, not uploaded
+    assert lib.pj_eval_source(mech.handle, 0, 0, -1, dummy, dummy, dummy, None) == 1
+    assert lib.pj_eval_source(mech.handle, 2, 0, 1, dummy, dummy, dummy, None) == 1
+    assert lib.pj_eval_source(mech.handle, 0, 5, 1, dummy, dummy, dummy, None) == 1
+    assert lib.pj_eval_source(mech.handle, 0, 0, 1, None, dummy, dummy, None) == 1
+    assert lib.pj_eval_source(None, 0, 0, 1, dummy, dummy, dummy, None) == 1
+    assert lib.pj_eval_jacobian_sparse(mech.handle, 0, 0, 1, dummy, dummy, None, None, None) == 1
+    assert lib.pj_eval_jacobian_dense(mech.handle, 0, 0, 1, dummy, dummy, None, None, None) == 1
+    assert lib.pj_eval_source(mech.handle, 0, 0, 1, dummy, dummy, dummy, None) == 1
+    assert b"not uploaded" in lib.pj_last_error()
+    assert lib.pj_mech_set_waves_per_state(mech.handle, 3) == 1
+    assert lib.pj_mech_set_waves_per_state(mech.handle, 2) == 0
+    assert lib.pj_mech_waves_per_state(mech.handle, 0) == 2
+    assert lib.pj_mech_set_waves_per_state(mech.handle, 0) == 0

@@ -1,0 +1,217 @@
+"""Parity of the HIP path with the CPU oracle, through the C-ABI.
+
+Gates (element by element, on the same seeded inputs):
+  source terms   |gpu - oracle| <= 1e-10 * s
+  Jacobian       |gpu - oracle| <= 1e-8  * s_J + 1e-20
+where s is the oracle's absolute-term scale of that entry (|value| when the
+entry's sum does not cancel; larger by the amount it cancels).  Dense output
+equals the sparse output on the pattern and is exactly zero off it.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_01029_amd import synth
+from conftest import TINY_SEEDS, tiny_file, workload_file
+
+pytestmark = pytest.mark.gpu
+
+SRC_TOL = 1e-10
+JAC_TOL = 1e-8
+JAC_ABS = 1e-20
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def api(torch_cuda):
+    from paper_1809_01029_amd import api as a
+    return a
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(torch, x_c, p, layout):
+    x = x_c if layout == "C" else np.ascontiguousarray(x_c.T)
+    return (torch.from_numpy(np.ascontiguousarray(x)).cuda(), torch.from_numpy(p.copy()).cuda())
+
+
+def src_to_c(a, layout):
+    a = a.cpu().numpy()
+    return a if layout == "C" else a.T
+
+
+def check_source(g, o, s, what):
+    err = np.abs(g - o)
+    bad = err > SRC_TOL * s
+    assert not bad.any(), f"{what}: {int(bad.sum())} source entries outside the gate, " \
+                          f"worst ratio {float(np.max(err / np.maximum(s, 1e-300))):.3e}"
+
+
+def check_jac(g, o, s, what):
+    err = np.abs(g - o)
+    bad = err > JAC_TOL * s + JAC_ABS
+    assert not bad.any(), f"{what}: {int(bad.sum())} Jacobian entries outside the gate, " \
+                          f"worst ratio {float(np.max(err / (JAC_TOL * s + JAC_ABS))):.3e}"
+
+
+def run_case(torch, api, path, x_c, p, form, layout, dense=True, sample=None):
+    """Evaluate on the GPU and compare with the oracle on all states (or the
+    ``sample`` indices)."""
+    o = oracle.Oracle(path)
+    mech = api.load_mechanism(path)
+    n = x_c.shape[0]
+    note(f"case {path} n={n} form={form} layout={layout}")
+    xs, ps = to_dev(torch, x_c, p, layout)
+    f_g = api.eval_source(mech, xs, ps, form, layout)
+    d2 = torch.empty_like(xs)
+    j_g = api.eval_jacobian_sparse(mech, xs, ps, form, layout, dstate=d2)
+    jd_g = api.eval_jacobian_dense(mech, xs, ps, form, layout) if dense else None
+    torch.cuda.synchronize()
+    idx = np.arange(n) if sample is None else np.asarray(sample)
+    f_o, f_s = o.source(x_c[idx], p[idx], form, scale=True)
+    J_o, J_s = o.jacobian(x_c[idx], p[idx], form, scale=True)
+    f_gc = src_to_c(f_g, layout)[idx]
+    check_source(f_gc, f_o, f_s, "pj_eval_source")
+    # the fused source output of the Jacobian call meets the same gate
+    check_source(src_to_c(d2, layout)[idx], f_o, f_s, "pj_eval_jacobian_sparse (source terms)")
+    vals = j_g.cpu().numpy()
+    Jg = api.sparse_to_dense(mech, vals[:, idx] if layout == "F" else vals[idx], layout)
+    check_jac(Jg, J_o, J_s, "pj_eval_jacobian_sparse")
+    # nothing outside the pattern in the oracle either
+    P = mech.pattern_dense()
+    assert np.all(J_o[:, ~P] == 0)
+    if dense:
+        Jd = api.dense_as_sij(jd_g, layout).cpu().numpy()[idx]
+        check_jac(Jd, J_o, J_s, "pj_eval_jacobian_dense")
+        assert np.all(Jd[:, ~P] == 0.0)
+        if mech.waves_per_state(True) == 1:
+            # one wave per state accumulates in program order: same bits as the sparse call
+            np.testing.assert_array_equal(Jd, Jg)
+    return mech
+
+
+@pytest.mark.parametrize("layout", ["F", "C"])
+@pytest.mark.parametrize("form", ["conp", "conv"])
+@pytest.mark.parametrize("seed", TINY_SEEDS)
+@pytest.mark.parametrize("bath", [False, True])
+def test_tiny_mechanisms(torch_cuda, api, seed, bath, form, layout, mech_dir):
+    kw = dict(bath_reactions=1, bath_efficiency=True) if bath else {}
+    m, path = tiny_file(seed, mech_dir, **kw)
+    st = synth.make_states(m, 37, 100 + seed)
+    x, p = synth.pack_state(st, form, "C")
+    run_case(torch_cuda, api, path, x, p, form, layout)
+
+
+@pytest.mark.parametrize("layout", ["F", "C"])
+@pytest.mark.parametrize("form", ["conp", "conv"])
+def test_ns13_full_workload(torch_cuda, api, form, layout, mech_dir):
+    # the 13-species configuration at its full size (1024 states), every state
+    m, path = workload_file("ns13", mech_dir)
+    w = synth.WORKLOADS["ns13"]
+    st = synth.make_states(m, w.n_states, w.state_seed, T_range=w.T_range, P_range_atm=w.P_range_atm)
+    x, p = synth.pack_state(st, form, "C")
+    run_case(torch_cuda, api, path, x, p, form, layout)
+
+
+@pytest.mark.parametrize("layout", ["F", "C"])
+@pytest.mark.parametrize("form", ["conp", "conv"])
+@pytest.mark.parametrize("name,n", [("ns53", 96), ("ns111", 70), ("ns360", 6)])
+def test_larger_mechanisms(torch_cuda, api, name, n, form, layout, mech_dir):
+    m, path = workload_file(name, mech_dir)
+    w = synth.WORKLOADS[name]
+    st = synth.make_states(m, n, w.state_seed + 7, T_range=w.T_range, P_range_atm=w.P_range_atm)
+    x, p = synth.pack_state(st, form, "C")
+    run_case(torch_cuda, api, path, x, p, form, layout, dense=(name != "ns360" or layout == "C"))
+
+
+def test_waves_per_state_variants_agree(torch_cuda, api, mech_dir):
+    torch = torch_cuda
+    m, path = workload_file("ns111", mech_dir)
+    st = synth.make_states(m, 50, 5)
+    x, p = synth.pack_state(st, "conp", "F")
+    o = oracle.Oracle(path)
+    xc, pc = synth.pack_state(st, "conp", "C")
+    J_o, J_s = o.jacobian(xc, pc, "conp", scale=True)
+    f_o, f_s = o.source(xc, pc, "conp", scale=True)
+    mech = api.load_mechanism(path)
+    xs, ps = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda()
+    for wps in (1, 2, 4):
+        note(f"waves_per_state={wps}")
+        mech.set_waves_per_state(wps)
+        f = api.eval_source(mech, xs, ps, "conp", "F")
+        j = api.eval_jacobian_sparse(mech, xs, ps, "conp", "F")
+        torch.cuda.synchronize()
+        check_source(f.cpu().numpy().T, f_o, f_s, f"wps={wps}")
+        check_jac(api.sparse_to_dense(mech, j.cpu().numpy(), "F"), J_o, J_s, f"wps={wps}")
+
+
+def test_one_wave_per_state_is_bitwise_reproducible(torch_cuda, api, mech_dir):
+    torch = torch_cuda
+    m, path = workload_file("ns53", mech_dir)
+    st = synth.make_states(m, 500, 11)
+    x, p = synth.pack_state(st, "conv", "C")
+    mech = api.load_mechanism(path)
+    mech.set_waves_per_state(1)
+    xs, ps = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda()
+    a = api.eval_jacobian_sparse(mech, xs, ps, "conv", "C")
+    b = api.eval_jacobian_sparse(mech, xs, ps, "conv", "C")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_edge_sizes(torch_cuda, api, mech_dir):
+    torch = torch_cuda
+    m, path = workload_file("ns13", mech_dir)
+    mech = api.load_mechanism(path)
+    o = oracle.Oracle(path)
+    # zero states: no-op
+    e = torch.empty((mech.N, 0), dtype=torch.float64, device="cuda")
+    api.eval_source(mech, e, torch.empty(0, dtype=torch.float64, device="cuda"), "conp", "F")
+    for n in (1, 2, 63, 65, 1001):
+        st = synth.make_states(m, n, 1000 + n)
+        x, p = synth.pack_state(st, "conp", "C")
+        note(f"edge n={n}")
+        xs, ps = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda()
+        f = api.eval_source(mech, xs, ps, "conp", "C")
+        torch.cuda.synchronize()
+        f_o, f_s = o.source(x, p, "conp", scale=True)
+        check_source(f.cpu().numpy(), f_o, f_s, f"n={n}")
+
+
+def test_bench_configuration_sampled(torch_cuda, api, mech_dir):
+    """The 111-species configuration at full size (262,144 states, CONP,
+    layout F, fused source + sparse Jacobian, the launch the benchmark times),
+    checked on sampled states."""
+    torch = torch_cuda
+    m, path = workload_file("ns111", mech_dir)
+    w = synth.WORKLOADS["ns111"]
+    st = synth.make_states(m, w.n_states, w.state_seed, T_range=w.T_range, P_range_atm=w.P_range_atm)
+    x, p = synth.pack_state(st, "conp", "F")
+    mech = api.load_mechanism(path)
+    xs, ps = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda()
+    d = torch.empty_like(xs)
+    note("bench configuration: 262144 states")
+    j = api.eval_jacobian_sparse(mech, xs, ps, "conp", "F", dstate=d)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2024)
+    idx = np.sort(np.concatenate([rng.choice(w.n_states, 40, replace=False), [0, w.n_states - 1]]))
+    xc = np.ascontiguousarray(x[:, idx].T)
+    o = oracle.Oracle(path)
+    f_o, f_s = o.source(xc, p[idx], "conp", scale=True)
+    J_o, J_s = o.jacobian(xc, p[idx], "conp", scale=True)
+    check_source(d[:, idx].cpu().numpy().T, f_o, f_s, "bench sample")
+    vals = j[:, idx].cpu().numpy()
+    check_jac(api.sparse_to_dense(mech, vals, "F"), J_o, J_s, "bench sample")
+    assert torch.isfinite(j).all() and torch.isfinite(d).all()
