@@ -30,44 +30,63 @@ constexpr uint32_t INFO_BATH = 1u << 27;
 __host__ __device__ inline int info_nu(uint32_t w, int a) { return (w >> (4 * a)) & 0xF; }
 __host__ __device__ inline int info_kind(uint32_t w) { return (w >> 24) & 0x3; }
 
-// Device tables of one mechanism.  Per-reaction arrays are indexed by the
-// reaction's position in the kernel order (sorted by kind) and padded to a
-// multiple of 64; "[a][i]" arrays are slot-major so that consecutive lanes
-// (consecutive reactions) read consecutive words.
+// Per-reaction device records, in the kernel order (sorted by kind) and
+// padded to a multiple of 64 reactions.  Each record is 16-byte aligned and
+// read with 16-byte vector loads.
+struct alignas(16) RxnRec {          // 80 B
+    uint32_t info;                   // see INFO_* above
+    uint32_t eff0, eff1;             // this reaction's range in the efficiency list
+    uint32_t pad0;
+    uint16_t sp[6];                  // species of slot a (Ns = empty slot)
+    uint16_t pad1[2];
+    double lnA, b, theta;            // Arrhenius (k_inf for falloff)
+    double dnu;                      // sum of net coefficients
+    double domega;                   // sum_{k<Ns} nu_ki (1 - W_k/W_Ns)
+    double pad2;
+};
+struct alignas(16) FallRec {         // 64 B, falloff reactions
+    double lnA0, b0, theta0;         // low-pressure limit
+    double alpha, inv_t3, inv_t1, t2;// Troe: alpha, 1/T***, 1/T*, T**
+    double pad;
+};
+struct alignas(16) JacRec {          // 96 B, Jacobian scatter slots (NOSLOT = none)
+    uint16_t rowbase[6];             // CSR start of the row of slot a's species
+    uint16_t pad0[2];
+    uint16_t slot[36];               // CSR slot of (row of slot a, column of slot b), [a*6+b]
+    uint16_t pad1[4];
+};
+static_assert(sizeof(RxnRec) == 80 && sizeof(FallRec) == 64 && sizeof(JacRec) == 96, "record sizes");
+
+// Thermodynamic coefficients of one species and one temperature range.
+constexpr int TH_N = 18;
+struct alignas(16) ThermoRec {       // 144 B
+    double c[TH_N];
+};
+
 struct DevMech {
     int ns, nr, nr_pad, N;
     int nnz;            // CSR non-zeros
     int n_dense_rows;   // species rows made dense by bath-gas dependent rates
     int bath;           // ns - 1
 
-    // species (Ns entries, index k)
-    const double* th;   // [2 ranges][TH_N coefficients][ns]
-    const double* tmid; // [ns]
-    const double* wfac; // [ns] 1 - W_k / W_Ns (0 for the bath gas)
+    // species
+    const ThermoRec* th;      // [ns][2] (low range, high range)
+    const double* tmid;       // [ns]
+    const double* wfac;       // [ns] 1 - W_k / W_Ns (0 for the bath gas)
 
     // reactions
-    const uint32_t* info;     // [nr_pad]
-    const uint16_t* sp;       // [6][nr_pad] species of slot a (ns = empty)
-    const double* arr;        // [3][nr_pad] lnA, b, Ea/R
-    const double* low;        // [3][nr_pad] lnA0, b0, Ea0/R (falloff)
-    const double* troe;       // [4][nr_pad] alpha, 1/T***, 1/T*, T**
-    const double* dnu;        // [nr_pad] sum of net coefficients
-    const double* domega;     // [nr_pad] sum_{k<Ns} nu_ki (1 - W_k/W_Ns)
-    const int32_t* eff_ptr;   // [nr_pad + 1]
+    const RxnRec* rec;        // [nr_pad]
+    const FallRec* fall;      // [nr_pad]
+    const JacRec* jrec;       // [nr_pad]
     const uint16_t* eff_sp;   // [n_eff]
     const double* eff_am1;    // [n_eff] efficiency - 1
-
-    // Jacobian scatter tables (CSR slots; NOSLOT = none)
-    const uint16_t* rowbase;  // [6][nr_pad] row_ptr of the row of slot a's species
-    const uint16_t* slot;     // [36][nr_pad] slot (row of slot a, column of slot b)
     const uint16_t* effslot;  // [n_eff][6] slot (row of slot a, column of the third body)
+
+    // pattern
     const int32_t* row_ptr;   // [N + 1]
     const uint16_t* col_idx;  // [nnz]
     const int32_t* dense_rows;// [n_dense_rows] species index k of bath-dense rows
 };
-
-// Thermodynamic coefficient rows per range (see mech.cpp for the layout).
-constexpr int TH_N = 18;
 
 struct Mechanism {
     // host copy of the description

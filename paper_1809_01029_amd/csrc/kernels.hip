@@ -107,6 +107,20 @@ __device__ inline dd block_dd_sum(dd a, double* red, int wave, int nwave) {
     return t;
 }
 
+// 16-byte vector loads of a table record
+template <class T>
+__device__ inline T load_rec(const T* src) {
+    static_assert(sizeof(T) % 16 == 0, "record size");
+    union U {
+        T t;
+        uint4 v[sizeof(T) / 16];
+    } u;
+    const uint4* q = reinterpret_cast<const uint4*>(src);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 16); ++i) u.v[i] = q[i];
+    return u.t;
+}
+
 __device__ inline double cpow(double c, int nu) {
     // c^nu for nu in 0..3
     return nu == 0 ? 1.0 : nu == 1 ? c : nu == 2 ? c * c : c * c * c;
@@ -133,7 +147,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                                                   double* __restrict__ jac) {
     extern __shared__ double lds[];
     constexpr bool JAC = MODE != MODE_SRC;
-    const int ns = dm.ns, N = dm.N, bath = dm.bath, nrp = dm.nr_pad, nnz = dm.nnz;
+    const int ns = dm.ns, N = dm.N, bath = dm.bath, nnz = dm.nnz;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, nwave = nthr >> 6;
 
@@ -149,7 +163,18 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
     double* SQ = TQ + (ns + 1);
     double* ROW = SQ + (ns + 1);
 
-    for (long s = blockIdx.x; s < n; s += gridDim.x) {
+    // Consecutive states go to workgroups of the same XCD (workgroups are
+    // handed to the 8 XCDs round-robin), so that the partial cache lines of
+    // layout-F arrays of neighbouring states meet in one L2: XCD x takes the
+    // contiguous state range [n x/8, n (x+1)/8) in increasing order.
+    long s0 = blockIdx.x, s1 = n, sstep = gridDim.x;
+    if (gridDim.x >= 8 && (gridDim.x & 7) == 0) {
+        const long x = blockIdx.x & 7;
+        s0 = n * x / 8 + (blockIdx.x >> 3);
+        s1 = n * (x + 1) / 8;
+        sstep = gridDim.x >> 3;
+    }
+    for (long s = s0; s < s1; s += sstep) {
         auto X = [&](int i) -> double {
             return LAYOUT == PJ_LAYOUT_F ? state[(long)i * n + s] : state[s * (long)N + i];
         };
@@ -196,8 +221,8 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
         double tsum[2] = {0.0, 0.0};   // D' = sum C chat/R, dD'/dT = sum C dCp/R/dT
         for (int k = tid; k < ns; k += nthr) {
             const int rg = T < dm.tmid[k] ? 0 : 1;
-            const double* c = dm.th + (size_t)rg * TH_N * ns + k;
-            auto a = [&](int q) { return c[(size_t)q * ns]; };
+            const ThermoRec tr = load_rec(dm.th + 2 * (size_t)k + rg);
+            auto a = [&](int q) { return tr.c[q]; };
             const double a0 = a(0), a1 = a(1);
             double cp = a0 + T * (a1 + T * (a(2) + T * (a(3) + T * a(4))));
             double h = a0 + T * (a(5) + T * (a(6) + T * (a(7) + T * a(8)))) + a(12) * invT;
@@ -218,16 +243,17 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
         // ---- reactions: rates of progress and Jacobian sub-products
         double racc[4] = {0.0, 0.0, 0.0, 0.0};  // TT, TS, ST, SS
         for (int p = tid; p < dm.nr; p += nthr) {
-            const uint32_t w = dm.info[p];
+            const RxnRec rr = load_rec(dm.rec + p);
+            const uint32_t w = rr.info;
             const int kind = info_kind(w);
             const bool rev = (w & INFO_REV) != 0;
             int spc[NSLOT], nu[NSLOT];
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) {
-                spc[a] = dm.sp[(size_t)a * nrp + p];
+                spc[a] = rr.sp[a];
                 nu[a] = info_nu(w, a);
             }
-            const double lnA = dm.arr[p], bexp = dm.arr[nrp + p], th = dm.arr[2 * (size_t)nrp + p];
+            const double lnA = rr.lnA, bexp = rr.b, th = rr.theta;
             const double lnkf = lnA + bexp * lnT - th * invT;
             double dG = 0.0, dH = 0.0;
             double cf[NSLOT];
@@ -238,7 +264,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                 dH += sgn * H[spc[a]];
                 cf[a] = C[spc[a]];
             }
-            const double dnu = dm.dnu[p];
+            const double dnu = rr.dnu;
             const double kf = exp(lnkf);
             double fr[NSLOT];
 #pragma unroll
@@ -253,7 +279,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
 
             // pressure modification
             double c = 1.0, dcdM = 0.0, dcdT = 0.0;
-            const int e0 = dm.eff_ptr[p], e1 = dm.eff_ptr[p + 1];
+            const int e0 = (int)rr.eff0, e1 = (int)rr.eff1;
             if (kind != K_ELEM) {
                 double M = Ctot;
                 for (int e = e0; e < e1; ++e) M += dm.eff_am1[e] * C[dm.eff_sp[e]];
@@ -261,13 +287,13 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                     c = M;
                     dcdM = 1.0;
                 } else {
-                    const double lnk0 = dm.low[p] + dm.low[nrp + p] * lnT - dm.low[2 * (size_t)nrp + p] * invT;
+                    const FallRec fr_ = load_rec(dm.fall + p);
+                    const double lnk0 = fr_.lnA0 + fr_.b0 * lnT - fr_.theta0 * invT;
                     const double rk = exp(lnk0 - lnkf);     // k0 / k_inf
                     const double Pr = M * rk;
                     double F = 1.0, dlF_dlP = 0.0, dlF_dT = 0.0;
                     if (kind == K_TROE) {
-                        const double al = dm.troe[p], i3 = dm.troe[nrp + p];
-                        const double i1 = dm.troe[2 * (size_t)nrp + p], t2 = dm.troe[3 * (size_t)nrp + p];
+                        const double al = fr_.alpha, i3 = fr_.inv_t3, i1 = fr_.inv_t1, t2 = fr_.t2;
                         const double e3 = exp(-T * i3), e1x = exp(-T * i1), e2 = exp(-t2 * invT);
                         const double Fc = (1.0 - al) * e3 + al * e1x + e2;
                         const double L = log10(Fc);
@@ -293,7 +319,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                     if (JAC) {
                         const double dc_dPr = F * ip * ip + F * ip * dlF_dlP;
                         dcdM = dc_dPr * rk;
-                        const double dlnPr = (dm.low[nrp + p] + dm.low[2 * (size_t)nrp + p] * invT) * invT
+                        const double dlnPr = (fr_.b0 + fr_.theta0 * invT) * invT
                                              - (bexp + th * invT) * invT;
                         dcdT = dc_dPr * Pr * dlnPr + c * LN10 * dlF_dT;
                     }
@@ -347,7 +373,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
             const double dqdS = FORM == PJ_CONP ? -(sQC - Qb * (nsum * invV)) * invV
                                                 : (Qb + QM) / (RU * T);
             const double dE = FORM == PJ_CONP ? dH : dH - dnu;
-            const double dOm = dm.domega[p];
+            const double dOm = rr.domega;
             racc[0] += dE * dqdT;
             racc[1] += dE * dqdS;
             racc[2] += dOm * dqdT;
@@ -367,10 +393,11 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                 atomicAdd(&SQ[dm.eff_sp[e]], dOm * qe);
             }
             // species rows
+            const JacRec jr = load_rec(dm.jrec + p);
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) {
                 if (!nu[a]) continue;
-                const uint16_t rb = dm.rowbase[(size_t)a * nrp + p];
+                const uint16_t rb = jr.rowbase[a];
                 if (rb == NOSLOT) continue;
                 const double sgn = a < MAXSIDE ? -(double)nu[a] : (double)nu[a];
                 atomicAdd(&J[rb], V * sgn * dqdT);
@@ -381,7 +408,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                     if (spc[b] == bath) {
                         atomicAdd(&B[spc[a]], sgn * Qs[b]);
                     } else {
-                        atomicAdd(&J[dm.slot[((size_t)a * NSLOT + b) * nrp + p]], sgn * Qs[b]);
+                        atomicAdd(&J[jr.slot[a * NSLOT + b]], sgn * Qs[b]);
                     }
                 }
                 for (int e = e0; e < e1; ++e) {
@@ -506,7 +533,9 @@ static hipError_t launch_t(const DevMech& dm, int64_t n, const double* state, co
         if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
         if (e != hipSuccess) return e;
     }
-    const int64_t grid = n < (1 << 30) ? n : (1 << 30);
+    // one workgroup per state, rounded down to a multiple of 8 (the XCD count)
+    int64_t grid = n < (1 << 30) ? n : (1 << 30);
+    if (grid >= 8) grid &= ~(int64_t)7;
     hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * wps), (size_t)lds, stream, dm, (long)n,
                        state, param, dstate, jac);
     return hipGetLastError();

@@ -242,36 +242,43 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     const int nr_pad = std::max(64, (nr + 63) / 64 * 64);
     const double Wb = m.W[bath];
 
-    // ---- species tables
-    std::vector<double> th((size_t)2 * TH_N * ns, 0.0), tmid(ns), wfac(ns);
+    // ---- species tables.  Coefficient layout of one range (c[]):
+    //   0..4   Cp/R    = c0 + c1 T + c2 T^2 + c3 T^3 + c4 T^4
+    //   5..8   H/RT    = c0 + c5 T + c6 T^2 + c7 T^3 + c8 T^4 + c12 / T
+    //   9..11  S/R     = c0 ln T + c1 T + c9 T^2 + c10 T^3 + c11 T^4 + c13
+    //   14..16 dCp/R/dT = c1 + c14 T + c15 T^2 + c16 T^3
+    std::vector<ThermoRec> th((size_t)ns * 2);
+    std::vector<double> tmid(ns), wfac(ns);
     for (int k = 0; k < ns; ++k) {
         for (int rg = 0; rg < 2; ++rg) {
             const double* a = (rg == 0 ? m.alo.data() : m.ahi.data()) + (size_t)k * 7;
-            double row[TH_N] = {a[0], a[1], a[2], a[3], a[4],                 // Cp/R
-                                a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5,     // H/RT
-                                a[2] / 2, a[3] / 3, a[4] / 4,               // S/R
+            double row[TH_N] = {a[0], a[1], a[2], a[3], a[4],
+                                a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5,
+                                a[2] / 2, a[3] / 3, a[4] / 4,
                                 a[5], a[6],
-                                2 * a[2], 3 * a[3], 4 * a[4],               // dCp/R/dT
+                                2 * a[2], 3 * a[3], 4 * a[4],
                                 0.0};
-            for (int c = 0; c < TH_N; ++c) th[((size_t)rg * TH_N + c) * ns + k] = row[c];
+            for (int c = 0; c < TH_N; ++c) th[(size_t)k * 2 + rg].c[c] = row[c];
         }
         tmid[k] = m.tmid[k];
         wfac[k] = k == bath ? 0.0 : 1.0 - m.W[k] / Wb;
     }
 
-    // ---- reaction tables (kernel order)
-    std::vector<uint32_t> info(nr_pad, 0);
-    std::vector<uint16_t> sp((size_t)NSLOT * nr_pad, (uint16_t)ns);
-    std::vector<double> arr((size_t)3 * nr_pad, 0.0), low((size_t)3 * nr_pad, 0.0),
-        troe((size_t)4 * nr_pad, 0.0), dnu(nr_pad, 0.0), domega(nr_pad, 0.0);
-    std::vector<int32_t> eff_ptr(nr_pad + 1, 0);
+    // ---- reaction records (kernel order)
+    std::vector<RxnRec> rec(nr_pad);
+    std::vector<FallRec> fall(nr_pad);
+    std::vector<JacRec> jrec(nr_pad);
+    std::memset(rec.data(), 0, rec.size() * sizeof(RxnRec));
+    std::memset(fall.data(), 0, fall.size() * sizeof(FallRec));
+    std::memset(jrec.data(), 0xFF, jrec.size() * sizeof(JacRec));
     std::vector<uint16_t> eff_sp;
     std::vector<double> eff_am1;
-    std::vector<uint16_t> rowbase((size_t)NSLOT * nr_pad, NOSLOT), slot((size_t)NSLOT * NSLOT * nr_pad, NOSLOT);
     std::vector<uint16_t> effslot;
     std::vector<char> dense_row(ns, 0);
     for (int p = 0; p < nr_pad; ++p) {
-        eff_ptr[p] = (int32_t)eff_sp.size();
+        RxnRec& R = rec[p];
+        for (int a = 0; a < NSLOT; ++a) R.sp[a] = (uint16_t)ns;
+        R.eff0 = R.eff1 = (uint32_t)eff_sp.size();
         if (p >= nr) continue;
         const auto& r = m.rx[m.order[p]];
         int spa[NSLOT], nua[NSLOT];
@@ -284,42 +291,43 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
         w |= (uint32_t)r.kind << 24;
         if (r.rev) w |= INFO_REV;
         if (bathdep) w |= INFO_BATH;
-        info[p] = w;
+        R.info = w;
         double sumnu = 0, om = 0;
         for (int a = 0; a < NSLOT; ++a) {
-            sp[(size_t)a * nr_pad + p] = (uint16_t)spa[a];
+            R.sp[a] = (uint16_t)spa[a];
             if (!nua[a]) continue;
             double nu = a < 3 ? -nua[a] : nua[a];
             sumnu += nu;
             om += nu * wfac[spa[a]];
         }
-        dnu[p] = sumnu;
-        domega[p] = om;
-        arr[0 * (size_t)nr_pad + p] = r.lnA;
-        arr[1 * (size_t)nr_pad + p] = r.b;
-        arr[2 * (size_t)nr_pad + p] = r.theta;
+        R.dnu = sumnu;
+        R.domega = om;
+        R.lnA = r.lnA;
+        R.b = r.b;
+        R.theta = r.theta;
         if (r.kind == K_LINDEMANN || r.kind == K_TROE) {
-            low[0 * (size_t)nr_pad + p] = r.lnA0;
-            low[1 * (size_t)nr_pad + p] = r.b0;
-            low[2 * (size_t)nr_pad + p] = r.theta0;
+            fall[p].lnA0 = r.lnA0;
+            fall[p].b0 = r.b0;
+            fall[p].theta0 = r.theta0;
         }
         if (r.kind == K_TROE) {
-            troe[0 * (size_t)nr_pad + p] = r.alpha;
-            troe[1 * (size_t)nr_pad + p] = 1.0 / r.T3;
-            troe[2 * (size_t)nr_pad + p] = 1.0 / r.T1;
-            troe[3 * (size_t)nr_pad + p] = r.T2;
+            fall[p].alpha = r.alpha;
+            fall[p].inv_t3 = 1.0 / r.T3;
+            fall[p].inv_t1 = 1.0 / r.T1;
+            fall[p].t2 = r.T2;
         }
         // rows: species of the reaction other than the bath gas
+        JacRec& Jr = jrec[p];
         for (int a = 0; a < NSLOT; ++a) {
             if (!nua[a] || spa[a] == bath) continue;
-            rowbase[(size_t)a * nr_pad + p] = (uint16_t)m.row_ptr[2 + spa[a]];
+            Jr.rowbase[a] = (uint16_t)m.row_ptr[2 + spa[a]];
             if (bathdep) dense_row[spa[a]] = 1;
             for (int b = 0; b < NSLOT; ++b) {
                 bool dep = nua[b] && (b < 3 || r.rev) && spa[b] != bath;
                 if (!dep) continue;
-                int s = csr_find(m, 2 + spa[a], 2 + spa[b]);
-                if (s < 0) { err = "internal: pattern misses a reaction entry"; return PJ_E_UNSUPPORTED; }
-                slot[((size_t)a * NSLOT + b) * nr_pad + p] = (uint16_t)s;
+                int sl = csr_find(m, 2 + spa[a], 2 + spa[b]);
+                if (sl < 0) { err = "internal: pattern misses a reaction entry"; return PJ_E_UNSUPPORTED; }
+                Jr.slot[a * NSLOT + b] = (uint16_t)sl;
             }
         }
         if (r.kind != K_ELEM) {
@@ -327,52 +335,46 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
                 eff_sp.push_back((uint16_t)e.first);
                 eff_am1.push_back(e.second - 1.0);
                 for (int a = 0; a < NSLOT; ++a) {
-                    uint16_t s = NOSLOT;
+                    uint16_t sl = NOSLOT;
                     if (nua[a] && spa[a] != bath && e.first != bath) {
                         int f = csr_find(m, 2 + spa[a], 2 + e.first);
                         if (f < 0) { err = "internal: pattern misses a third-body entry"; return PJ_E_UNSUPPORTED; }
-                        s = (uint16_t)f;
+                        sl = (uint16_t)f;
                     }
-                    effslot.push_back(s);
+                    effslot.push_back(sl);
                 }
             }
         }
+        R.eff1 = (uint32_t)eff_sp.size();
     }
-    eff_ptr[nr_pad] = (int32_t)eff_sp.size();
     std::vector<int32_t> dense_rows;
     for (int k = 0; k < ns; ++k) if (dense_row[k]) dense_rows.push_back(k);
     std::vector<uint16_t> col16(m.col_idx.begin(), m.col_idx.end());
     if (eff_sp.empty()) { eff_sp.push_back(0); eff_am1.push_back(0.0); effslot.assign(NSLOT, NOSLOT); }
+    const int n_dense = (int)dense_rows.size();
     if (dense_rows.empty()) dense_rows.push_back(-1);
 
     // ---- one device buffer
     size_t total = 0;
     auto place = [&](size_t bytes) { size_t o = (total + 255) / 256 * 256; total = o + bytes; return o; };
-    size_t o_th = place(th.size() * 8), o_tmid = place(tmid.size() * 8), o_wfac = place(wfac.size() * 8);
-    size_t o_info = place(info.size() * 4), o_sp = place(sp.size() * 2), o_arr = place(arr.size() * 8);
-    size_t o_low = place(low.size() * 8), o_troe = place(troe.size() * 8), o_dnu = place(dnu.size() * 8);
-    size_t o_dom = place(domega.size() * 8), o_effp = place(eff_ptr.size() * 4);
-    size_t o_effs = place(eff_sp.size() * 2), o_effa = place(eff_am1.size() * 8);
-    size_t o_rowb = place(rowbase.size() * 2), o_slot = place(slot.size() * 2);
-    size_t o_effslot = place(effslot.size() * 2), o_rowp = place(m.row_ptr.size() * 4);
-    size_t o_col = place(col16.size() * 2), o_dr = place(dense_rows.size() * 4);
+    size_t o_th = place(th.size() * sizeof(ThermoRec)), o_tmid = place(tmid.size() * 8),
+           o_wfac = place(wfac.size() * 8);
+    size_t o_rec = place(rec.size() * sizeof(RxnRec)), o_fall = place(fall.size() * sizeof(FallRec)),
+           o_jrec = place(jrec.size() * sizeof(JacRec));
+    size_t o_effs = place(eff_sp.size() * 2), o_effa = place(eff_am1.size() * 8),
+           o_effslot = place(effslot.size() * 2);
+    size_t o_rowp = place(m.row_ptr.size() * 4), o_col = place(col16.size() * 2),
+           o_dr = place(dense_rows.size() * 4);
     std::vector<unsigned char> host(total, 0);
     auto put = [&](size_t off, const void* src, size_t bytes) { std::memcpy(host.data() + off, src, bytes); };
-    put(o_th, th.data(), th.size() * 8);
+    put(o_th, th.data(), th.size() * sizeof(ThermoRec));
     put(o_tmid, tmid.data(), tmid.size() * 8);
     put(o_wfac, wfac.data(), wfac.size() * 8);
-    put(o_info, info.data(), info.size() * 4);
-    put(o_sp, sp.data(), sp.size() * 2);
-    put(o_arr, arr.data(), arr.size() * 8);
-    put(o_low, low.data(), low.size() * 8);
-    put(o_troe, troe.data(), troe.size() * 8);
-    put(o_dnu, dnu.data(), dnu.size() * 8);
-    put(o_dom, domega.data(), domega.size() * 8);
-    put(o_effp, eff_ptr.data(), eff_ptr.size() * 4);
+    put(o_rec, rec.data(), rec.size() * sizeof(RxnRec));
+    put(o_fall, fall.data(), fall.size() * sizeof(FallRec));
+    put(o_jrec, jrec.data(), jrec.size() * sizeof(JacRec));
     put(o_effs, eff_sp.data(), eff_sp.size() * 2);
     put(o_effa, eff_am1.data(), eff_am1.size() * 8);
-    put(o_rowb, rowbase.data(), rowbase.size() * 2);
-    put(o_slot, slot.data(), slot.size() * 2);
     put(o_effslot, effslot.data(), effslot.size() * 2);
     put(o_rowp, m.row_ptr.data(), m.row_ptr.size() * 4);
     put(o_col, col16.data(), col16.size() * 2);
@@ -396,23 +398,16 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.nr_pad = nr_pad;
     dm.N = N;
     dm.nnz = m.nnz;
-    dm.n_dense_rows = dense_rows[0] < 0 ? 0 : (int)dense_rows.size();
+    dm.n_dense_rows = n_dense;
     dm.bath = bath;
-    dm.th = (const double*)P(o_th);
+    dm.th = (const ThermoRec*)P(o_th);
     dm.tmid = (const double*)P(o_tmid);
     dm.wfac = (const double*)P(o_wfac);
-    dm.info = (const uint32_t*)P(o_info);
-    dm.sp = (const uint16_t*)P(o_sp);
-    dm.arr = (const double*)P(o_arr);
-    dm.low = (const double*)P(o_low);
-    dm.troe = (const double*)P(o_troe);
-    dm.dnu = (const double*)P(o_dnu);
-    dm.domega = (const double*)P(o_dom);
-    dm.eff_ptr = (const int32_t*)P(o_effp);
+    dm.rec = (const RxnRec*)P(o_rec);
+    dm.fall = (const FallRec*)P(o_fall);
+    dm.jrec = (const JacRec*)P(o_jrec);
     dm.eff_sp = (const uint16_t*)P(o_effs);
     dm.eff_am1 = (const double*)P(o_effa);
-    dm.rowbase = (const uint16_t*)P(o_rowb);
-    dm.slot = (const uint16_t*)P(o_slot);
     dm.effslot = (const uint16_t*)P(o_effslot);
     dm.row_ptr = (const int32_t*)P(o_rowp);
     dm.col_idx = (const uint16_t*)P(o_col);
