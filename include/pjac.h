@@ -80,7 +80,7 @@ typedef enum {
  * device.  Synchronous.  On success *out receives a handle; on failure *out is
  * NULL and the status says why.
  * Limits (PJ_E_UNSUPPORTED beyond them): at most 3 distinct species per
- * reaction side, coefficients 1..3, at most 65534 Jacobian non-zeros, and the
+ * reaction side, coefficients 1..2, at most 65534 Jacobian non-zeros, and the
  * per-state working set must fit the device's LDS per workgroup.
  */
 pj_status pj_mech_load(const char* desc_path, pj_mech** out);

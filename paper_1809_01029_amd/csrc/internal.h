@@ -25,8 +25,10 @@ enum RxnKind : int { K_ELEM = 0, K_THREEBODY = 1, K_LINDEMANN = 2, K_TROE = 3 };
 //   bits 24..25: kind (RxnKind)
 //   bit  26    : reversible
 //   bit  27    : the rate depends on the bath-gas concentration
+//   bit  28    : the bath gas has a non-zero coefficient
 constexpr uint32_t INFO_REV = 1u << 26;
 constexpr uint32_t INFO_BATH = 1u << 27;
+constexpr uint32_t INFO_BATHROW = 1u << 28;
 __host__ __device__ inline int info_nu(uint32_t w, int a) { return (w >> (4 * a)) & 0xF; }
 __host__ __device__ inline int info_kind(uint32_t w) { return (w >> 24) & 0x3; }
 
@@ -86,6 +88,8 @@ struct DevMech {
     const int32_t* row_ptr;   // [N + 1]
     const uint16_t* col_idx;  // [nnz]
     const int32_t* dense_rows;// [n_dense_rows] species index k of bath-dense rows
+    const uint32_t* chunk;    // [nr_pad / 64] slot positions used in the chunk (bits 0..5),
+                              // any reversible (bit 6), any third body (bit 7)
 };
 
 struct Mechanism {

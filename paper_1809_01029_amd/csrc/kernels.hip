@@ -121,13 +121,11 @@ __device__ inline T load_rec(const T* src) {
     return u.t;
 }
 
-__device__ inline double cpow(double c, int nu) {
-    // c^nu for nu in 0..3
-    return nu == 0 ? 1.0 : nu == 1 ? c : nu == 2 ? c * c : c * c * c;
-}
-__device__ inline double dcpow(double c, int nu) {
-    // d(c^nu)/dc for nu in 0..3
-    return nu == 0 ? 0.0 : nu == 1 ? 1.0 : nu == 2 ? 2.0 * c : 3.0 * c * c;
+// c^nu and d(c^nu)/dc for nu in {0, 1, 2} with selects instead of branches;
+// an empty slot (nu = 0) reads the sentinel concentration 1, giving f = 1
+__device__ inline void powd(double c, int nu, double& f, double& d) {
+    f = nu == 2 ? c * c : c;
+    d = nu == 2 ? 2.0 * c : (double)nu;
 }
 
 }  // namespace
@@ -216,6 +214,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
         const double lnT = log(T);
         const double Ctot = P / (RU * T);
         const double lnP0RT = log(PREF / (RU * T));
+        const double invRT = 1.0 / (RU * T);
 
         // ---- species thermodynamics (NASA-7)
         double tsum[2] = {0.0, 0.0};   // D' = sum C chat/R, dD'/dT = sum C dCp/R/dT
@@ -243,6 +242,10 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
         // ---- reactions: rates of progress and Jacobian sub-products
         double racc[4] = {0.0, 0.0, 0.0, 0.0};  // TT, TS, ST, SS
         for (int p = tid; p < dm.nr; p += nthr) {
+            // positions any reaction of this 64-reaction chunk uses (uniform
+            // over the wave: a wave's lanes take 64 consecutive reactions)
+            const uint32_t cmask = __builtin_amdgcn_readfirstlane(dm.chunk[p >> 6]);
+            const bool any_rev = (cmask >> 6) & 1;
             const RxnRec rr = load_rec(dm.rec + p);
             const uint32_t w = rr.info;
             const int kind = info_kind(w);
@@ -256,19 +259,17 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
             const double lnA = rr.lnA, bexp = rr.b, th = rr.theta;
             const double lnkf = lnA + bexp * lnT - th * invT;
             double dG = 0.0, dH = 0.0;
-            double cf[NSLOT];
+            double cf[NSLOT], fr[NSLOT], dfr[NSLOT], sg[NSLOT];
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) {
-                const double sgn = a < MAXSIDE ? -(double)nu[a] : (double)nu[a];
-                dG += sgn * G[spc[a]];
-                dH += sgn * H[spc[a]];
+                sg[a] = a < MAXSIDE ? -(double)nu[a] : (double)nu[a];
+                dG += sg[a] * G[spc[a]];
+                dH += sg[a] * H[spc[a]];
                 cf[a] = C[spc[a]];
+                powd(cf[a], nu[a], fr[a], dfr[a]);
             }
             const double dnu = rr.dnu;
             const double kf = exp(lnkf);
-            double fr[NSLOT];
-#pragma unroll
-            for (int a = 0; a < NSLOT; ++a) fr[a] = cpow(cf[a], nu[a]);
             const double Pf = fr[0] * fr[1] * fr[2];
             const double Pb = fr[3] * fr[4] * fr[5];
             const double lnkr = lnkf + dG - dnu * lnP0RT;
@@ -328,50 +329,46 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
             const double q = c * R;
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) {
-                if (nu[a]) {
-                    const double sgn = a < MAXSIDE ? -(double)nu[a] : (double)nu[a];
-                    atomicAdd(&W[spc[a]], sgn * q);
-                }
+                if (!((cmask >> a) & 1)) continue;
+                if (nu[a]) atomicAdd(&W[spc[a]], sg[a] * q);
             }
             if (!JAC) continue;
 
-            // concentration partials of q
+            // concentration partials of q (zero for empty slots and for the
+            // products of an irreversible reaction)
             const double dlnkf = (bexp + th * invT) * invT;
             const double dlnkr = dlnkf - (dH - dnu) * invT;
+            const double ckf = c * kf, ckr = -c * kr;
             double Qs[NSLOT];
-#pragma unroll
-            for (int a = 0; a < NSLOT; ++a) {
-                const double d = dcpow(cf[a], nu[a]);
-                if (a < MAXSIDE) {
-                    const double o = (a == 0 ? fr[1] * fr[2] : a == 1 ? fr[0] * fr[2] : fr[0] * fr[1]);
-                    Qs[a] = c * kf * d * o;
-                } else {
-                    const double o = (a == 3 ? fr[4] * fr[5] : a == 4 ? fr[3] * fr[5] : fr[3] * fr[4]);
-                    Qs[a] = rev ? -c * kr * d * o : 0.0;
-                }
-            }
+            Qs[0] = ckf * dfr[0] * (fr[1] * fr[2]);
+            Qs[1] = ckf * dfr[1] * (fr[0] * fr[2]);
+            Qs[2] = ckf * dfr[2] * (fr[0] * fr[1]);
+            Qs[3] = ckr * dfr[3] * (fr[4] * fr[5]);
+            Qs[4] = ckr * dfr[4] * (fr[3] * fr[5]);
+            Qs[5] = ckr * dfr[5] * (fr[3] * fr[4]);
             const double QM = R * dcdM;
             const double qT = c * (Rf * dlnkf - Rr * dlnkr) + R * dcdT;
             double Qb = 0.0, sQC = 0.0;
+#pragma unroll
+            for (int a = 0; a < NSLOT; ++a) sQC += Qs[a] * cf[a];
+            for (int e = e0; e < e1; ++e) {
+                const int se = dm.eff_sp[e];
+                const double qe = QM * dm.eff_am1[e];
+                sQC += qe * C[se];
+            }
             if (w & INFO_BATH) {
+                // rates that depend on the bath gas: its partial Q_Ns, taken out
+                // of the sum over the other species
 #pragma unroll
                 for (int a = 0; a < NSLOT; ++a)
                     if (spc[a] == bath) Qb += Qs[a];
                 for (int e = e0; e < e1; ++e)
                     if (dm.eff_sp[e] == bath) Qb += QM * dm.eff_am1[e];
-            }
-            if (FORM == PJ_CONP) {
-#pragma unroll
-                for (int a = 0; a < NSLOT; ++a)
-                    if (spc[a] < bath) sQC += Qs[a] * cf[a];
-                for (int e = e0; e < e1; ++e) {
-                    const int se = dm.eff_sp[e];
-                    if (se < bath) sQC += QM * dm.eff_am1[e] * C[se];
-                }
+                sQC -= Qb * C[bath];
             }
             const double dqdT = qT - Ctot * invT * (Qb + QM);
             const double dqdS = FORM == PJ_CONP ? -(sQC - Qb * (nsum * invV)) * invV
-                                                : (Qb + QM) / (RU * T);
+                                                : (Qb + QM) * invRT;
             const double dE = FORM == PJ_CONP ? dH : dH - dnu;
             const double dOm = rr.domega;
             racc[0] += dE * dqdT;
@@ -382,6 +379,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
             // energy / mole weighted partials (T and V/P rows)
 #pragma unroll
             for (int b = 0; b < NSLOT; ++b) {
+                if (!((cmask >> b) & 1) || (b >= MAXSIDE && !any_rev)) continue;
                 if (nu[b] && (b < MAXSIDE || rev)) {
                     atomicAdd(&TQ[spc[b]], dE * Qs[b]);
                     atomicAdd(&SQ[spc[b]], dOm * Qs[b]);
@@ -392,29 +390,38 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                 atomicAdd(&TQ[dm.eff_sp[e]], dE * qe);
                 atomicAdd(&SQ[dm.eff_sp[e]], dOm * qe);
             }
-            // species rows
+            // species rows; the slot table holds NOSLOT for pairs that do not
+            // exist (empty slots, irreversible products, bath-gas columns)
             const JacRec jr = load_rec(dm.jrec + p);
+            const double Vt = V * dqdT, Vs = V * dqdS;
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) {
-                if (!nu[a]) continue;
+                if (!((cmask >> a) & 1)) continue;
                 const uint16_t rb = jr.rowbase[a];
                 if (rb == NOSLOT) continue;
-                const double sgn = a < MAXSIDE ? -(double)nu[a] : (double)nu[a];
-                atomicAdd(&J[rb], V * sgn * dqdT);
-                atomicAdd(&J[rb + 1], V * sgn * dqdS);
+                atomicAdd(&J[rb], sg[a] * Vt);
+                atomicAdd(&J[rb + 1], sg[a] * Vs);
 #pragma unroll
                 for (int b = 0; b < NSLOT; ++b) {
-                    if (!(nu[b] && (b < MAXSIDE || rev))) continue;
-                    if (spc[b] == bath) {
-                        atomicAdd(&B[spc[a]], sgn * Qs[b]);
-                    } else {
-                        atomicAdd(&J[jr.slot[a * NSLOT + b]], sgn * Qs[b]);
-                    }
+                    if (!((cmask >> b) & 1) || (b >= MAXSIDE && !any_rev)) continue;
+                    const uint16_t sl = jr.slot[a * NSLOT + b];
+                    if (sl != NOSLOT) atomicAdd(&J[sl], sg[a] * Qs[b]);
                 }
                 for (int e = e0; e < e1; ++e) {
-                    const double qe = sgn * QM * dm.eff_am1[e];
-                    if (dm.eff_sp[e] == bath) atomicAdd(&B[spc[a]], qe);
-                    else atomicAdd(&J[dm.effslot[(size_t)e * NSLOT + a]], qe);
+                    const uint16_t sl = dm.effslot[(size_t)e * NSLOT + a];
+                    if (sl != NOSLOT) atomicAdd(&J[sl], sg[a] * QM * dm.eff_am1[e]);
+                }
+            }
+            if (w & INFO_BATH) {
+                // bath-gas columns of these rows go to the per-row sum B
+#pragma unroll
+                for (int a = 0; a < NSLOT; ++a) {
+                    if (jr.rowbase[a] == NOSLOT) continue;
+#pragma unroll
+                    for (int b = 0; b < NSLOT; ++b)
+                        if (spc[b] == bath && nu[b] && (b < MAXSIDE || rev)) atomicAdd(&B[spc[a]], sg[a] * Qs[b]);
+                    for (int e = e0; e < e1; ++e)
+                        if (dm.eff_sp[e] == bath) atomicAdd(&B[spc[a]], sg[a] * QM * dm.eff_am1[e]);
                 }
             }
         }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -147,12 +148,12 @@ pj_status validate(const Mechanism& m, std::string& err) {
             return PJ_E_UNSUPPORTED;
         }
         for (auto& a : r.reac) {
-            if (a.second > 3) { err = "coefficient above 3 in reaction " + std::to_string(i); return PJ_E_UNSUPPORTED; }
+            if (a.second > 2) { err = "coefficient above 2 in reaction " + std::to_string(i); return PJ_E_UNSUPPORTED; }
             for (auto& b : r.prod)
                 if (a.first == b.first) { err = "species on both sides of reaction " + std::to_string(i); return PJ_E_UNSUPPORTED; }
         }
         for (auto& b : r.prod)
-            if (b.second > 3) { err = "coefficient above 3 in reaction " + std::to_string(i); return PJ_E_UNSUPPORTED; }
+            if (b.second > 2) { err = "coefficient above 2 in reaction " + std::to_string(i); return PJ_E_UNSUPPORTED; }
         for (int e = 0; e < 4; ++e) {
             long lhs = 0, rhs = 0;
             for (auto& a : r.reac) lhs += (long)a.second * m.comp[(size_t)a.first * 4 + e];
@@ -226,12 +227,18 @@ pj_status build_mechanism(const char* path, Mechanism& m, std::string& err) {
     if (st != PJ_OK) return st;
     st = validate(m, err);
     if (st != PJ_OK) return st;
-    // kernel order: by kind, reversible elementary before irreversible, so
-    // that each 64-reaction chunk runs one code path
+    // Kernel order: by kind and reversibility, then by shape (number of
+    // reactant and product species), so that the reactions a wave handles
+    // together take the same branches and the empty slots of a 64-reaction
+    // chunk are skipped by wave-uniform branches instead of masked execution.
     m.order.resize(m.nr);
     for (int i = 0; i < m.nr; ++i) m.order[i] = i;
-    auto cls = [&](int i) { const auto& r = m.rx[i]; return r.kind == K_ELEM ? (r.rev ? 0 : 1) : r.kind + 1; };
-    std::stable_sort(m.order.begin(), m.order.end(), [&](int a, int b) { return cls(a) < cls(b); });
+    auto key = [&](int i) {
+        const auto& r = m.rx[i];
+        int cls = r.kind == K_ELEM ? (r.rev ? 0 : 1) : r.kind + 1;
+        return cls * 100 + (int)r.reac.size() * 10 + (int)r.prod.size();
+    };
+    std::stable_sort(m.order.begin(), m.order.end(), [&](int a, int b) { return key(a) < key(b); });
     build_pattern(m);
     if (m.nnz >= 65535) { err = "more than 65534 Jacobian non-zeros"; return PJ_E_UNSUPPORTED; }
     return PJ_OK;
@@ -275,6 +282,62 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     std::vector<double> eff_am1;
     std::vector<uint16_t> effslot;
     std::vector<char> dense_row(ns, 0);
+    // Slot positions.  The lanes of a wave handle 64 consecutive reactions
+    // and scatter slot a of every reaction in the same instruction, so a
+    // species that sits in the same slot of many of those reactions (a hub
+    // such as a radical present in most reactions) makes the LDS serialise the
+    // additions.  Within each side the order of the species is free: for every
+    // chunk of 64 reactions choose, greedily, the arrangement that adds the
+    // fewest repeats of an address already used at the same slot position.
+    std::vector<std::array<int, NSLOT>> SPA(nr), NUA(nr);
+    {
+        // orders of the species of one side; species stay in the leading
+        // positions so that a chunk of same-shape reactions leaves the same
+        // trailing positions empty (skipped as a whole by the kernel)
+        static const int perms[6][3] = {{0, 1, 2}, {1, 0, 2}, {0, 2, 1}, {2, 0, 1}, {1, 2, 0}, {2, 1, 0}};
+        auto nperm = [](size_t n) { return n <= 1 ? 1 : n == 2 ? 2 : 6; };
+        std::map<long, int> cnt;   // (position code, address) -> uses in this chunk
+        auto code = [](int kind, int pos, long addr) { return ((long)kind << 56) | ((long)pos << 48) | addr; };
+        for (int p = 0; p < nr; ++p) {
+            if (p % 64 == 0) cnt.clear();
+            const auto& r = m.rx[m.order[p]];
+            int rs[3] = {ns, ns, ns}, rn[3] = {0, 0, 0}, ps[3] = {ns, ns, ns}, pn[3] = {0, 0, 0};
+            for (size_t a = 0; a < r.reac.size(); ++a) { rs[a] = r.reac[a].first; rn[a] = r.reac[a].second; }
+            for (size_t b = 0; b < r.prod.size(); ++b) { ps[b] = r.prod[b].first; pn[b] = r.prod[b].second; }
+            long best = -1;
+            std::array<int, NSLOT> bs{}, bn{};
+            for (int pr = 0; pr < nperm(r.reac.size()); ++pr)
+                for (int pp = 0; pp < nperm(r.prod.size()); ++pp) {
+                    std::array<int, NSLOT> sa, na;
+                    for (int q = 0; q < 3; ++q) {
+                        sa[perms[pr][q]] = rs[q]; na[perms[pr][q]] = rn[q];
+                        sa[3 + perms[pp][q]] = ps[q]; na[3 + perms[pp][q]] = pn[q];
+                    }
+                    long c = 0;
+                    auto use = [&](long key) { auto it = cnt.find(key); if (it != cnt.end()) c += it->second; };
+                    for (int a = 0; a < NSLOT; ++a) {
+                        if (!na[a]) continue;
+                        use(code(0, a, sa[a]));
+                        if (sa[a] == bath) continue;
+                        use(code(1, a, sa[a]));
+                        for (int b = 0; b < NSLOT; ++b)
+                            if (na[b] && (b < 3 || r.rev)) use(code(2, a * NSLOT + b, (long)sa[a] * 65536 + sa[b]));
+                    }
+                    if (best < 0 || c < best) { best = c; bs = sa; bn = na; }
+                }
+            for (int a = 0; a < NSLOT; ++a) {
+                if (!bn[a]) continue;
+                cnt[code(0, a, bs[a])]++;
+                if (bs[a] == bath) continue;
+                cnt[code(1, a, bs[a])]++;
+                for (int b = 0; b < NSLOT; ++b)
+                    if (bn[b] && (b < 3 || r.rev)) cnt[code(2, a * NSLOT + b, (long)bs[a] * 65536 + bs[b])]++;
+            }
+            SPA[p] = bs;
+            NUA[p] = bn;
+        }
+    }
+
     for (int p = 0; p < nr_pad; ++p) {
         RxnRec& R = rec[p];
         for (int a = 0; a < NSLOT; ++a) R.sp[a] = (uint16_t)ns;
@@ -282,15 +345,15 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
         if (p >= nr) continue;
         const auto& r = m.rx[m.order[p]];
         int spa[NSLOT], nua[NSLOT];
-        for (int a = 0; a < NSLOT; ++a) { spa[a] = ns; nua[a] = 0; }
-        for (size_t a = 0; a < r.reac.size(); ++a) { spa[a] = r.reac[a].first; nua[a] = r.reac[a].second; }
-        for (size_t b = 0; b < r.prod.size(); ++b) { spa[3 + b] = r.prod[b].first; nua[3 + b] = r.prod[b].second; }
+        for (int a = 0; a < NSLOT; ++a) { spa[a] = SPA[p][a]; nua[a] = NUA[p][a]; }
         bool bathdep = depends_on_bath(m, r);
         uint32_t w = 0;
         for (int a = 0; a < NSLOT; ++a) w |= (uint32_t)nua[a] << (4 * a);
         w |= (uint32_t)r.kind << 24;
         if (r.rev) w |= INFO_REV;
         if (bathdep) w |= INFO_BATH;
+        for (int a = 0; a < NSLOT; ++a)
+            if (nua[a] && spa[a] == bath) w |= INFO_BATHROW;
         R.info = w;
         double sumnu = 0, om = 0;
         for (int a = 0; a < NSLOT; ++a) {
@@ -347,6 +410,15 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
         }
         R.eff1 = (uint32_t)eff_sp.size();
     }
+    // per 64-reaction chunk: which slot positions any of its reactions uses
+    // (bits 0..5), whether any is reversible (bit 6) or has third bodies (bit 7)
+    std::vector<uint32_t> chunk((size_t)nr_pad / 64, 0);
+    for (int p = 0; p < nr; ++p) {
+        uint32_t& cm = chunk[p / 64];
+        for (int a = 0; a < NSLOT; ++a) if (NUA[p][a]) cm |= 1u << a;
+        if (rec[p].info & INFO_REV) cm |= 1u << 6;
+        if (rec[p].eff1 > rec[p].eff0) cm |= 1u << 7;
+    }
     std::vector<int32_t> dense_rows;
     for (int k = 0; k < ns; ++k) if (dense_row[k]) dense_rows.push_back(k);
     std::vector<uint16_t> col16(m.col_idx.begin(), m.col_idx.end());
@@ -364,7 +436,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     size_t o_effs = place(eff_sp.size() * 2), o_effa = place(eff_am1.size() * 8),
            o_effslot = place(effslot.size() * 2);
     size_t o_rowp = place(m.row_ptr.size() * 4), o_col = place(col16.size() * 2),
-           o_dr = place(dense_rows.size() * 4);
+           o_dr = place(dense_rows.size() * 4), o_chunk = place(chunk.size() * 4);
     std::vector<unsigned char> host(total, 0);
     auto put = [&](size_t off, const void* src, size_t bytes) { std::memcpy(host.data() + off, src, bytes); };
     put(o_th, th.data(), th.size() * sizeof(ThermoRec));
@@ -379,6 +451,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     put(o_rowp, m.row_ptr.data(), m.row_ptr.size() * 4);
     put(o_col, col16.data(), col16.size() * 2);
     put(o_dr, dense_rows.data(), dense_rows.size() * 4);
+    put(o_chunk, chunk.data(), chunk.size() * 4);
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) { err = "no HIP device"; return PJ_E_DEVICE; }
@@ -412,6 +485,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.row_ptr = (const int32_t*)P(o_rowp);
     dm.col_idx = (const uint16_t*)P(o_col);
     dm.dense_rows = (const int32_t*)P(o_dr);
+    dm.chunk = (const uint32_t*)P(o_chunk);
 
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
