@@ -20,12 +20,13 @@ pj_status fail(pj_status st, const std::string& msg) {
 
 bool valid_wps(int w) { return w == 1 || w == 2 || w == 4; }
 
-// Automatic launch shape: one wave per state while several states fit in
-// the LDS of a compute unit, otherwise more waves share one state so that
-// every SIMD still has work.
+// Automatic launch shape: the fewest waves per state that still give a
+// compute unit at least 8 resident waves (two per SIMD) given how many
+// states fit in its LDS at once.
 int auto_wps(int64_t lds_bytes, int lds_max) {
-    if (lds_bytes * 4 <= lds_max) return 1;
-    if (lds_bytes * 2 <= lds_max) return 2;
+    const int64_t blocks = lds_bytes > 0 ? lds_max / lds_bytes : 32;
+    for (int w = 1; w <= 4; w *= 2)
+        if (blocks * w >= 8) return w;
     return 4;
 }
 

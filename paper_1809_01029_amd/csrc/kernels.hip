@@ -38,6 +38,8 @@ namespace pj {
 namespace {
 
 constexpr double LN10 = 2.302585092994045684;
+// LDS scratch of the workgroup reductions: up to 4 waves x 7 values
+constexpr int RED_N = 32;
 
 struct dd {
     double hi, lo;
@@ -72,7 +74,7 @@ __device__ inline double wave_sum(double v) {
 }
 
 // Sum of K per-thread values over the workgroup, in a fixed order; every
-// thread receives the totals.  red: LDS scratch of 16*K doubles.
+// thread receives the totals.  red: LDS scratch of nwave*K doubles.
 template <int K>
 __device__ inline void block_sum(double (&v)[K], double* red, int wave, int nwave) {
 #pragma unroll
@@ -131,8 +133,8 @@ __device__ inline void powd(double c, int nu, double& f, double& d) {
 }  // namespace
 
 int64_t lds_bytes(const DevMech& dm, int mode) {
-    int64_t d = 5 * (int64_t)(dm.ns + 1) + 16 * 8;
-    if (mode != MODE_SRC) d += dm.nnz + dm.ns + 2 * (int64_t)(dm.ns + 1);
+    int64_t d = 5 * (int64_t)(dm.ns + 1) + RED_N;
+    if (mode != MODE_SRC) d += dm.nnz + dm.ns;
     if (mode == MODE_DENSE) d += dm.N;
     return d * 8;
 }
@@ -155,11 +157,14 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
     double* CP = H + (ns + 1);
     double* W = CP + (ns + 1);
     double* red = W + (ns + 1);
-    double* J = red + 16 * 8;
+    double* J = red + RED_N;
     double* B = J + nnz;
-    double* TQ = B + ns;
-    double* SQ = TQ + (ns + 1);
-    double* ROW = SQ + (ns + 1);
+    double* ROW = B + ns;
+    // The T and V/P rows (the first 2N CSR slots) are written to the output
+    // straight from registers; their LDS space holds the energy- and
+    // mole-weighted partial sums meanwhile.
+    double* TQ = J;
+    double* SQ = J + N;
 
     // Consecutive states go to workgroups of the same XCD (workgroups are
     // handed to the 8 XCDs round-robin), so that the partial cache lines of
@@ -196,7 +201,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
         if (JAC) {
             for (int e = tid; e < nnz; e += nthr) J[e] = 0.0;
             for (int k = tid; k < ns; k += nthr) B[k] = 0.0;
-            for (int k = tid; k < ns + 1; k += nthr) { TQ[k] = 0.0; SQ[k] = 0.0; }
+
         }
         acc = block_dd_sum(acc, red, wave, nwave);
         const double nsum = acc.hi;
@@ -488,8 +493,23 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                     j1 = FORM == PJ_CONP ? V * invT * j0 + RTP * (SQ[k] - SQ[bath])
                                          : P * invT * j0 + RU * T * (SQ[k] - SQ[bath]) * invV;
                 }
-                J[j] = j0;
-                J[N + j] = j1;
+                if (MODE == MODE_SPARSE) {
+                    if (LAYOUT == PJ_LAYOUT_F) {
+                        jac[(long)j * n + s] = j0;
+                        jac[(long)(N + j) * n + s] = j1;
+                    } else {
+                        jac[s * (long)nnz + j] = j0;
+                        jac[s * (long)nnz + N + j] = j1;
+                    }
+                } else {
+                    if (LAYOUT == PJ_LAYOUT_F) {
+                        jac[s + n * ((long)N * j)] = j0;
+                        jac[s + n * (1 + (long)N * j)] = j1;
+                    } else {
+                        jac[s * (long)N * N + j] = j0;
+                        jac[s * (long)N * N + N + j] = j1;
+                    }
+                }
             }
             // bath-gas dependent rows are dense: subtract their bath partial
             for (int d = 0; d < dm.n_dense_rows; ++d) {
@@ -506,12 +526,12 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
         __syncthreads();
 
         if (MODE == MODE_SPARSE) {
-            for (int e = tid; e < nnz; e += nthr) {
+            for (int e = 2 * N + tid; e < nnz; e += nthr) {
                 if (LAYOUT == PJ_LAYOUT_F) jac[(long)e * n + s] = J[e];
                 else jac[s * (long)nnz + e] = J[e];
             }
         } else {
-            for (int i = 0; i < N; ++i) {
+            for (int i = 2; i < N; ++i) {
                 for (int j = tid; j < N; j += nthr) ROW[j] = 0.0;
                 __syncthreads();
                 const int r0 = dm.row_ptr[i], r1 = dm.row_ptr[i + 1];
