@@ -143,16 +143,25 @@ pj_status pj_eval_jacobian_dense(const pj_mech* mech, pj_form form, pj_layout la
                                  double* d_jac, double* d_dstate_or_null, pj_stream stream);
 
 /*
- * Launch shape: waves_per_state workgroup waves cooperate on one state
- * (1, 2 or 4; 0 restores the automatic choice).  With one wave per
- * state every accumulation happens in a fixed order, so results are bitwise
- * reproducible; with more, the order of LDS atomic additions across waves may
- * vary between runs (results then agree to rounding).
+ * Launch shape.  A workgroup evaluates states_per_group consecutive states at
+ * once (1, 2 or 4) with waves_per_group waves (1, 2, 4 or 8); 0 restores the
+ * automatic choice (the most states whose working set fits the LDS of one
+ * workgroup, and enough waves for about 8 resident waves per compute unit).
+ * A states_per_group that does not fit for a mode is ignored for that mode.
+ * With one wave per workgroup every accumulation happens in a fixed order,
+ * so results are bitwise reproducible; with more, the order of LDS atomic
+ * additions across waves may vary between runs (results then agree to
+ * rounding).  pj_mech_set_waves_per_state(w) is pj_mech_set_launch(1, w)
+ * (w in 1, 2, 4; 0 = automatic).
  */
+pj_status pj_mech_set_launch(pj_mech* mech, int states_per_group, int waves_per_group);
 pj_status pj_mech_set_waves_per_state(pj_mech* mech, int waves_per_state);
+/* waves per workgroup when one state per workgroup is used, else -1 */
 int pj_mech_waves_per_state(const pj_mech* mech, int for_jacobian);
+/* launch shape of mode 0 (source), 1 (sparse Jacobian) or 2 (dense Jacobian); -1 on error */
+int pj_mech_launch_shape(const pj_mech* mech, int mode, int* states_per_group, int* waves_per_group);
 
-/* Bytes of LDS one state needs for source terms (0) or the Jacobian (1). */
+/* Bytes of LDS one workgroup needs for source terms (0) or the sparse Jacobian (1). */
 int64_t pj_mech_lds_bytes(const pj_mech* mech, int for_jacobian);
 
 /* Thread-local description of the last error ("" if none). */

@@ -61,6 +61,10 @@ _lib.pj_mech_set_waves_per_state.argtypes = [_P, ctypes.c_int]
 _lib.pj_mech_set_waves_per_state.restype = ctypes.c_int
 _lib.pj_mech_waves_per_state.argtypes = [_P, ctypes.c_int]
 _lib.pj_mech_waves_per_state.restype = ctypes.c_int
+_lib.pj_mech_set_launch.argtypes = [_P, ctypes.c_int, ctypes.c_int]
+_lib.pj_mech_set_launch.restype = ctypes.c_int
+_lib.pj_mech_launch_shape.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.pj_mech_launch_shape.restype = ctypes.c_int
 _lib.pj_mech_lds_bytes.argtypes = [_P, ctypes.c_int]
 _lib.pj_mech_lds_bytes.restype = _I64
 _lib.pj_last_error.argtypes = []
@@ -128,6 +132,18 @@ class Mechanism:
     def set_waves_per_state(self, w: int):
         _check(_lib.pj_mech_set_waves_per_state(self._h, int(w)), "pj_mech_set_waves_per_state")
 
+    def set_launch(self, states_per_group: int = 0, waves_per_group: int = 0):
+        _check(_lib.pj_mech_set_launch(self._h, int(states_per_group), int(waves_per_group)),
+               "pj_mech_set_launch")
+
+    def launch_shape(self, mode: int = 1):
+        """(states per workgroup, waves per workgroup) of mode 0 (source),
+        1 (sparse Jacobian) or 2 (dense Jacobian)."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        if _lib.pj_mech_launch_shape(self._h, int(mode), ctypes.byref(a), ctypes.byref(b)) != 0:
+            raise PjError(1, "pj_mech_launch_shape")
+        return a.value, b.value
+
     def waves_per_state(self, jacobian: bool = False) -> int:
         return _lib.pj_mech_waves_per_state(self._h, 1 if jacobian else 0)
 
@@ -135,7 +151,7 @@ class Mechanism:
         return int(_lib.pj_mech_lds_bytes(self._h, 1 if jacobian else 0))
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.pj_mech_free(self._h)
             self._h = None
 

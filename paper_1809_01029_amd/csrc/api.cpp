@@ -18,17 +18,37 @@ pj_status fail(pj_status st, const std::string& msg) {
     return st;
 }
 
-bool valid_wps(int w) { return w == 1 || w == 2 || w == 4; }
+bool pow2_upto(int v, int mx) { return v >= 1 && v <= mx && (v & (v - 1)) == 0; }
 
-// Automatic launch shape: the fewest waves per state that still give a
-// compute unit at least 8 resident waves (two per SIMD) given how many
-// states fit in its LDS at once.
-int auto_wps(int64_t lds_bytes, int lds_max) {
-    const int64_t blocks = lds_bytes > 0 ? lds_max / lds_bytes : 32;
-    for (int w = 1; w <= 4; w *= 2)
-        if (blocks * w >= 8) return w;
-    return 4;
+}  // namespace
+
+namespace pj {
+
+// Launch shape of each mode.  States per workgroup S: the most (4, 2 or 1)
+// whose interleaved working set fits the LDS of one workgroup.  Waves per
+// workgroup: enough that a compute unit holds about 8 resident waves given
+// how many workgroups fit in its LDS (at most 8).  A user setting overrides
+// either choice when it fits.
+void choose_launch(Mechanism& m) {
+    for (int mode = 0; mode < 3; ++mode) {
+        int S = 1;
+        for (int c = 4; c >= 1; c >>= 1)
+            if (lds_bytes(m.dm, mode, c) <= m.lds_max) { S = c; break; }
+        if (m.user_S && lds_bytes(m.dm, mode, m.user_S) <= m.lds_max) S = m.user_S;
+        const int64_t l = lds_bytes(m.dm, mode, S);
+        const int64_t blocks = l > 0 ? m.lds_max / l : 8;
+        int w = 1;
+        while (w < 8 && blocks * w < 8) w *= 2;
+        if (m.user_waves) w = m.user_waves;
+        m.S[mode] = S;
+        m.waves[mode] = w;
+        m.lds[mode] = l;
+    }
 }
+
+}  // namespace pj
+
+namespace {
 
 pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, int64_t n,
                const double* state, const double* param, double* dstate, double* jac,
@@ -46,13 +66,12 @@ pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, in
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != m.device)
         return fail(PJ_E_INVALID, "the current HIP device is not the one the mechanism was loaded on");
-    int64_t lds = mode == pj::MODE_SRC ? m.lds_src : mode == pj::MODE_SPARSE ? m.lds_jac : m.lds_dense;
+    const int64_t lds = m.lds[mode];
     if (lds > m.lds_max)
         return fail(PJ_E_UNSUPPORTED, "per-state working set (" + std::to_string(lds) +
                                           " B) exceeds the LDS of one workgroup");
-    int wps = mode == pj::MODE_SRC ? m.wps_src : m.wps_jac;
-    hipError_t e = pj::launch(m.dm, mode, form, layout, n, state, param, dstate, jac, wps, lds,
-                              (hipStream_t)stream);
+    hipError_t e = pj::launch(m.dm, mode, form, layout, m.S[mode], n, state, param, dstate, jac,
+                              m.waves[mode], lds, (hipStream_t)stream);
     if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     g_err.clear();
     return PJ_OK;
@@ -87,10 +106,6 @@ pj_status pj_mech_upload(pj_mech* mech) {
     if (st != PJ_OK) {
         if (mech->m.dbuf) { (void)hipFree(mech->m.dbuf); mech->m.dbuf = nullptr; }
         return fail(st, err);
-    }
-    if (!mech->m.wps_user) {
-        mech->m.wps_src = auto_wps(mech->m.lds_src, mech->m.lds_max);
-        mech->m.wps_jac = auto_wps(mech->m.lds_jac, mech->m.lds_max);
     }
     g_err.clear();
     return PJ_OK;
@@ -156,31 +171,49 @@ pj_status pj_eval_jacobian_dense(const pj_mech* mech, pj_form form, pj_layout la
                 d_jac, stream);
 }
 
-pj_status pj_mech_set_waves_per_state(pj_mech* mech, int waves_per_state) {
+pj_status pj_mech_set_launch(pj_mech* mech, int states_per_group, int waves_per_group) {
     if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
-    if (waves_per_state == 0) {
-        if (mech->m.dbuf) {
-            mech->m.wps_src = auto_wps(mech->m.lds_src, mech->m.lds_max);
-            mech->m.wps_jac = auto_wps(mech->m.lds_jac, mech->m.lds_max);
-        }
-        mech->m.wps_user = false;
+    if (states_per_group && !pow2_upto(states_per_group, 4))
+        return fail(PJ_E_INVALID, "states_per_group must be 0, 1, 2 or 4");
+    if (waves_per_group && !pow2_upto(waves_per_group, 8))
+        return fail(PJ_E_INVALID, "waves_per_group must be 0, 1, 2, 4 or 8");
+    mech->m.user_S = states_per_group;
+    mech->m.user_waves = waves_per_group;
+    if (mech->m.dbuf) {
+        pj::choose_launch(mech->m);
     } else {
-        if (!valid_wps(waves_per_state)) return fail(PJ_E_INVALID, "waves_per_state must be 1, 2 or 4");
-        mech->m.wps_src = mech->m.wps_jac = waves_per_state;
-        mech->m.wps_user = true;
+        // provisional until the upload measures the LDS the modes need
+        for (int mode = 0; mode < 3; ++mode) {
+            mech->m.S[mode] = states_per_group ? states_per_group : 1;
+            mech->m.waves[mode] = waves_per_group ? waves_per_group : 1;
+        }
     }
     g_err.clear();
     return PJ_OK;
 }
 
+pj_status pj_mech_set_waves_per_state(pj_mech* mech, int waves_per_state) {
+    if (waves_per_state != 0 && !pow2_upto(waves_per_state, 4))
+        return fail(PJ_E_INVALID, "waves_per_state must be 0, 1, 2 or 4");
+    return pj_mech_set_launch(mech, waves_per_state ? 1 : 0, waves_per_state);
+}
+
 int pj_mech_waves_per_state(const pj_mech* mech, int for_jacobian) {
     if (!mech) return -1;
-    return for_jacobian ? mech->m.wps_jac : mech->m.wps_src;
+    const int mode = for_jacobian ? pj::MODE_SPARSE : pj::MODE_SRC;
+    return mech->m.S[mode] == 1 ? mech->m.waves[mode] : -1;
+}
+
+int pj_mech_launch_shape(const pj_mech* mech, int mode, int* states_per_group, int* waves_per_group) {
+    if (!mech || mode < 0 || mode > 2) return -1;
+    if (states_per_group) *states_per_group = mech->m.S[mode];
+    if (waves_per_group) *waves_per_group = mech->m.waves[mode];
+    return 0;
 }
 
 int64_t pj_mech_lds_bytes(const pj_mech* mech, int for_jacobian) {
     if (!mech) return -1;
-    return for_jacobian ? mech->m.lds_jac : mech->m.lds_src;
+    return for_jacobian ? mech->m.lds[pj::MODE_SPARSE] : mech->m.lds[pj::MODE_SRC];
 }
 
 const char* pj_last_error(void) { return g_err.c_str(); }

@@ -38,7 +38,8 @@ __host__ __device__ inline int info_kind(uint32_t w) { return (w >> 24) & 0x3; }
 struct alignas(16) RxnRec {          // 80 B
     uint32_t info;                   // see INFO_* above
     uint32_t eff0, eff1;             // this reaction's range in the efficiency list
-    uint32_t pad0;
+    uint32_t chunk;                  // slot positions used in this reaction's 64-reaction
+                                     // chunk (bits 0..5), any reversible (bit 6)
     uint16_t sp[6];                  // species of slot a (Ns = empty slot)
     uint16_t pad1[2];
     double lnA, b, theta;            // Arrhenius (k_inf for falloff)
@@ -88,8 +89,6 @@ struct DevMech {
     const int32_t* row_ptr;   // [N + 1]
     const uint16_t* col_idx;  // [nnz]
     const int32_t* dense_rows;// [n_dense_rows] species index k of bath-dense rows
-    const uint32_t* chunk;    // [nr_pad / 64] slot positions used in the chunk (bits 0..5),
-                              // any reversible (bit 6), any third body (bit 7)
 };
 
 struct Mechanism {
@@ -118,9 +117,11 @@ struct Mechanism {
     int device = -1;
     void* dbuf = nullptr;
     DevMech dm{};
-    int wps_src = 1, wps_jac = 1;          // waves per state
-    bool wps_user = false;
-    int64_t lds_src = 0, lds_jac = 0, lds_dense = 0;
+    // launch shape per mode (source, sparse, dense): states per workgroup,
+    // waves per workgroup, and the LDS bytes that needs
+    int S[3] = {1, 1, 1}, waves[3] = {1, 1, 1};
+    int64_t lds[3] = {0, 0, 0};
+    int user_S = 0, user_waves = 0;        // 0 = automatic
     int lds_max = 0;
 };
 
@@ -130,10 +131,12 @@ pj_status upload_mechanism(Mechanism& m, std::string& err);
 
 // kernels.hip
 enum Mode : int { MODE_SRC = 0, MODE_SPARSE = 1, MODE_DENSE = 2 };
-int64_t lds_bytes(const DevMech& dm, int mode);
-hipError_t launch(const DevMech& dm, int mode, int form, int layout, int64_t n, const double* state,
-                  const double* param, double* dstate, double* jac, int wps, int64_t lds,
-                  hipStream_t stream);
+int64_t lds_bytes(const DevMech& dm, int mode, int S);
+hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
+                  const double* state, const double* param, double* dstate, double* jac, int waves,
+                  int64_t lds, hipStream_t stream);
+// api.cpp
+void choose_launch(Mechanism& m);
 
 }  // namespace pj
 

@@ -1,21 +1,29 @@
 // FP64 HIP kernels for gfx950: thermochemical source terms and the analytical
 // sparse / dense Jacobian (Curtis, Niemeyer & Sung, pyJac v2, Sec. 2.2 and
-// Sec. 3.4), one workgroup per state ("deep" vectorization, Sec. 2.1).
+// Sec. 3.4), with the lanes of a workgroup cooperating on a few states at a
+// time ("deep" vectorization, Sec. 2.1).
 //
-// Mapping.  A workgroup of `wps` waves evaluates one state at a time (a
-// grid-stride loop over states).  Its lanes split the species for the
-// thermodynamics and the reactions (sorted by kind, so a 64-reaction chunk
-// takes one code path) for the rates and the Jacobian sub-products.  The
-// per-state working set lives in LDS:
-//     C, G, H, CP, W   [Ns+1] each: concentrations, g = G/RT, h = H/RT,
-//                      chat/R, production rates; entry Ns is a sentinel
-//                      (C = 1, G = H = 0) that empty reaction slots point at
+// Mapping.  A workgroup evaluates S consecutive states at once (S = 1, 2 or
+// 4) in a grid-stride loop over groups of states.  Thread t works for state
+// t mod S; the t / S index splits the species for the thermodynamics and the
+// reactions (sorted by kind and shape) for the rates and the Jacobian
+// sub-products, so the S lanes of one reaction fetch its record together.
+// The per-state working set lives in LDS, every array interleaved with the
+// state fastest (element i of state s at i*S + s):
+//     C, G, H, CP, W   [Ns+1] concentrations, g = G/RT, h = H/RT, chat/R,
+//                      production rates; entry Ns is a sentinel (C = 1,
+//                      G = H = 0) that empty reaction slots point at
 //     J                [nnz]  CSR accumulator of the species rows
 //     B                [Ns]   per-row sum of the bath-gas partials
-//     TQ, SQ           [Ns+1] energy- and mole-weighted concentration partials
-// Reactions scatter into these with LDS FP64 atomics (ds_add_f64).  With one
-// wave per state the order of those additions is fixed by program order, so
-// the results are bitwise reproducible.
+//     TQ, SQ           [Ns+1] energy- and mole-weighted concentration
+//                      partials, kept in the space of CSR rows 0 and 1,
+//                      which are written to the output from registers
+// Reactions scatter into these with LDS FP64 atomics (ds_add_f64).  Because
+// the S states of one reaction sit in adjacent words, one atomic instruction
+// touches 64/S reactions in S-word blocks, which keeps LDS bank conflicts and
+// same-address collisions (hub species) low.  With one wave per workgroup the
+// order of those additions is fixed by program order, so results are bitwise
+// reproducible.
 //
 // Jacobian formulation.  With the third-body concentration written as
 // [M] = C_tot + sum_k (alpha_k - 1) [C]_k, C_tot = P/(R T), each reaction
@@ -38,8 +46,9 @@ namespace pj {
 namespace {
 
 constexpr double LN10 = 2.302585092994045684;
-// LDS scratch of the workgroup reductions: up to 4 waves x 7 values
-constexpr int RED_N = 32;
+// LDS scratch of the workgroup reductions, per state: up to 8 waves x 8 values
+constexpr int RED_PER_STATE = 64;
+constexpr int MAX_THREADS = 512;
 
 struct dd {
     double hi, lo;
@@ -67,44 +76,52 @@ __device__ inline dd dd_add(dd a, dd b) {
     return {s, t};
 }
 
+// Sum over the lanes of a wave that work for the same state (lanes equal
+// modulo S); every such lane receives the sum.
+template <int S>
 __device__ inline double wave_sum(double v) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int o = 32; o >= S; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-// Sum of K per-thread values over the workgroup, in a fixed order; every
-// thread receives the totals.  red: LDS scratch of nwave*K doubles.
-template <int K>
-__device__ inline void block_sum(double (&v)[K], double* red, int wave, int nwave) {
+// Per-state sum of K per-thread values over the workgroup, in a fixed order;
+// every thread receives the totals of its state.  red: LDS scratch of
+// RED_PER_STATE * S doubles.
+template <int S, int K>
+__device__ inline void block_sum(double (&v)[K], double* red, int wave, int nwave, int s) {
 #pragma unroll
-    for (int q = 0; q < K; ++q) v[q] = wave_sum(v[q]);
+    for (int q = 0; q < K; ++q) v[q] = wave_sum<S>(v[q]);
     if (nwave == 1) return;
-    if ((threadIdx.x & 63) == 0) {
+    if ((threadIdx.x & 63) < S) {
 #pragma unroll
-        for (int q = 0; q < K; ++q) red[wave * K + q] = v[q];
+        for (int q = 0; q < K; ++q) red[(wave * K + q) * S + s] = v[q];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < K; ++q) {
         double t = 0.0;
-        for (int w = 0; w < nwave; ++w) t += red[w * K + q];
+        for (int w = 0; w < nwave; ++w) t += red[(w * K + q) * S + s];
         v[q] = t;
     }
     __syncthreads();
 }
 
-__device__ inline dd block_dd_sum(dd a, double* red, int wave, int nwave) {
+template <int S>
+__device__ inline dd block_dd_sum(dd a, double* red, int wave, int nwave, int s) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int o = 32; o >= S; o >>= 1) {
         dd b{__shfl_xor(a.hi, o, 64), __shfl_xor(a.lo, o, 64)};
         a = dd_add(a, b);
     }
     if (nwave == 1) return a;
-    if ((threadIdx.x & 63) == 0) { red[2 * wave] = a.hi; red[2 * wave + 1] = a.lo; }
+    if ((threadIdx.x & 63) < S) {
+        red[(2 * wave) * S + s] = a.hi;
+        red[(2 * wave + 1) * S + s] = a.lo;
+    }
     __syncthreads();
     dd t{0.0, 0.0};
-    for (int w = 0; w < nwave; ++w) t = dd_add(t, dd{red[2 * w], red[2 * w + 1]});
+    for (int w = 0; w < nwave; ++w) t = dd_add(t, dd{red[(2 * w) * S + s], red[(2 * w + 1) * S + s]});
     __syncthreads();
     return t;
 }
@@ -132,58 +149,66 @@ __device__ inline void powd(double c, int nu, double& f, double& d) {
 
 }  // namespace
 
-int64_t lds_bytes(const DevMech& dm, int mode) {
-    int64_t d = 5 * (int64_t)(dm.ns + 1) + RED_N;
+int64_t lds_bytes(const DevMech& dm, int mode, int S) {
+    int64_t d = 5 * (int64_t)(dm.ns + 1);
     if (mode != MODE_SRC) d += dm.nnz + dm.ns;
     if (mode == MODE_DENSE) d += dm.N;
-    return d * 8;
+    return (d * S + (int64_t)RED_PER_STATE * S) * 8;
 }
 
-template <int FORM, int LAYOUT, int MODE>
-__global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
-                                                  const double* __restrict__ state,
-                                                  const double* __restrict__ param,
-                                                  double* __restrict__ dstate,
-                                                  double* __restrict__ jac) {
+template <int FORM, int LAYOUT, int MODE, int S>
+__global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const long n,
+                                                          const double* __restrict__ state,
+                                                          const double* __restrict__ param,
+                                                          double* __restrict__ dstate,
+                                                          double* __restrict__ jac) {
     extern __shared__ double lds[];
     constexpr bool JAC = MODE != MODE_SRC;
     const int ns = dm.ns, N = dm.N, bath = dm.bath, nnz = dm.nnz;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, nwave = nthr >> 6;
+    const int s = tid % S;          // the state of this thread within the group
+    const int g = tid / S;          // its index among the threads of that state
+    const int G = nthr / S;         // threads per state
 
     double* C = lds;
-    double* G = C + (ns + 1);
-    double* H = G + (ns + 1);
-    double* CP = H + (ns + 1);
-    double* W = CP + (ns + 1);
-    double* red = W + (ns + 1);
-    double* J = red + RED_N;
-    double* B = J + nnz;
-    double* ROW = B + ns;
-    // The T and V/P rows (the first 2N CSR slots) are written to the output
-    // straight from registers; their LDS space holds the energy- and
-    // mole-weighted partial sums meanwhile.
+    double* Gg = C + (ns + 1) * S;
+    double* H = Gg + (ns + 1) * S;
+    double* CP = H + (ns + 1) * S;
+    double* W = CP + (ns + 1) * S;
+    double* red = W + (ns + 1) * S;
+    double* J = red + RED_PER_STATE * S;
+    double* B = J + (size_t)nnz * S;
+    double* ROW = B + (size_t)ns * S;
+    // The T and V/P rows (the first 2N CSR slots) go to the output straight
+    // from registers; their LDS space holds the energy- and mole-weighted
+    // partial sums meanwhile.
     double* TQ = J;
-    double* SQ = J + N;
+    double* SQ = J + (size_t)N * S;
+#define AT(arr, i) (arr)[(size_t)(i) * S + s]
 
-    // Consecutive states go to workgroups of the same XCD (workgroups are
-    // handed to the 8 XCDs round-robin), so that the partial cache lines of
-    // layout-F arrays of neighbouring states meet in one L2: XCD x takes the
-    // contiguous state range [n x/8, n (x+1)/8) in increasing order.
-    long s0 = blockIdx.x, s1 = n, sstep = gridDim.x;
+    // Groups of S consecutive states.  Consecutive groups go to workgroups of
+    // the same XCD (workgroups are handed to the 8 XCDs round-robin), so that
+    // the partial cache lines of layout-F arrays of neighbouring states meet
+    // in one L2: XCD x takes the contiguous range [ng x/8, ng (x+1)/8).
+    const long ngroups = (n + S - 1) / S;
+    long q0 = blockIdx.x, q1 = ngroups, qstep = gridDim.x;
     if (gridDim.x >= 8 && (gridDim.x & 7) == 0) {
         const long x = blockIdx.x & 7;
-        s0 = n * x / 8 + (blockIdx.x >> 3);
-        s1 = n * (x + 1) / 8;
-        sstep = gridDim.x >> 3;
+        q0 = ngroups * x / 8 + (blockIdx.x >> 3);
+        q1 = ngroups * (x + 1) / 8;
+        qstep = gridDim.x >> 3;
     }
-    for (long s = s0; s < s1; s += sstep) {
+    for (long qg = q0; qg < q1; qg += qstep) {
+        const long st = qg * S + s;           // this thread's state
+        const bool valid = st < n;
+        const long sc = valid ? st : n - 1;   // states past the end compute a copy of the last
         auto X = [&](int i) -> double {
-            return LAYOUT == PJ_LAYOUT_F ? state[(long)i * n + s] : state[s * (long)N + i];
+            return LAYOUT == PJ_LAYOUT_F ? state[(long)i * n + sc] : state[sc * (long)N + i];
         };
         const double T = X(0);
         const double Sv = X(1);
-        const double Q = param[s];
+        const double Q = param[sc];
         const double V = FORM == PJ_CONP ? Sv : Q;
         const double P = FORM == PJ_CONP ? Q : Sv;
         const double invT = 1.0 / T;
@@ -192,27 +217,26 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
         // ---- concentrations and the bath-gas closure (Sec. 2.2):
         //      n_Ns = P V / (R T) - RN(sum_{k<Ns} n_k)
         dd acc{0.0, 0.0};
-        for (int k = tid; k < ns - 1; k += nthr) {
-            double nk = X(2 + k);
+        for (int k = g; k < ns - 1; k += G) {
+            const double nk = X(2 + k);
             acc = dd_add(acc, dd{nk, 0.0});
-            C[k] = nk / V;
+            AT(C, k) = nk / V;
         }
-        for (int k = tid; k < ns + 1; k += nthr) W[k] = 0.0;
+        for (int k = g; k < ns + 1; k += G) AT(W, k) = 0.0;
         if (JAC) {
-            for (int e = tid; e < nnz; e += nthr) J[e] = 0.0;
-            for (int k = tid; k < ns; k += nthr) B[k] = 0.0;
-
+            for (int e = g; e < nnz; e += G) AT(J, e) = 0.0;
+            for (int k = g; k < ns; k += G) AT(B, k) = 0.0;
         }
-        acc = block_dd_sum(acc, red, wave, nwave);
+        acc = block_dd_sum<S>(acc, red, wave, nwave, s);
         const double nsum = acc.hi;
         const double ntot = (P * V) / (RU * T);
         const double nbath = ntot - nsum;
-        if (tid == 0) {
-            C[bath] = nbath / V;
-            C[ns] = 1.0;
-            G[ns] = 0.0;
-            H[ns] = 0.0;
-            CP[ns] = 0.0;
+        if (g == 0) {
+            AT(C, bath) = nbath / V;
+            AT(C, ns) = 1.0;
+            AT(Gg, ns) = 0.0;
+            AT(H, ns) = 0.0;
+            AT(CP, ns) = 0.0;
         }
         __syncthreads();
 
@@ -223,35 +247,36 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
 
         // ---- species thermodynamics (NASA-7)
         double tsum[2] = {0.0, 0.0};   // D' = sum C chat/R, dD'/dT = sum C dCp/R/dT
-        for (int k = tid; k < ns; k += nthr) {
+        for (int k = g; k < ns; k += G) {
             const int rg = T < dm.tmid[k] ? 0 : 1;
             const ThermoRec tr = load_rec(dm.th + 2 * (size_t)k + rg);
             auto a = [&](int q) { return tr.c[q]; };
             const double a0 = a(0), a1 = a(1);
-            double cp = a0 + T * (a1 + T * (a(2) + T * (a(3) + T * a(4))));
-            double h = a0 + T * (a(5) + T * (a(6) + T * (a(7) + T * a(8)))) + a(12) * invT;
-            double sr = a0 * lnT + T * (a1 + T * (a(9) + T * (a(10) + T * a(11)))) + a(13);
-            G[k] = h - sr;
-            H[k] = h;
-            double ch = FORM == PJ_CONP ? cp : cp - 1.0;
-            CP[k] = ch;
-            double ck = C[k];
+            const double cp = a0 + T * (a1 + T * (a(2) + T * (a(3) + T * a(4))));
+            const double h = a0 + T * (a(5) + T * (a(6) + T * (a(7) + T * a(8)))) + a(12) * invT;
+            const double sr = a0 * lnT + T * (a1 + T * (a(9) + T * (a(10) + T * a(11)))) + a(13);
+            AT(Gg, k) = h - sr;
+            AT(H, k) = h;
+            const double ch = FORM == PJ_CONP ? cp : cp - 1.0;
+            AT(CP, k) = ch;
+            const double ck = AT(C, k);
             tsum[0] += ck * ch;
             if (JAC) tsum[1] += ck * (a1 + T * (a(14) + T * (a(15) + T * a(16))));
         }
-        block_sum(tsum, red, wave, nwave);
+        block_sum<S>(tsum, red, wave, nwave, s);
         const double Dp = tsum[0];
         const double dDpdT = tsum[1];
         __syncthreads();
 
         // ---- reactions: rates of progress and Jacobian sub-products
         double racc[4] = {0.0, 0.0, 0.0, 0.0};  // TT, TS, ST, SS
-        for (int p = tid; p < dm.nr; p += nthr) {
-            // positions any reaction of this 64-reaction chunk uses (uniform
-            // over the wave: a wave's lanes take 64 consecutive reactions)
-            const uint32_t cmask = __builtin_amdgcn_readfirstlane(dm.chunk[p >> 6]);
-            const bool any_rev = (cmask >> 6) & 1;
+        for (int p = g; p < dm.nr; p += G) {
             const RxnRec rr = load_rec(dm.rec + p);
+            // slot positions any reaction of this 64-reaction chunk uses
+            // (uniform over the wave: a wave's lanes take 64/S consecutive
+            // reactions inside one chunk)
+            const uint32_t cmask = __builtin_amdgcn_readfirstlane(rr.chunk);
+            const bool any_rev = (cmask >> 6) & 1;
             const uint32_t w = rr.info;
             const int kind = info_kind(w);
             const bool rev = (w & INFO_REV) != 0;
@@ -268,9 +293,13 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) {
                 sg[a] = a < MAXSIDE ? -(double)nu[a] : (double)nu[a];
-                dG += sg[a] * G[spc[a]];
-                dH += sg[a] * H[spc[a]];
-                cf[a] = C[spc[a]];
+                if ((cmask >> a) & 1) {
+                    dG += sg[a] * AT(Gg, spc[a]);
+                    dH += sg[a] * AT(H, spc[a]);
+                    cf[a] = AT(C, spc[a]);
+                } else {
+                    cf[a] = 1.0;
+                }
                 powd(cf[a], nu[a], fr[a], dfr[a]);
             }
             const double dnu = rr.dnu;
@@ -288,7 +317,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
             const int e0 = (int)rr.eff0, e1 = (int)rr.eff1;
             if (kind != K_ELEM) {
                 double M = Ctot;
-                for (int e = e0; e < e1; ++e) M += dm.eff_am1[e] * C[dm.eff_sp[e]];
+                for (int e = e0; e < e1; ++e) M += dm.eff_am1[e] * AT(C, dm.eff_sp[e]);
                 if (kind == K_THREEBODY) {
                     c = M;
                     dcdM = 1.0;
@@ -312,10 +341,10 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                         const double lF = L / den;
                         F = exp(LN10 * lF);
                         if (JAC) {
-                            const double g = -2.0 * L * f / (den * den);
-                            dlF_dlP = g * nn / (Bd * Bd);
+                            const double gg = -2.0 * L * f / (den * den);
+                            dlF_dlP = gg * nn / (Bd * Bd);
                             const double df_dL = (-0.67 * Bd + 1.1762 * A) / (Bd * Bd);
-                            const double dlF_dL = 1.0 / den + g * df_dL;
+                            const double dlF_dL = 1.0 / den + gg * df_dL;
                             const double dFc = -(1.0 - al) * i3 * e3 - al * i1 * e1x + t2 * invT * invT * e2;
                             dlF_dT = dlF_dL * dFc / (Fc * LN10);
                         }
@@ -325,8 +354,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                     if (JAC) {
                         const double dc_dPr = F * ip * ip + F * ip * dlF_dlP;
                         dcdM = dc_dPr * rk;
-                        const double dlnPr = (fr_.b0 + fr_.theta0 * invT) * invT
-                                             - (bexp + th * invT) * invT;
+                        const double dlnPr = (fr_.b0 + fr_.theta0 * invT) * invT - (bexp + th * invT) * invT;
                         dcdT = dc_dPr * Pr * dlnPr + c * LN10 * dlF_dT;
                     }
                 }
@@ -335,7 +363,7 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) {
                 if (!((cmask >> a) & 1)) continue;
-                if (nu[a]) atomicAdd(&W[spc[a]], sg[a] * q);
+                if (nu[a]) atomicAdd(&AT(W, spc[a]), sg[a] * q);
             }
             if (!JAC) continue;
 
@@ -356,24 +384,19 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
             double Qb = 0.0, sQC = 0.0;
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) sQC += Qs[a] * cf[a];
-            for (int e = e0; e < e1; ++e) {
-                const int se = dm.eff_sp[e];
-                const double qe = QM * dm.eff_am1[e];
-                sQC += qe * C[se];
-            }
+            for (int e = e0; e < e1; ++e) sQC += QM * dm.eff_am1[e] * AT(C, dm.eff_sp[e]);
             if (w & INFO_BATH) {
-                // rates that depend on the bath gas: its partial Q_Ns, taken out
-                // of the sum over the other species
+                // rates that depend on the bath gas: its partial Q_Ns, taken
+                // out of the sum over the other species
 #pragma unroll
                 for (int a = 0; a < NSLOT; ++a)
                     if (spc[a] == bath) Qb += Qs[a];
                 for (int e = e0; e < e1; ++e)
                     if (dm.eff_sp[e] == bath) Qb += QM * dm.eff_am1[e];
-                sQC -= Qb * C[bath];
+                sQC -= Qb * AT(C, bath);
             }
             const double dqdT = qT - Ctot * invT * (Qb + QM);
-            const double dqdS = FORM == PJ_CONP ? -(sQC - Qb * (nsum * invV)) * invV
-                                                : (Qb + QM) * invRT;
+            const double dqdS = FORM == PJ_CONP ? -(sQC - Qb * (nsum * invV)) * invV : (Qb + QM) * invRT;
             const double dE = FORM == PJ_CONP ? dH : dH - dnu;
             const double dOm = rr.domega;
             racc[0] += dE * dqdT;
@@ -386,14 +409,14 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
             for (int b = 0; b < NSLOT; ++b) {
                 if (!((cmask >> b) & 1) || (b >= MAXSIDE && !any_rev)) continue;
                 if (nu[b] && (b < MAXSIDE || rev)) {
-                    atomicAdd(&TQ[spc[b]], dE * Qs[b]);
-                    atomicAdd(&SQ[spc[b]], dOm * Qs[b]);
+                    atomicAdd(&AT(TQ, spc[b]), dE * Qs[b]);
+                    atomicAdd(&AT(SQ, spc[b]), dOm * Qs[b]);
                 }
             }
             for (int e = e0; e < e1; ++e) {
                 const double qe = QM * dm.eff_am1[e];
-                atomicAdd(&TQ[dm.eff_sp[e]], dE * qe);
-                atomicAdd(&SQ[dm.eff_sp[e]], dOm * qe);
+                atomicAdd(&AT(TQ, dm.eff_sp[e]), dE * qe);
+                atomicAdd(&AT(SQ, dm.eff_sp[e]), dOm * qe);
             }
             // species rows; the slot table holds NOSLOT for pairs that do not
             // exist (empty slots, irreversible products, bath-gas columns)
@@ -404,17 +427,17 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                 if (!((cmask >> a) & 1)) continue;
                 const uint16_t rb = jr.rowbase[a];
                 if (rb == NOSLOT) continue;
-                atomicAdd(&J[rb], sg[a] * Vt);
-                atomicAdd(&J[rb + 1], sg[a] * Vs);
+                atomicAdd(&AT(J, rb), sg[a] * Vt);
+                atomicAdd(&AT(J, rb + 1), sg[a] * Vs);
 #pragma unroll
                 for (int b = 0; b < NSLOT; ++b) {
                     if (!((cmask >> b) & 1) || (b >= MAXSIDE && !any_rev)) continue;
                     const uint16_t sl = jr.slot[a * NSLOT + b];
-                    if (sl != NOSLOT) atomicAdd(&J[sl], sg[a] * Qs[b]);
+                    if (sl != NOSLOT) atomicAdd(&AT(J, sl), sg[a] * Qs[b]);
                 }
                 for (int e = e0; e < e1; ++e) {
                     const uint16_t sl = dm.effslot[(size_t)e * NSLOT + a];
-                    if (sl != NOSLOT) atomicAdd(&J[sl], sg[a] * QM * dm.eff_am1[e]);
+                    if (sl != NOSLOT) atomicAdd(&AT(J, sl), sg[a] * QM * dm.eff_am1[e]);
                 }
             }
             if (w & INFO_BATH) {
@@ -424,16 +447,17 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                     if (jr.rowbase[a] == NOSLOT) continue;
 #pragma unroll
                     for (int b = 0; b < NSLOT; ++b)
-                        if (spc[b] == bath && nu[b] && (b < MAXSIDE || rev)) atomicAdd(&B[spc[a]], sg[a] * Qs[b]);
+                        if (spc[b] == bath && nu[b] && (b < MAXSIDE || rev))
+                            atomicAdd(&AT(B, spc[a]), sg[a] * Qs[b]);
                     for (int e = e0; e < e1; ++e)
-                        if (dm.eff_sp[e] == bath) atomicAdd(&B[spc[a]], sg[a] * QM * dm.eff_am1[e]);
+                        if (dm.eff_sp[e] == bath) atomicAdd(&AT(B, spc[a]), sg[a] * QM * dm.eff_am1[e]);
                 }
             }
         }
         __syncthreads();
 
         // ---- source terms (Sec. 2.2)
-        double fsum[JAC ? 7 : 2];
+        double fsum[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         fsum[0] = 0.0;  // N' = sum e_k/(RT) wdot_k
         fsum[1] = 0.0;  // Omega
         if (JAC) {
@@ -441,23 +465,23 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
 #pragma unroll
             for (int q = 0; q < 4; ++q) fsum[3 + q] = racc[q];
         }
-        for (int k = tid; k < ns; k += nthr) {
-            const double wk = W[k];
-            const double ek = FORM == PJ_CONP ? H[k] : H[k] - 1.0;
+        for (int k = g; k < ns; k += G) {
+            const double wk = AT(W, k);
+            const double ek = FORM == PJ_CONP ? AT(H, k) : AT(H, k) - 1.0;
             fsum[0] += ek * wk;
             fsum[1] += dm.wfac[k] * wk;
-            if (JAC) fsum[2] += CP[k] * wk;
+            if (JAC) fsum[2] += AT(CP, k) * wk;
         }
-        block_sum(fsum, red, wave, nwave);
+        block_sum<S>(fsum, red, wave, nwave, s);
         const double Np = fsum[0], Om = fsum[1];
         const double Tdot = -T * Np / Dp;
         const double Sdot = FORM == PJ_CONP ? V * Tdot * invT + V * RU * T * Om / P
                                             : P * Tdot * invT + RU * T * Om;
-        if (dstate) {
-            for (int i = tid; i < N; i += nthr) {
-                const double v = i == 0 ? Tdot : i == 1 ? Sdot : V * W[i - 2];
-                if (LAYOUT == PJ_LAYOUT_F) dstate[(long)i * n + s] = v;
-                else dstate[s * (long)N + i] = v;
+        if (dstate && valid) {
+            for (int i = g; i < N; i += G) {
+                const double v = i == 0 ? Tdot : i == 1 ? Sdot : V * AT(W, i - 2);
+                if (LAYOUT == PJ_LAYOUT_F) dstate[(long)i * n + st] = v;
+                else dstate[st * (long)N + i] = v;
             }
         }
         if (!JAC) {
@@ -468,15 +492,16 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
         // ---- Jacobian: T and V/P rows, closure of the species rows
         {
             const double Scw = fsum[2], TT = fsum[3], TS = fsum[4], ST = fsum[5], SS = fsum[6];
-            const double cpb = CP[bath];
+            const double cpb = AT(CP, bath);
             const double Csum = nsum * invV;
             const double dDdT = dDpdT - cpb * Ctot * invT;
-            const double dDdS = FORM == PJ_CONP ? -((Dp - cpb * C[bath]) - cpb * Csum) * invV
+            const double dDdS = FORM == PJ_CONP ? -((Dp - cpb * AT(C, bath)) - cpb * Csum) * invV
                                                 : cpb / (RU * T);
             const double J00 = -(T * TT + Scw + Tdot * dDdT) / Dp;
             const double J01 = -(T * TS + Tdot * dDdS) / Dp;
             const double RTP = RU * T / P;
-            for (int j = tid; j < N; j += nthr) {
+            const double tqb = AT(TQ, bath), sqb = AT(SQ, bath);
+            for (int j = g; j < N && valid; j += G) {
                 double j0, j1;
                 if (j == 0) {
                     j0 = J00;
@@ -489,25 +514,25 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
                                          : Tdot * invT + P * invT * J01 + RU * T * SS;
                 } else {
                     const int k = j - 2;
-                    j0 = -(T * (TQ[k] - TQ[bath]) + Tdot * (CP[k] - cpb)) * invV / Dp;
-                    j1 = FORM == PJ_CONP ? V * invT * j0 + RTP * (SQ[k] - SQ[bath])
-                                         : P * invT * j0 + RU * T * (SQ[k] - SQ[bath]) * invV;
+                    j0 = -(T * (AT(TQ, k) - tqb) + Tdot * (AT(CP, k) - cpb)) * invV / Dp;
+                    j1 = FORM == PJ_CONP ? V * invT * j0 + RTP * (AT(SQ, k) - sqb)
+                                         : P * invT * j0 + RU * T * (AT(SQ, k) - sqb) * invV;
                 }
                 if (MODE == MODE_SPARSE) {
                     if (LAYOUT == PJ_LAYOUT_F) {
-                        jac[(long)j * n + s] = j0;
-                        jac[(long)(N + j) * n + s] = j1;
+                        jac[(long)j * n + st] = j0;
+                        jac[(long)(N + j) * n + st] = j1;
                     } else {
-                        jac[s * (long)nnz + j] = j0;
-                        jac[s * (long)nnz + N + j] = j1;
+                        jac[st * (long)nnz + j] = j0;
+                        jac[st * (long)nnz + N + j] = j1;
                     }
                 } else {
                     if (LAYOUT == PJ_LAYOUT_F) {
-                        jac[s + n * ((long)N * j)] = j0;
-                        jac[s + n * (1 + (long)N * j)] = j1;
+                        jac[st + n * ((long)N * j)] = j0;
+                        jac[st + n * (1 + (long)N * j)] = j1;
                     } else {
-                        jac[s * (long)N * N + j] = j0;
-                        jac[s * (long)N * N + N + j] = j1;
+                        jac[st * (long)N * N + j] = j0;
+                        jac[st * (long)N * N + N + j] = j1;
                     }
                 }
             }
@@ -515,43 +540,58 @@ __global__ void __launch_bounds__(256) pj_kernel(const DevMech dm, const long n,
             for (int d = 0; d < dm.n_dense_rows; ++d) {
                 const int k = dm.dense_rows[d];
                 const int r0 = dm.row_ptr[2 + k] + 2, r1 = dm.row_ptr[3 + k];
-                const double bk = B[k];
-                for (int e = r0 + tid; e < r1; e += nthr) J[e] -= bk;
+                const double bk = AT(B, k);
+                for (int e = r0 + g; e < r1; e += G) AT(J, e) -= bk;
             }
             if (FORM == PJ_CONP) {
                 // d(V wdot_k)/dV = wdot_k + V dwdot_k/dV
-                for (int k = tid; k < ns - 1; k += nthr) J[dm.row_ptr[2 + k] + 1] += W[k];
+                for (int k = g; k < ns - 1; k += G) AT(J, dm.row_ptr[2 + k] + 1) += AT(W, k);
             }
         }
         __syncthreads();
 
         if (MODE == MODE_SPARSE) {
-            for (int e = 2 * N + tid; e < nnz; e += nthr) {
-                if (LAYOUT == PJ_LAYOUT_F) jac[(long)e * n + s] = J[e];
-                else jac[s * (long)nnz + e] = J[e];
+            if (LAYOUT == PJ_LAYOUT_F) {
+                // S consecutive states of one slot are contiguous
+                if (valid)
+                    for (int e = 2 * N + g; e < nnz; e += G) jac[(long)e * n + st] = AT(J, e);
+            } else {
+                // one state's slots are contiguous: threads of one state take
+                // consecutive slots
+                const int s2 = tid / G, g2 = tid % G;
+                const long st2 = qg * S + s2;
+                if (st2 < n)
+                    for (int e = 2 * N + g2; e < nnz; e += G) jac[st2 * (long)nnz + e] = J[(size_t)e * S + s2];
             }
         } else {
+            const int s2 = tid / G, g2 = tid % G;
+            const long st2 = qg * S + s2;
             for (int i = 2; i < N; ++i) {
-                for (int j = tid; j < N; j += nthr) ROW[j] = 0.0;
+                for (int j = g; j < N; j += G) AT(ROW, j) = 0.0;
                 __syncthreads();
                 const int r0 = dm.row_ptr[i], r1 = dm.row_ptr[i + 1];
-                for (int e = r0 + tid; e < r1; e += nthr) ROW[dm.col_idx[e]] = J[e];
+                for (int e = r0 + g; e < r1; e += G) AT(ROW, dm.col_idx[e]) = AT(J, e);
                 __syncthreads();
-                for (int j = tid; j < N; j += nthr) {
-                    if (LAYOUT == PJ_LAYOUT_F) jac[s + n * ((long)i + (long)N * j)] = ROW[j];
-                    else jac[s * (long)N * N + (long)i * N + j] = ROW[j];
+                if (LAYOUT == PJ_LAYOUT_F) {
+                    if (valid)
+                        for (int j = g; j < N; j += G) jac[st + n * ((long)i + (long)N * j)] = AT(ROW, j);
+                } else {
+                    if (st2 < n)
+                        for (int j = g2; j < N; j += G)
+                            jac[st2 * (long)N * N + (long)i * N + j] = ROW[(size_t)j * S + s2];
                 }
                 __syncthreads();
             }
         }
         __syncthreads();
     }
+#undef AT
 }
 
-template <int FORM, int LAYOUT, int MODE>
+template <int FORM, int LAYOUT, int MODE, int S>
 static hipError_t launch_t(const DevMech& dm, int64_t n, const double* state, const double* param,
-                           double* dstate, double* jac, int wps, int64_t lds, hipStream_t stream) {
-    auto k = pj_kernel<FORM, LAYOUT, MODE>;
+                           double* dstate, double* jac, int waves, int64_t lds, hipStream_t stream) {
+    auto k = pj_kernel<FORM, LAYOUT, MODE, S>;
     if (lds > 65536) {
         // allow the kernel the device's whole LDS per workgroup
         int dev = 0, mx = 0;
@@ -560,26 +600,30 @@ static hipError_t launch_t(const DevMech& dm, int64_t n, const double* state, co
         if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
         if (e != hipSuccess) return e;
     }
-    // one workgroup per state, rounded down to a multiple of 8 (the XCD count)
-    int64_t grid = n < (1 << 30) ? n : (1 << 30);
+    // one workgroup per group of S states, rounded down to a multiple of 8
+    // (the XCD count)
+    const int64_t groups = (n + S - 1) / S;
+    int64_t grid = groups < (1 << 30) ? groups : (1 << 30);
     if (grid >= 8) grid &= ~(int64_t)7;
-    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * wps), (size_t)lds, stream, dm, (long)n,
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * waves), (size_t)lds, stream, dm, (long)n,
                        state, param, dstate, jac);
     return hipGetLastError();
 }
 
-hipError_t launch(const DevMech& dm, int mode, int form, int layout, int64_t n, const double* state,
-                  const double* param, double* dstate, double* jac, int wps, int64_t lds,
-                  hipStream_t stream) {
-#define PJ_CASE(F, L, M)                                                                   \
-    if (form == F && layout == L && mode == M)                                             \
-        return launch_t<F, L, M>(dm, n, state, param, dstate, jac, wps, lds, stream);
-#define PJ_MODES(F, L) PJ_CASE(F, L, MODE_SRC) PJ_CASE(F, L, MODE_SPARSE) PJ_CASE(F, L, MODE_DENSE)
+hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
+                  const double* state, const double* param, double* dstate, double* jac, int waves,
+                  int64_t lds, hipStream_t stream) {
+#define PJ_CASE(F, L, M, SS)                                                                 \
+    if (form == F && layout == L && mode == M && S == SS)                                    \
+        return launch_t<F, L, M, SS>(dm, n, state, param, dstate, jac, waves, lds, stream);
+#define PJ_S(F, L, M) PJ_CASE(F, L, M, 1) PJ_CASE(F, L, M, 2) PJ_CASE(F, L, M, 4)
+#define PJ_MODES(F, L) PJ_S(F, L, MODE_SRC) PJ_S(F, L, MODE_SPARSE) PJ_S(F, L, MODE_DENSE)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_F)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_C)
     PJ_MODES(PJ_CONV, PJ_LAYOUT_F)
     PJ_MODES(PJ_CONV, PJ_LAYOUT_C)
 #undef PJ_MODES
+#undef PJ_S
 #undef PJ_CASE
     return hipErrorInvalidValue;
 }

@@ -411,7 +411,8 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
         R.eff1 = (uint32_t)eff_sp.size();
     }
     // per 64-reaction chunk: which slot positions any of its reactions uses
-    // (bits 0..5), whether any is reversible (bit 6) or has third bodies (bit 7)
+    // (bits 0..5), whether any is reversible (bit 6) or has third bodies (bit 7);
+    // copied into every record of the chunk
     std::vector<uint32_t> chunk((size_t)nr_pad / 64, 0);
     for (int p = 0; p < nr; ++p) {
         uint32_t& cm = chunk[p / 64];
@@ -419,6 +420,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
         if (rec[p].info & INFO_REV) cm |= 1u << 6;
         if (rec[p].eff1 > rec[p].eff0) cm |= 1u << 7;
     }
+    for (int p = 0; p < nr_pad; ++p) rec[p].chunk = chunk[p / 64];
     std::vector<int32_t> dense_rows;
     for (int k = 0; k < ns; ++k) if (dense_row[k]) dense_rows.push_back(k);
     std::vector<uint16_t> col16(m.col_idx.begin(), m.col_idx.end());
@@ -436,7 +438,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     size_t o_effs = place(eff_sp.size() * 2), o_effa = place(eff_am1.size() * 8),
            o_effslot = place(effslot.size() * 2);
     size_t o_rowp = place(m.row_ptr.size() * 4), o_col = place(col16.size() * 2),
-           o_dr = place(dense_rows.size() * 4), o_chunk = place(chunk.size() * 4);
+           o_dr = place(dense_rows.size() * 4);
     std::vector<unsigned char> host(total, 0);
     auto put = [&](size_t off, const void* src, size_t bytes) { std::memcpy(host.data() + off, src, bytes); };
     put(o_th, th.data(), th.size() * sizeof(ThermoRec));
@@ -451,7 +453,6 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     put(o_rowp, m.row_ptr.data(), m.row_ptr.size() * 4);
     put(o_col, col16.data(), col16.size() * 2);
     put(o_dr, dense_rows.data(), dense_rows.size() * 4);
-    put(o_chunk, chunk.data(), chunk.size() * 4);
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) { err = "no HIP device"; return PJ_E_DEVICE; }
@@ -485,16 +486,16 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.row_ptr = (const int32_t*)P(o_rowp);
     dm.col_idx = (const uint16_t*)P(o_col);
     dm.dense_rows = (const int32_t*)P(o_dr);
-    dm.chunk = (const uint32_t*)P(o_chunk);
 
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         lds_max = 65536;
     m.lds_max = lds_max;
-    m.lds_src = lds_bytes(dm, MODE_SRC);
-    m.lds_jac = lds_bytes(dm, MODE_SPARSE);
-    m.lds_dense = lds_bytes(dm, MODE_DENSE);
-    if (m.lds_src > lds_max) { err = "source-term working set exceeds the LDS of one workgroup"; return PJ_E_UNSUPPORTED; }
+    if (lds_bytes(dm, MODE_SRC, 1) > lds_max) {
+        err = "source-term working set exceeds the LDS of one workgroup";
+        return PJ_E_UNSUPPORTED;
+    }
+    choose_launch(m);
     return PJ_OK;
 }
 

@@ -96,8 +96,8 @@ def run_case(torch, api, path, x_c, p, form, layout, dense=True, sample=None):
         Jd = api.dense_as_sij(jd_g, layout).cpu().numpy()[idx]
         check_jac(Jd, J_o, J_s, "pj_eval_jacobian_dense")
         assert np.all(Jd[:, ~P] == 0.0)
-        if mech.waves_per_state(True) == 1:
-            # one wave per state accumulates in program order: same bits as the sparse call
+        if mech.launch_shape(1)[1] == 1 and mech.launch_shape(1) == mech.launch_shape(2):
+            # one wave per workgroup accumulates in program order: same bits as the sparse call
             np.testing.assert_array_equal(Jd, Jg)
     return mech
 
@@ -136,25 +136,30 @@ def test_larger_mechanisms(torch_cuda, api, name, n, form, layout, mech_dir):
     run_case(torch_cuda, api, path, x, p, form, layout, dense=(name != "ns360" or layout == "C"))
 
 
-def test_waves_per_state_variants_agree(torch_cuda, api, mech_dir):
+@pytest.mark.parametrize("layout", ["F", "C"])
+def test_launch_shapes_agree(torch_cuda, api, layout, mech_dir):
+    """Every launch shape (states per workgroup x waves per workgroup) gives
+    results inside the gates, including a ragged last group of states."""
     torch = torch_cuda
     m, path = workload_file("ns111", mech_dir)
-    st = synth.make_states(m, 50, 5)
-    x, p = synth.pack_state(st, "conp", "F")
+    st = synth.make_states(m, 51, 5)
+    x, p = synth.pack_state(st, "conp", layout)
     o = oracle.Oracle(path)
     xc, pc = synth.pack_state(st, "conp", "C")
     J_o, J_s = o.jacobian(xc, pc, "conp", scale=True)
     f_o, f_s = o.source(xc, pc, "conp", scale=True)
     mech = api.load_mechanism(path)
     xs, ps = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda()
-    for wps in (1, 2, 4):
-        note(f"waves_per_state={wps}")
-        mech.set_waves_per_state(wps)
-        f = api.eval_source(mech, xs, ps, "conp", "F")
-        j = api.eval_jacobian_sparse(mech, xs, ps, "conp", "F")
+    for S, w in [(1, 1), (1, 2), (1, 4), (2, 2), (4, 1), (4, 4), (4, 8), (0, 0)]:
+        mech.set_launch(S, w)
+        note(f"launch S={S} waves={w} -> {mech.launch_shape(0)} {mech.launch_shape(1)}")
+        f = api.eval_source(mech, xs, ps, "conp", layout)
+        d = torch.empty_like(xs)
+        j = api.eval_jacobian_sparse(mech, xs, ps, "conp", layout, dstate=d)
         torch.cuda.synchronize()
-        check_source(f.cpu().numpy().T, f_o, f_s, f"wps={wps}")
-        check_jac(api.sparse_to_dense(mech, j.cpu().numpy(), "F"), J_o, J_s, f"wps={wps}")
+        check_source(src_to_c(f, layout), f_o, f_s, f"S={S} w={w} source")
+        check_source(src_to_c(d, layout), f_o, f_s, f"S={S} w={w} fused source")
+        check_jac(api.sparse_to_dense(mech, j.cpu().numpy(), layout), J_o, J_s, f"S={S} w={w}")
 
 
 def test_one_wave_per_state_is_bitwise_reproducible(torch_cuda, api, mech_dir):
@@ -163,12 +168,14 @@ def test_one_wave_per_state_is_bitwise_reproducible(torch_cuda, api, mech_dir):
     st = synth.make_states(m, 500, 11)
     x, p = synth.pack_state(st, "conv", "C")
     mech = api.load_mechanism(path)
-    mech.set_waves_per_state(1)
     xs, ps = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda()
-    a = api.eval_jacobian_sparse(mech, xs, ps, "conv", "C")
-    b = api.eval_jacobian_sparse(mech, xs, ps, "conv", "C")
-    torch.cuda.synchronize()
-    assert torch.equal(a, b)
+    for S in (1, 4):
+        # one wave per workgroup: every LDS addition happens in program order
+        mech.set_launch(S, 1)
+        a = api.eval_jacobian_sparse(mech, xs, ps, "conv", "C")
+        b = api.eval_jacobian_sparse(mech, xs, ps, "conv", "C")
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
 
 
 def test_edge_sizes(torch_cuda, api, mech_dir):
