@@ -37,15 +37,17 @@ __host__ __device__ inline int info_kind(uint32_t w) { return (w >> 24) & 0x3; }
 // read with 16-byte vector loads.
 struct alignas(16) RxnRec {          // 80 B
     uint32_t info;                   // see INFO_* above
-    uint32_t eff0, eff1;             // this reaction's range in the efficiency list
+    uint32_t eff;                    // index of this reaction's EffRec (third bodies)
+    uint32_t neff;                   // number of third bodies with efficiency != 1
     uint32_t chunk;                  // slot positions used in this reaction's 64-reaction
-                                     // chunk (bits 0..5), any reversible (bit 6)
+                                     // chunk (bits 0..5), any reversible (bit 6), the
+                                     // largest neff in the chunk (bits 8..11)
     uint16_t sp[6];                  // species of slot a (Ns = empty slot)
     uint16_t pad1[2];
     double lnA, b, theta;            // Arrhenius (k_inf for falloff)
     double dnu;                      // sum of net coefficients
     double domega;                   // sum_{k<Ns} nu_ki (1 - W_k/W_Ns)
-    double pad2;
+    double bam1;                     // efficiency - 1 of the bath gas (0 if none)
 };
 struct alignas(16) FallRec {         // 64 B, falloff reactions
     double lnA0, b0, theta0;         // low-pressure limit
@@ -58,7 +60,16 @@ struct alignas(16) JacRec {          // 96 B, Jacobian scatter slots (NOSLOT = n
     uint16_t slot[36];               // CSR slot of (row of slot a, column of slot b), [a*6+b]
     uint16_t pad1[4];
 };
-static_assert(sizeof(RxnRec) == 80 && sizeof(FallRec) == 64 && sizeof(JacRec) == 96, "record sizes");
+constexpr int MAXEFF = 8;             // third bodies with efficiency != 1 per reaction
+struct alignas(16) EffRec {          // 176 B, third-body reactions; record 0 is
+                                     // all-empty and serves the elementary ones
+    uint16_t sp[MAXEFF];             // species (Ns = unused entry)
+    double am1[MAXEFF];              // efficiency - 1
+    uint16_t slot[6][MAXEFF];        // CSR slot of (row of reaction slot a, column of
+                                     // entry e) at [a][e]
+};
+static_assert(sizeof(RxnRec) == 80 && sizeof(FallRec) == 64 && sizeof(JacRec) == 96 &&
+              sizeof(EffRec) == 176, "record sizes");
 
 // Thermodynamic coefficients of one species and one temperature range.
 constexpr int TH_N = 18;
@@ -81,9 +92,7 @@ struct DevMech {
     const RxnRec* rec;        // [nr_pad]
     const FallRec* fall;      // [nr_pad]
     const JacRec* jrec;       // [nr_pad]
-    const uint16_t* eff_sp;   // [n_eff]
-    const double* eff_am1;    // [n_eff] efficiency - 1
-    const uint16_t* effslot;  // [n_eff][6] slot (row of slot a, column of the third body)
+    const EffRec* effrec;     // [1 + reactions with third bodies]
 
     // pattern
     const int32_t* row_ptr;   // [N + 1]

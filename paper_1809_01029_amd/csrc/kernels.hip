@@ -140,6 +140,31 @@ __device__ inline T load_rec(const T* src) {
     return u.t;
 }
 
+// Species (two 16-bit entries per word) and efficiency - 1 of the first
+// n (uniform over the wave) third bodies of a reaction; the rest read as 0
+__device__ inline void load_eff(const EffRec* r, int n, uint32_t (&sp)[MAXEFF / 2],
+                                double (&am1)[MAXEFF]) {
+    const uint4* q = reinterpret_cast<const uint4*>(r);
+    const uint4 v = q[0];
+    sp[0] = v.x;
+    sp[1] = v.y;
+    sp[2] = v.z;
+    sp[3] = v.w;
+#pragma unroll
+    for (int h = 0; h < MAXEFF / 2; ++h) {
+        if (2 * h < n) {
+            const uint4 u = q[1 + h];
+            am1[2 * h] = __hiloint2double(u.y, u.x);
+            am1[2 * h + 1] = __hiloint2double(u.w, u.z);
+        } else {
+            am1[2 * h] = am1[2 * h + 1] = 0.0;
+        }
+    }
+}
+__device__ inline int eff_species(const uint32_t (&sp)[MAXEFF / 2], int e) {
+    return (sp[e >> 1] >> (16 * (e & 1))) & 0xFFFF;
+}
+
 // c^nu and d(c^nu)/dc for nu in {0, 1, 2} with selects instead of branches;
 // an empty slot (nu = 0) reads the sentinel concentration 1, giving f = 1
 __device__ inline void powd(double c, int nu, double& f, double& d) {
@@ -312,12 +337,25 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
             const double Rr = kr * Pb;
             const double R = Rf - Rr;
 
+            // third bodies with efficiency != 1, held in registers for the
+            // whole iteration; the count is the chunk's largest (uniform over
+            // the wave), unused entries have efficiency - 1 = 0
+            const int neffc = (cmask >> 8) & 0xF;
+            const int neff = (int)rr.neff;
+            double Meff = 0.0;   // sum_k (alpha_k - 1) [C]_k
+            if (neffc) {
+                uint32_t esp[MAXEFF / 2];
+                double am1[MAXEFF];
+                load_eff(dm.effrec + rr.eff, neffc, esp, am1);
+#pragma unroll
+                for (int e = 0; e < MAXEFF; ++e)
+                    if (e < neffc) Meff += am1[e] * AT(C, eff_species(esp, e));
+            }
+
             // pressure modification
             double c = 1.0, dcdM = 0.0, dcdT = 0.0;
-            const int e0 = (int)rr.eff0, e1 = (int)rr.eff1;
             if (kind != K_ELEM) {
-                double M = Ctot;
-                for (int e = e0; e < e1; ++e) M += dm.eff_am1[e] * AT(C, dm.eff_sp[e]);
+                const double M = Ctot + Meff;
                 if (kind == K_THREEBODY) {
                     c = M;
                     dcdM = 1.0;
@@ -384,15 +422,15 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
             double Qb = 0.0, sQC = 0.0;
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) sQC += Qs[a] * cf[a];
-            for (int e = e0; e < e1; ++e) sQC += QM * dm.eff_am1[e] * AT(C, dm.eff_sp[e]);
+            sQC += QM * Meff;
+            const double bam1 = rr.bam1;
             if (w & INFO_BATH) {
                 // rates that depend on the bath gas: its partial Q_Ns, taken
                 // out of the sum over the other species
 #pragma unroll
                 for (int a = 0; a < NSLOT; ++a)
                     if (spc[a] == bath) Qb += Qs[a];
-                for (int e = e0; e < e1; ++e)
-                    if (dm.eff_sp[e] == bath) Qb += QM * dm.eff_am1[e];
+                Qb += QM * bam1;
                 sQC -= Qb * AT(C, bath);
             }
             const double dqdT = qT - Ctot * invT * (Qb + QM);
@@ -413,10 +451,20 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
                     atomicAdd(&AT(SQ, spc[b]), dOm * Qs[b]);
                 }
             }
-            for (int e = e0; e < e1; ++e) {
-                const double qe = QM * dm.eff_am1[e];
-                atomicAdd(&AT(TQ, dm.eff_sp[e]), dE * qe);
-                atomicAdd(&AT(SQ, dm.eff_sp[e]), dOm * qe);
+            // third-body partials Q_k = Q_M (alpha_k - 1), record read again
+            // (cache hit) rather than held in registers across the iteration
+            uint32_t esp[MAXEFF / 2];
+            double qe[MAXEFF];
+            if (neffc) {
+                load_eff(dm.effrec + rr.eff, neffc, esp, qe);
+#pragma unroll
+                for (int e = 0; e < MAXEFF; ++e) {
+                    qe[e] *= QM;
+                    if (e < neffc && e < neff) {
+                        atomicAdd(&AT(TQ, eff_species(esp, e)), dE * qe[e]);
+                        atomicAdd(&AT(SQ, eff_species(esp, e)), dOm * qe[e]);
+                    }
+                }
             }
             // species rows; the slot table holds NOSLOT for pairs that do not
             // exist (empty slots, irreversible products, bath-gas columns)
@@ -435,9 +483,16 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
                     const uint16_t sl = jr.slot[a * NSLOT + b];
                     if (sl != NOSLOT) atomicAdd(&AT(J, sl), sg[a] * Qs[b]);
                 }
-                for (int e = e0; e < e1; ++e) {
-                    const uint16_t sl = dm.effslot[(size_t)e * NSLOT + a];
-                    if (sl != NOSLOT) atomicAdd(&AT(J, sl), sg[a] * QM * dm.eff_am1[e]);
+                if (neffc) {
+                    // third-body columns of this row: one 16-byte load
+                    const uint4 u = reinterpret_cast<const uint4*>((dm.effrec + rr.eff)->slot[a])[0];
+                    const uint32_t sw[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (int e = 0; e < MAXEFF; ++e) {
+                        if (e >= neffc) break;
+                        const uint32_t sl = (sw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+                        if (sl != NOSLOT) atomicAdd(&AT(J, sl), sg[a] * qe[e]);
+                    }
                 }
             }
             if (w & INFO_BATH) {
@@ -449,8 +504,7 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
                     for (int b = 0; b < NSLOT; ++b)
                         if (spc[b] == bath && nu[b] && (b < MAXSIDE || rev))
                             atomicAdd(&AT(B, spc[a]), sg[a] * Qs[b]);
-                    for (int e = e0; e < e1; ++e)
-                        if (dm.eff_sp[e] == bath) atomicAdd(&AT(B, spc[a]), sg[a] * QM * dm.eff_am1[e]);
+                    if (bam1 != 0.0) atomicAdd(&AT(B, spc[a]), sg[a] * QM * bam1);
                 }
             }
         }

@@ -139,6 +139,14 @@ pj_status parse_description(const char* path, Mechanism& m, std::string& err) {
     return PJ_OK;
 }
 
+std::vector<std::pair<int, double>> enhanced(const Mechanism::Rxn& r) {
+    std::map<int, double> a;
+    for (auto& e : r.eff) a[e.first] = e.second;
+    std::vector<std::pair<int, double>> out;
+    for (auto& e : a) if (e.second != 1.0) out.push_back(e);
+    return out;
+}
+
 pj_status validate(const Mechanism& m, std::string& err) {
     for (int i = 0; i < m.nr; ++i) {
         const auto& r = m.rx[i];
@@ -154,6 +162,10 @@ pj_status validate(const Mechanism& m, std::string& err) {
         }
         for (auto& b : r.prod)
             if (b.second > 2) { err = "coefficient above 2 in reaction " + std::to_string(i); return PJ_E_UNSUPPORTED; }
+        if (enhanced(r).size() > (size_t)MAXEFF) {
+            err = "more than " + std::to_string(MAXEFF) + " third-body efficiencies in reaction " + std::to_string(i);
+            return PJ_E_UNSUPPORTED;
+        }
         for (int e = 0; e < 4; ++e) {
             long lhs = 0, rhs = 0;
             for (auto& a : r.reac) lhs += (long)a.second * m.comp[(size_t)a.first * 4 + e];
@@ -165,14 +177,6 @@ pj_status validate(const Mechanism& m, std::string& err) {
 }
 
 // third-body efficiencies different from one, merged per species
-std::vector<std::pair<int, double>> enhanced(const Mechanism::Rxn& r) {
-    std::map<int, double> a;
-    for (auto& e : r.eff) a[e.first] = e.second;
-    std::vector<std::pair<int, double>> out;
-    for (auto& e : a) if (e.second != 1.0) out.push_back(e);
-    return out;
-}
-
 bool depends_on_bath(const Mechanism& m, const Mechanism::Rxn& r) {
     int bath = m.ns - 1;
     for (auto& a : r.reac) if (a.first == bath) return true;
@@ -278,9 +282,13 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     std::memset(rec.data(), 0, rec.size() * sizeof(RxnRec));
     std::memset(fall.data(), 0, fall.size() * sizeof(FallRec));
     std::memset(jrec.data(), 0xFF, jrec.size() * sizeof(JacRec));
-    std::vector<uint16_t> eff_sp;
-    std::vector<double> eff_am1;
-    std::vector<uint16_t> effslot;
+    std::vector<EffRec> effrec(1);
+    auto empty_eff = [&](EffRec& E) {
+        std::memset(&E, 0, sizeof(E));
+        std::memset(E.slot, 0xFF, sizeof(E.slot));
+        for (int q = 0; q < MAXEFF; ++q) E.sp[q] = (uint16_t)ns;
+    };
+    empty_eff(effrec[0]);
     std::vector<char> dense_row(ns, 0);
     // Slot positions.  The lanes of a wave handle 64 consecutive reactions
     // and scatter slot a of every reaction in the same instruction, so a
@@ -341,7 +349,8 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     for (int p = 0; p < nr_pad; ++p) {
         RxnRec& R = rec[p];
         for (int a = 0; a < NSLOT; ++a) R.sp[a] = (uint16_t)ns;
-        R.eff0 = R.eff1 = (uint32_t)eff_sp.size();
+        R.eff = 0;
+        R.neff = 0;
         if (p >= nr) continue;
         const auto& r = m.rx[m.order[p]];
         int spa[NSLOT], nua[NSLOT];
@@ -394,37 +403,42 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
             }
         }
         if (r.kind != K_ELEM) {
+            EffRec E;
+            empty_eff(E);
+            int ne = 0;
             for (auto& e : enhanced(r)) {
-                eff_sp.push_back((uint16_t)e.first);
-                eff_am1.push_back(e.second - 1.0);
+                E.sp[ne] = (uint16_t)e.first;
+                E.am1[ne] = e.second - 1.0;
+                if (e.first == bath) R.bam1 = e.second - 1.0;
                 for (int a = 0; a < NSLOT; ++a) {
-                    uint16_t sl = NOSLOT;
                     if (nua[a] && spa[a] != bath && e.first != bath) {
                         int f = csr_find(m, 2 + spa[a], 2 + e.first);
                         if (f < 0) { err = "internal: pattern misses a third-body entry"; return PJ_E_UNSUPPORTED; }
-                        sl = (uint16_t)f;
+                        E.slot[a][ne] = (uint16_t)f;
                     }
-                    effslot.push_back(sl);
                 }
+                ++ne;
             }
+            R.eff = (uint32_t)effrec.size();
+            R.neff = (uint32_t)ne;
+            effrec.push_back(E);
         }
-        R.eff1 = (uint32_t)eff_sp.size();
     }
     // per 64-reaction chunk: which slot positions any of its reactions uses
-    // (bits 0..5), whether any is reversible (bit 6) or has third bodies (bit 7);
-    // copied into every record of the chunk
+    // (bits 0..5), whether any is reversible (bit 6), and the largest number of
+    // third bodies of its reactions (bits 8..11); copied into every record
     std::vector<uint32_t> chunk((size_t)nr_pad / 64, 0);
     for (int p = 0; p < nr; ++p) {
         uint32_t& cm = chunk[p / 64];
         for (int a = 0; a < NSLOT; ++a) if (NUA[p][a]) cm |= 1u << a;
         if (rec[p].info & INFO_REV) cm |= 1u << 6;
-        if (rec[p].eff1 > rec[p].eff0) cm |= 1u << 7;
+        const uint32_t ne = std::max((cm >> 8) & 0xFu, rec[p].neff);
+        cm = (cm & ~(0xFu << 8)) | (ne << 8);
     }
     for (int p = 0; p < nr_pad; ++p) rec[p].chunk = chunk[p / 64];
     std::vector<int32_t> dense_rows;
     for (int k = 0; k < ns; ++k) if (dense_row[k]) dense_rows.push_back(k);
     std::vector<uint16_t> col16(m.col_idx.begin(), m.col_idx.end());
-    if (eff_sp.empty()) { eff_sp.push_back(0); eff_am1.push_back(0.0); effslot.assign(NSLOT, NOSLOT); }
     const int n_dense = (int)dense_rows.size();
     if (dense_rows.empty()) dense_rows.push_back(-1);
 
@@ -435,8 +449,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
            o_wfac = place(wfac.size() * 8);
     size_t o_rec = place(rec.size() * sizeof(RxnRec)), o_fall = place(fall.size() * sizeof(FallRec)),
            o_jrec = place(jrec.size() * sizeof(JacRec));
-    size_t o_effs = place(eff_sp.size() * 2), o_effa = place(eff_am1.size() * 8),
-           o_effslot = place(effslot.size() * 2);
+    size_t o_eff = place(effrec.size() * sizeof(EffRec));
     size_t o_rowp = place(m.row_ptr.size() * 4), o_col = place(col16.size() * 2),
            o_dr = place(dense_rows.size() * 4);
     std::vector<unsigned char> host(total, 0);
@@ -447,9 +460,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     put(o_rec, rec.data(), rec.size() * sizeof(RxnRec));
     put(o_fall, fall.data(), fall.size() * sizeof(FallRec));
     put(o_jrec, jrec.data(), jrec.size() * sizeof(JacRec));
-    put(o_effs, eff_sp.data(), eff_sp.size() * 2);
-    put(o_effa, eff_am1.data(), eff_am1.size() * 8);
-    put(o_effslot, effslot.data(), effslot.size() * 2);
+    put(o_eff, effrec.data(), effrec.size() * sizeof(EffRec));
     put(o_rowp, m.row_ptr.data(), m.row_ptr.size() * 4);
     put(o_col, col16.data(), col16.size() * 2);
     put(o_dr, dense_rows.data(), dense_rows.size() * 4);
@@ -480,9 +491,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.rec = (const RxnRec*)P(o_rec);
     dm.fall = (const FallRec*)P(o_fall);
     dm.jrec = (const JacRec*)P(o_jrec);
-    dm.eff_sp = (const uint16_t*)P(o_effs);
-    dm.eff_am1 = (const double*)P(o_effa);
-    dm.effslot = (const uint16_t*)P(o_effslot);
+    dm.effrec = (const EffRec*)P(o_eff);
     dm.row_ptr = (const int32_t*)P(o_rowp);
     dm.col_idx = (const uint16_t*)P(o_col);
     dm.dense_rows = (const int32_t*)P(o_dr);
