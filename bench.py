@@ -6,11 +6,16 @@ thermodynamics, rate constants, pressure modification, equilibrium constants,
 rates of progress, production rates, source terms, analytical Jacobian on the
 CSR pattern) over one batch of synthetic states already resident in HBM.  The
 default workload is the 111-species / 784-reaction synthetic mechanism at
-262,144 states, constant pressure, layout F.
+262,144 states, constant pressure, layout C (each state's values contiguous).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
+
+``--copy-calibration`` instead runs a plain device copy of known size, the
+reference that scales the rocprofv3 FETCH_SIZE / WRITE_SIZE readings into
+bytes.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,6 +35,53 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources that decide the kernel's memory traffic; a traffic figure measured
+# with other versions of them is not reported.
+KERNEL_SOURCES = ["paper_1809_01029_amd/csrc/kernels.hip", "paper_1809_01029_amd/csrc/internal.h",
+                  "paper_1809_01029_amd/csrc/mech.cpp", "paper_1809_01029_amd/csrc/api.cpp"]
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, form, layout, n):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this workload, or None if there is none or the kernel sources changed
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"pj_kernel_{workload}_{form}_{layout}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv.get("kernel_sources_sha256") != kernel_sources_sha256() or int(kv["n_states"]) != n:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of ``nbytes``, ``reps`` times."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -38,16 +90,22 @@ def main():
     ap.add_argument("--workload", default="ns111")
     ap.add_argument("--n-states", type=int, default=0, help="override the workload's state count")
     ap.add_argument("--form", default="conp", choices=["conp", "conv"])
-    ap.add_argument("--layout", default="F", choices=["F", "C"])
+    ap.add_argument("--layout", default="C", choices=["F", "C"])
     ap.add_argument("--cpu-sample", type=int, default=2048, help="states timed on the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (traffic-counter reference)")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); states are independent, "
               "so more GPUs would each run this same benchmark on their own share.", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
@@ -99,9 +157,10 @@ def main():
     # CSR values out (mechanism tables and intermediates excluded)
     bytes_state = 8 * (N + 1) + 8 * N + 8 * nnz
     achieved = bytes_state * n / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, args.form, args.layout, n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_state": bytes_state}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_state": bytes_state, "algorithmic_bytes_per_launch": bytes_state * n}
 
     variants = {}
     if not args.no_variants:
@@ -171,7 +230,8 @@ def main():
                                f"fused source terms + sparse CSR Jacobian",
                    "n_species": m.n_species, "n_reactions": m.n_reactions, "n_states": n, "nnz": nnz,
                    "form": args.form, "layout": args.layout,
-                   "waves_per_state": mech.waves_per_state(True)},
+                   "launch_shape": {"states_per_workgroup": mech.launch_shape(1)[0],
+                                    "waves_per_workgroup": mech.launch_shape(1)[1]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,

@@ -197,28 +197,52 @@ def test_edge_sizes(torch_cuda, api, mech_dir):
         check_source(f.cpu().numpy(), f_o, f_s, f"n={n}")
 
 
-def test_bench_configuration_sampled(torch_cuda, api, mech_dir):
-    """The 111-species configuration at full size (262,144 states, CONP,
-    layout F, fused source + sparse Jacobian, the launch the benchmark times),
-    checked on sampled states."""
+FULL_SIZE_CASES = [
+    # (workload, form, layout, output): the full-size configurations; the
+    # first is the one the benchmark times
+    ("ns111", "conp", "C", "sparse"),
+    ("ns111", "conp", "F", "sparse"),
+    ("ns111", "conv", "C", "sparse"),
+    ("ns111", "conv", "F", "sparse"),
+    ("ns111", "conp", "C", "dense"),
+    ("ns111", "conv", "F", "dense"),
+    ("ns53", "conp", "C", "sparse"),
+]
+
+
+@pytest.mark.parametrize("name,form,layout,output", FULL_SIZE_CASES)
+def test_full_size_sampled(torch_cuda, api, name, form, layout, output, mech_dir):
+    """Full-size workloads (262,144 states of the 111-species mechanism,
+    1,048,576 of the 53-species one) in the default launch shape, checked
+    against the oracle on sampled states, including the first and last."""
     torch = torch_cuda
-    m, path = workload_file("ns111", mech_dir)
-    w = synth.WORKLOADS["ns111"]
+    m, path = workload_file(name, mech_dir)
+    w = synth.WORKLOADS[name]
     st = synth.make_states(m, w.n_states, w.state_seed, T_range=w.T_range, P_range_atm=w.P_range_atm)
-    x, p = synth.pack_state(st, "conp", "F")
+    x, p = synth.pack_state(st, form, layout)
     mech = api.load_mechanism(path)
     xs, ps = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda()
+    del x
     d = torch.empty_like(xs)
-    note("bench configuration: 262144 states")
-    j = api.eval_jacobian_sparse(mech, xs, ps, "conp", "F", dstate=d)
+    note(f"full size {name} {form} {layout} {output}: {w.n_states} states, launch {mech.launch_shape(1 if output == 'sparse' else 2)}")
+    if output == "sparse":
+        j = api.eval_jacobian_sparse(mech, xs, ps, form, layout, dstate=d)
+    else:
+        j = api.eval_jacobian_dense(mech, xs, ps, form, layout, dstate=d)
     torch.cuda.synchronize()
     rng = np.random.default_rng(2024)
     idx = np.sort(np.concatenate([rng.choice(w.n_states, 40, replace=False), [0, w.n_states - 1]]))
-    xc = np.ascontiguousarray(x[:, idx].T)
+    xc, pc = synth.pack_state({k: v[idx] for k, v in st.items()}, form, "C")
     o = oracle.Oracle(path)
-    f_o, f_s = o.source(xc, p[idx], "conp", scale=True)
-    J_o, J_s = o.jacobian(xc, p[idx], "conp", scale=True)
-    check_source(d[:, idx].cpu().numpy().T, f_o, f_s, "bench sample")
-    vals = j[:, idx].cpu().numpy()
-    check_jac(api.sparse_to_dense(mech, vals, "F"), J_o, J_s, "bench sample")
+    f_o, f_s = o.source(xc, pc, form, scale=True)
+    J_o, J_s = o.jacobian(xc, pc, form, scale=True)
+    it = torch.from_numpy(idx).cuda()
+    dsel = (d[:, it].T if layout == "F" else d[it]).cpu().numpy()
+    check_source(dsel, f_o, f_s, f"{name} {form} {layout} sample")
+    if output == "sparse":
+        vals = (j[:, it] if layout == "F" else j[it]).cpu().numpy()
+        Jg = api.sparse_to_dense(mech, vals, layout)
+    else:
+        Jg = api.dense_as_sij(j[..., it] if layout == "F" else j[it], layout).cpu().numpy()
+    check_jac(Jg, J_o, J_s, f"{name} {form} {layout} {output} sample")
     assert torch.isfinite(j).all() and torch.isfinite(d).all()
