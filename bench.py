@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2048, help="states timed on the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shape instead of autotuning it first")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (traffic-counter reference)")
     args = ap.parse_args()
@@ -132,6 +134,12 @@ def main():
     jshape = (nnz, n) if args.layout == "F" else (n, nnz)
     jac = torch.empty(jshape, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
+    tuned = None
+    if not args.no_autotune:
+        # outside the timed region: pick the fastest launch shape for this batch
+        t0 = time.time()
+        tuned = api.autotune(mech, xs, ps, args.form, args.layout, mode="sparse", reps=2, stream=stream)
+        log(f"autotuned launch shape {tuned[:2]} ({tuned[2]:.3f} ms) in {time.time() - t0:.1f}s")
 
     def step():
         api.eval_jacobian_sparse(mech, xs, ps, args.form, args.layout, out=jac, dstate=dstate,
@@ -176,12 +184,16 @@ def main():
             torch.cuda.synchronize()
             return a.elapsed_time(b) / k
         out_src = torch.empty_like(xs)
+        if not args.no_autotune:
+            api.autotune(mech, xs, ps, args.form, args.layout, mode="source", reps=2, stream=stream)
         t = timeit(lambda: api.eval_source(mech, xs, ps, args.form, args.layout, out=out_src, stream=stream))
         variants["source_only"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3)}
         del out_src
         if N * N * n * 8 < 60e9:
             dshape = (N, N, n) if args.layout == "F" else (n, N, N)
             dj = torch.empty(dshape, dtype=torch.float64, device="cuda")
+            if not args.no_autotune:
+                api.autotune(mech, xs, ps, args.form, args.layout, mode="dense", reps=1, stream=stream)
             t = timeit(lambda: api.eval_jacobian_dense(mech, xs, ps, args.form, args.layout, out=dj,
                                                        dstate=dstate, stream=stream), k=3)
             variants["dense_jacobian"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3),
@@ -203,6 +215,33 @@ def main():
                                                     stream=stream))
         variants[f"layout_{ol}_sparse"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3)}
         del xs3, ps3, jac3, d3
+        if args.workload == "ns111" and not args.n_states:
+            # the 53-species configuration at its full size (1,048,576 states)
+            w53 = synth.WORKLOADS["ns53"]
+            m53 = synth.workload_mechanism("ns53")
+            p53 = os.path.join(tmp, "ns53.pjm")
+            synth.write_mechanism(m53, p53)
+            st53 = synth.make_states(m53, w53.n_states, w53.state_seed, T_range=w53.T_range,
+                                     P_range_atm=w53.P_range_atm)
+            x4, p4 = synth.pack_state(st53, args.form, args.layout)
+            del st53
+            mech53 = api.load_mechanism(p53)
+            xs4, ps4 = torch.from_numpy(x4).cuda(), torch.from_numpy(p4).cuda()
+            del x4
+            n4 = w53.n_states
+            jac4 = torch.empty((mech53.nnz, n4) if args.layout == "F" else (n4, mech53.nnz), dtype=torch.float64,
+                               device="cuda")
+            d4 = torch.empty_like(xs4)
+            if not args.no_autotune:
+                api.autotune(mech53, xs4, ps4, args.form, args.layout, mode="sparse", reps=1, stream=stream)
+            t = timeit(lambda: api.eval_jacobian_sparse(mech53, xs4, ps4, args.form, args.layout, out=jac4,
+                                                        dstate=d4, stream=stream), k=3)
+            b4 = 8 * (mech53.N + 1) + 8 * mech53.N + 8 * mech53.nnz
+            variants["ns53_1M_sparse"] = {"ms": round(t, 4), "states_per_s": n4 / (t * 1e-3),
+                                          "hbm_frac": b4 * n4 / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                          "launch_shape": list(mech53.launch_shape(1))}
+            del xs4, ps4, jac4, d4
+            mech53.close()
         log(f"variants: {json.dumps(variants)}")
 
     cpu = None
@@ -231,7 +270,8 @@ def main():
                    "n_species": m.n_species, "n_reactions": m.n_reactions, "n_states": n, "nnz": nnz,
                    "form": args.form, "layout": args.layout,
                    "launch_shape": {"states_per_workgroup": mech.launch_shape(1)[0],
-                                    "waves_per_workgroup": mech.launch_shape(1)[1]}},
+                                    "waves_per_workgroup": mech.launch_shape(1)[1],
+                                    "autotuned": tuned is not None}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,

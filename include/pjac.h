@@ -144,10 +144,13 @@ pj_status pj_eval_jacobian_dense(const pj_mech* mech, pj_form form, pj_layout la
 
 /*
  * Launch shape.  A workgroup evaluates states_per_group consecutive states at
- * once (1, 2 or 4) with waves_per_group waves (1, 2, 4 or 8); 0 restores the
- * automatic choice (the most states whose working set fits the LDS of one
- * workgroup, and enough waves for about 8 resident waves per compute unit).
- * A states_per_group that does not fit for a mode is ignored for that mode.
+ * once (a power of two up to 64) with waves_per_group waves (1, 2, 4 or 8);
+ * 1 state per workgroup is the paper's deep mapping (Sec. 2.1: the lanes of a
+ * workgroup cooperate on one state), 64 states on one wave its shallow
+ * mapping (a lane per state).  0 restores the automatic choice (the most
+ * states, up to 4, whose working set fits the LDS of one workgroup, and
+ * enough waves for about 8 resident waves per compute unit).  A
+ * states_per_group that does not fit for a mode is ignored for that mode.
  * With one wave per workgroup every accumulation happens in a fixed order,
  * so results are bitwise reproducible; with more, the order of LDS atomic
  * additions across waves may vary between runs (results then agree to
@@ -160,6 +163,24 @@ pj_status pj_mech_set_waves_per_state(pj_mech* mech, int waves_per_state);
 int pj_mech_waves_per_state(const pj_mech* mech, int for_jacobian);
 /* launch shape of mode 0 (source), 1 (sparse Jacobian) or 2 (dense Jacobian); -1 on error */
 int pj_mech_launch_shape(const pj_mech* mech, int mode, int* states_per_group, int* waves_per_group);
+
+/*
+ * Autotuner: time every launch shape that fits (states per workgroup 1, 2,
+ * 4, ..., 64; waves per workgroup 1, 2, 4, 8) for mode 0 (source), 1 (sparse
+ * Jacobian) or 2 (dense Jacobian) on the caller's batch, and keep the fastest
+ * for that mode until the next pj_mech_set_launch.  The buffers are those of
+ * the matching evaluation call (d_out: d_dstate for mode 0, the Jacobian
+ * output otherwise; d_dstate_or_null: the fused source output of modes 1 and
+ * 2) and are overwritten.  Every shape runs one warm-up launch and `reps`
+ * (>= 1) timed launches on `stream`; the call synchronises the stream.  On
+ * success the chosen shape and its mean time per launch (ms) are stored
+ * through the pointers that are not NULL.  Errors as for the evaluation
+ * calls; PJ_E_INVALID also for a bad mode, reps < 1 or n_states < 1.
+ */
+pj_status pj_mech_autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int64_t n_states,
+                           const double* d_state, const double* d_param, double* d_out,
+                           double* d_dstate_or_null, int reps, pj_stream stream,
+                           int* states_per_group, int* waves_per_group, float* ms);
 
 /* Bytes of LDS one workgroup needs for source terms (0) or the sparse Jacobian (1). */
 int64_t pj_mech_lds_bytes(const pj_mech* mech, int for_jacobian);

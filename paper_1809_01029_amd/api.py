@@ -65,6 +65,10 @@ _lib.pj_mech_set_launch.argtypes = [_P, ctypes.c_int, ctypes.c_int]
 _lib.pj_mech_set_launch.restype = ctypes.c_int
 _lib.pj_mech_launch_shape.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.pj_mech_launch_shape.restype = ctypes.c_int
+_lib.pj_mech_autotune.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P,
+                                  ctypes.c_int, _P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_float)]
+_lib.pj_mech_autotune.restype = ctypes.c_int
 _lib.pj_mech_lds_bytes.argtypes = [_P, ctypes.c_int]
 _lib.pj_mech_lds_bytes.restype = _I64
 _lib.pj_last_error.argtypes = []
@@ -250,6 +254,35 @@ def eval_jacobian_dense(mech: Mechanism, state: torch.Tensor, param: torch.Tenso
                                        _ptr(param), _ptr(out), _ptr(dstate), _stream(stream)),
            "pj_eval_jacobian_dense")
     return out
+
+
+MODES = {"source": 0, "sparse": 1, "dense": 2}
+
+
+def autotune(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, form: str = "conp",
+             layout: str = "F", mode: str = "sparse", reps: int = 2, stream=None):
+    """pj_mech_autotune: time every launch shape of ``mode`` ("source",
+    "sparse", "dense") on this batch and keep the fastest for that mode.
+    Returns (states per workgroup, waves per workgroup, ms per launch).
+    Scratch outputs are allocated here and discarded."""
+    n = _n_states(mech, state, layout)
+    _need(state, _state_shape(mech, n, layout), "state", None)
+    _need(param, (n,), "param", state.device)
+    m = MODES[mode]
+    dstate = torch.empty_like(state)
+    if m == 0:
+        out = dstate
+    elif m == 1:
+        out = torch.empty((mech.nnz, n) if layout == "F" else (n, mech.nnz), dtype=torch.float64,
+                          device=state.device)
+    else:
+        out = torch.empty((mech.N, mech.N, n) if layout == "F" else (n, mech.N, mech.N), dtype=torch.float64,
+                          device=state.device)
+    S, W, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    _check(_lib.pj_mech_autotune(mech.handle, m, FORMS[form], LAYOUTS[layout], n, _ptr(state), _ptr(param),
+                                 _ptr(out), _ptr(dstate) if m else None, int(reps), _stream(stream),
+                                 ctypes.byref(S), ctypes.byref(W), ctypes.byref(ms)), "pj_mech_autotune")
+    return S.value, W.value, ms.value
 
 
 def dense_as_sij(jac: torch.Tensor, layout: str) -> torch.Tensor:

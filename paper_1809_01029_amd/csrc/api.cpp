@@ -20,29 +20,41 @@ pj_status fail(pj_status st, const std::string& msg) {
 
 bool pow2_upto(int v, int mx) { return v >= 1 && v <= mx && (v & (v - 1)) == 0; }
 
+constexpr int MAX_S = 64, MAX_WAVES = 8;
+
 }  // namespace
 
 namespace pj {
 
+// Waves per workgroup for S states per workgroup: enough that a compute unit
+// holds about 8 resident waves given how many workgroups fit in its LDS, and
+// at least S/64 so that every state has a lane.
+static int default_waves(const Mechanism& m, int mode, int S) {
+    int w = S > 64 ? S / 64 : 1;
+    while (w < MAX_WAVES) {
+        const int64_t l = lds_bytes(m.dm, mode, S, w);
+        if (l > m.lds_max || (m.lds_max / l) * w >= 8) break;
+        w *= 2;
+    }
+    return w;
+}
+
 // Launch shape of each mode.  States per workgroup S: the most (4, 2 or 1)
-// whose interleaved working set fits the LDS of one workgroup.  Waves per
-// workgroup: enough that a compute unit holds about 8 resident waves given
-// how many workgroups fit in its LDS (at most 8).  A user setting overrides
-// either choice when it fits.
+// whose interleaved working set fits the LDS of one workgroup; waves per
+// workgroup as default_waves.  A user setting overrides either choice when it
+// fits.
 void choose_launch(Mechanism& m) {
     for (int mode = 0; mode < 3; ++mode) {
         int S = 1;
         for (int c = 4; c >= 1; c >>= 1)
-            if (lds_bytes(m.dm, mode, c) <= m.lds_max) { S = c; break; }
-        if (m.user_S && lds_bytes(m.dm, mode, m.user_S) <= m.lds_max) S = m.user_S;
-        const int64_t l = lds_bytes(m.dm, mode, S);
-        const int64_t blocks = l > 0 ? m.lds_max / l : 8;
-        int w = 1;
-        while (w < 8 && blocks * w < 8) w *= 2;
-        if (m.user_waves) w = m.user_waves;
+            if (lds_bytes(m.dm, mode, c, 1) <= m.lds_max) { S = c; break; }
+        if (m.user_S && lds_bytes(m.dm, mode, m.user_S, m.user_waves ? m.user_waves : 1) <= m.lds_max)
+            S = m.user_S;
+        int w = m.user_waves ? m.user_waves : default_waves(m, mode, S);
+        if (lds_bytes(m.dm, mode, S, w) > m.lds_max) w = default_waves(m, mode, S);
         m.S[mode] = S;
         m.waves[mode] = w;
-        m.lds[mode] = l;
+        m.lds[mode] = lds_bytes(m.dm, mode, S, w);
     }
 }
 
@@ -173,9 +185,9 @@ pj_status pj_eval_jacobian_dense(const pj_mech* mech, pj_form form, pj_layout la
 
 pj_status pj_mech_set_launch(pj_mech* mech, int states_per_group, int waves_per_group) {
     if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
-    if (states_per_group && !pow2_upto(states_per_group, 4))
-        return fail(PJ_E_INVALID, "states_per_group must be 0, 1, 2 or 4");
-    if (waves_per_group && !pow2_upto(waves_per_group, 8))
+    if (states_per_group && !pow2_upto(states_per_group, MAX_S))
+        return fail(PJ_E_INVALID, "states_per_group must be 0 or a power of two up to 64");
+    if (waves_per_group && !pow2_upto(waves_per_group, MAX_WAVES))
         return fail(PJ_E_INVALID, "waves_per_group must be 0, 1, 2, 4 or 8");
     mech->m.user_S = states_per_group;
     mech->m.user_waves = waves_per_group;
@@ -209,6 +221,62 @@ int pj_mech_launch_shape(const pj_mech* mech, int mode, int* states_per_group, i
     if (states_per_group) *states_per_group = mech->m.S[mode];
     if (waves_per_group) *waves_per_group = mech->m.waves[mode];
     return 0;
+}
+
+pj_status pj_mech_autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int64_t n_states,
+                           const double* d_state, const double* d_param, double* d_out,
+                           double* d_dstate_or_null, int reps, pj_stream stream,
+                           int* states_per_group, int* waves_per_group, float* ms) {
+    if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
+    if (mode < pj::MODE_SRC || mode > pj::MODE_DENSE) return fail(PJ_E_INVALID, "bad mode");
+    if (reps < 1) return fail(PJ_E_INVALID, "reps must be at least 1");
+    if (n_states < 1) return fail(PJ_E_INVALID, "autotuning needs at least one state");
+    pj::Mechanism& m = mech->m;
+    double* dst = mode == pj::MODE_SRC ? d_out : d_dstate_or_null;
+    double* jac = mode == pj::MODE_SRC ? nullptr : d_out;
+    // validate the arguments once with the current shape
+    pj_status st = eval(mech, mode, form, layout, n_states, d_state, d_param, dst, jac, stream);
+    if (st != PJ_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(PJ_E_DEVICE, "hipEventCreate failed");
+    }
+    int best_S = m.S[mode], best_w = m.waves[mode];
+    float best = -1.0f;
+    std::string err;
+    for (int S = 1; S <= MAX_S && err.empty(); S *= 2) {
+        for (int w = S > 64 ? S / 64 : 1; w <= MAX_WAVES; w *= 2) {
+            const int64_t l = pj::lds_bytes(m.dm, mode, S, w);
+            if (l > m.lds_max) continue;
+            hipError_t e = pj::launch(m.dm, mode, form, layout, S, n_states, d_state, d_param, dst, jac, w, l, hs);
+            if (e == hipSuccess) e = hipEventRecord(e0, hs);
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+                e = pj::launch(m.dm, mode, form, layout, S, n_states, d_state, d_param, dst, jac, w, l, hs);
+            if (e == hipSuccess) e = hipEventRecord(e1, hs);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) {
+                err = std::string("autotuning launch failed: ") + hipGetErrorString(e);
+                break;
+            }
+            t /= (float)reps;
+            if (best < 0.0f || t < best) { best = t; best_S = S; best_w = w; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!err.empty()) return fail(PJ_E_DEVICE, err);
+    m.S[mode] = best_S;
+    m.waves[mode] = best_w;
+    m.lds[mode] = pj::lds_bytes(m.dm, mode, best_S, best_w);
+    if (states_per_group) *states_per_group = best_S;
+    if (waves_per_group) *waves_per_group = best_w;
+    if (ms) *ms = best;
+    g_err.clear();
+    return PJ_OK;
 }
 
 int64_t pj_mech_lds_bytes(const pj_mech* mech, int for_jacobian) {

@@ -140,7 +140,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err);
 
 // kernels.hip
 enum Mode : int { MODE_SRC = 0, MODE_SPARSE = 1, MODE_DENSE = 2 };
-int64_t lds_bytes(const DevMech& dm, int mode, int S);
+int64_t lds_bytes(const DevMech& dm, int mode, int S, int waves);
 hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
                   const double* state, const double* param, double* dstate, double* jac, int waves,
                   int64_t lds, hipStream_t stream);

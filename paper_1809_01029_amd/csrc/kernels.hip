@@ -3,11 +3,16 @@
 // Sec. 3.4), with the lanes of a workgroup cooperating on a few states at a
 // time ("deep" vectorization, Sec. 2.1).
 //
-// Mapping.  A workgroup evaluates S consecutive states at once (S = 1, 2 or
-// 4) in a grid-stride loop over groups of states.  Thread t works for state
-// t mod S; the t / S index splits the species for the thermodynamics and the
-// reactions (sorted by kind and shape) for the rates and the Jacobian
+// Mapping.  A workgroup evaluates S consecutive states at once (S = 1, 2, 4,
+// ..., 64) in a grid-stride loop over groups of states.  Thread t works for
+// state t mod S; the t / S index splits the species for the thermodynamics
+// and the reactions (sorted by kind and shape) for the rates and the Jacobian
 // sub-products, so the S lanes of one reaction fetch its record together.
+// S = 1 is the "deep" mapping of the paper (Sec. 2.1: a workgroup cooperates
+// on one state); S = 64 with one wave is its "shallow" mapping (each lane owns
+// a state and walks all reactions, reading every table entry as a wave-wide
+// broadcast); the sizes between trade LDS per workgroup for fewer lanes per
+// state.
 // The per-state working set lives in LDS, every array interleaved with the
 // state fastest (element i of state s at i*S + s):
 //     C, G, H, CP, W   [Ns+1] concentrations, g = G/RT, h = H/RT, chat/R,
@@ -46,8 +51,8 @@ namespace pj {
 namespace {
 
 constexpr double LN10 = 2.302585092994045684;
-// LDS scratch of the workgroup reductions, per state: up to 8 waves x 8 values
-constexpr int RED_PER_STATE = 64;
+// LDS scratch of the workgroup reductions, per state and wave: up to 8 values
+constexpr int RED_PER_WAVE = 8;
 constexpr int MAX_THREADS = 512;
 
 struct dd {
@@ -87,7 +92,7 @@ __device__ inline double wave_sum(double v) {
 
 // Per-state sum of K per-thread values over the workgroup, in a fixed order;
 // every thread receives the totals of its state.  red: LDS scratch of
-// RED_PER_STATE * S doubles.
+// RED_PER_WAVE * nwave * S doubles.
 template <int S, int K>
 __device__ inline void block_sum(double (&v)[K], double* red, int wave, int nwave, int s) {
 #pragma unroll
@@ -174,11 +179,11 @@ __device__ inline void powd(double c, int nu, double& f, double& d) {
 
 }  // namespace
 
-int64_t lds_bytes(const DevMech& dm, int mode, int S) {
+int64_t lds_bytes(const DevMech& dm, int mode, int S, int waves) {
     int64_t d = 5 * (int64_t)(dm.ns + 1);
     if (mode != MODE_SRC) d += dm.nnz + dm.ns;
     if (mode == MODE_DENSE) d += dm.N;
-    return (d * S + (int64_t)RED_PER_STATE * S) * 8;
+    return (d * S + (int64_t)RED_PER_WAVE * waves * S) * 8;
 }
 
 template <int FORM, int LAYOUT, int MODE, int S>
@@ -202,7 +207,7 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
     double* CP = H + (ns + 1) * S;
     double* W = CP + (ns + 1) * S;
     double* red = W + (ns + 1) * S;
-    double* J = red + RED_PER_STATE * S;
+    double* J = red + RED_PER_WAVE * nwave * S;
     double* B = J + (size_t)nnz * S;
     double* ROW = B + (size_t)ns * S;
     // The T and V/P rows (the first 2N CSR slots) go to the output straight
@@ -670,7 +675,9 @@ hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int6
 #define PJ_CASE(F, L, M, SS)                                                                 \
     if (form == F && layout == L && mode == M && S == SS)                                    \
         return launch_t<F, L, M, SS>(dm, n, state, param, dstate, jac, waves, lds, stream);
-#define PJ_S(F, L, M) PJ_CASE(F, L, M, 1) PJ_CASE(F, L, M, 2) PJ_CASE(F, L, M, 4)
+#define PJ_S(F, L, M)                                                                        \
+    PJ_CASE(F, L, M, 1) PJ_CASE(F, L, M, 2) PJ_CASE(F, L, M, 4) PJ_CASE(F, L, M, 8)          \
+    PJ_CASE(F, L, M, 16) PJ_CASE(F, L, M, 32) PJ_CASE(F, L, M, 64)
 #define PJ_MODES(F, L) PJ_S(F, L, MODE_SRC) PJ_S(F, L, MODE_SPARSE) PJ_S(F, L, MODE_DENSE)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_F)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_C)

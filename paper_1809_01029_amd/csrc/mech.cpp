@@ -500,7 +500,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         lds_max = 65536;
     m.lds_max = lds_max;
-    if (lds_bytes(dm, MODE_SRC, 1) > lds_max) {
+    if (lds_bytes(dm, MODE_SRC, 1, 1) > lds_max) {
         err = "source-term working set exceeds the LDS of one workgroup";
         return PJ_E_UNSUPPORTED;
     }

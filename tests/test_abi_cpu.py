@@ -127,3 +127,30 @@ def test_eval_argument_checks_without_device(api, tmp_path):
     assert lib.pj_mech_set_waves_per_state(mech.handle, 2) == 0
     assert lib.pj_mech_waves_per_state(mech.handle, 0) == 2
     assert lib.pj_mech_set_waves_per_state(mech.handle, 0) == 0
+
+
+def test_launch_shape_and_autotune_argument_checks(api, tmp_path):
+    lib = api.library()
+    m = synth.make_mechanism(7, 10, 3, mix=synth.MixSpec(0.1, 0.2, 0.2), zipf=0.5)
+    mech = api.Mechanism(_write(tmp_path, synth.dumps(m)), upload=False)
+    h = mech.handle
+    dummy = ctypes.c_void_p(16)
+    # states per workgroup: powers of two up to 64; waves: 1, 2, 4, 8
+    for S in (1, 2, 4, 8, 16, 32, 64):
+        assert lib.pj_mech_set_launch(h, S, 1) == 0
+        assert mech.launch_shape(1) == (S, 1)
+    for S, W in ((3, 1), (128, 1), (-1, 1), (4, 3), (4, 16)):
+        assert lib.pj_mech_set_launch(h, S, W) == 1
+    assert lib.pj_mech_set_launch(h, 0, 0) == 0
+    # autotune: argument errors are reported before any device work
+    S, W, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    args = (0, 0, 16, dummy, dummy, dummy, None, 2, None, ctypes.byref(S), ctypes.byref(W), ctypes.byref(ms))
+    assert lib.pj_mech_autotune(None, 1, *args) == 1
+    assert lib.pj_mech_autotune(h, 3, *args) == 1
+    assert b"bad mode" in lib.pj_last_error()
+    bad_reps = (0, 0, 16, dummy, dummy, dummy, None, 0, None, None, None, None)
+    assert lib.pj_mech_autotune(h, 1, *bad_reps) == 1
+    no_states = (0, 0, 0, dummy, dummy, dummy, None, 2, None, None, None, None)
+    assert lib.pj_mech_autotune(h, 1, *no_states) == 1
+    assert lib.pj_mech_autotune(h, 1, *args) == 1
+    assert b"not uploaded" in lib.pj_last_error()

@@ -162,6 +162,68 @@ def test_launch_shapes_agree(torch_cuda, api, layout, mech_dir):
         check_jac(api.sparse_to_dense(mech, j.cpu().numpy(), layout), J_o, J_s, f"S={S} w={w}")
 
 
+@pytest.mark.parametrize("layout", ["F", "C"])
+@pytest.mark.parametrize("name,n", [("ns13", 333), ("ns53", 300)])
+def test_wide_launch_shapes(torch_cuda, api, name, n, layout, mech_dir):
+    """Up to 64 states per workgroup (one lane per state at 64 states on one
+    wave) where the working set fits the LDS, with a ragged last group."""
+    torch = torch_cuda
+    m, path = workload_file(name, mech_dir)
+    st = synth.make_states(m, n, 77)
+    for form in ("conp", "conv"):
+        x, p = synth.pack_state(st, form, layout)
+        xc, pc = synth.pack_state(st, form, "C")
+        o = oracle.Oracle(path)
+        J_o, J_s = o.jacobian(xc, pc, form, scale=True)
+        f_o, f_s = o.source(xc, pc, form, scale=True)
+        mech = api.load_mechanism(path)
+        xs, ps = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda()
+        for S, w in [(8, 1), (8, 2), (16, 1), (16, 4), (32, 1), (64, 1), (64, 2), (64, 8)]:
+            mech.set_launch(S, w)
+            note(f"{name} {form} {layout} S={S} waves={w} -> {mech.launch_shape(0)} {mech.launch_shape(1)} "
+                 f"{mech.launch_shape(2)}")
+            f = api.eval_source(mech, xs, ps, form, layout)
+            d = torch.empty_like(xs)
+            j = api.eval_jacobian_sparse(mech, xs, ps, form, layout, dstate=d)
+            jd = api.eval_jacobian_dense(mech, xs, ps, form, layout)
+            torch.cuda.synchronize()
+            check_source(src_to_c(f, layout), f_o, f_s, f"S={S} w={w} source")
+            check_source(src_to_c(d, layout), f_o, f_s, f"S={S} w={w} fused source")
+            check_jac(api.sparse_to_dense(mech, j.cpu().numpy(), layout), J_o, J_s, f"S={S} w={w} sparse")
+            check_jac(api.dense_as_sij(jd, layout).cpu().numpy(), J_o, J_s, f"S={S} w={w} dense")
+
+
+@pytest.mark.parametrize("mode", ["source", "sparse", "dense"])
+def test_autotune(torch_cuda, api, mode, mech_dir):
+    """The autotuner keeps a shape that fits and later calls stay within the
+    gates."""
+    torch = torch_cuda
+    m, path = workload_file("ns53", mech_dir)
+    st = synth.make_states(m, 2000, 91)
+    x, p = synth.pack_state(st, "conp", "C")
+    mech = api.load_mechanism(path)
+    xs, ps = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda()
+    S, W, ms = api.autotune(mech, xs, ps, "conp", "C", mode=mode, reps=1)
+    note(f"autotune {mode}: S={S} waves={W} {ms:.4f} ms")
+    mi = api.MODES[mode]
+    assert mech.launch_shape(mi) == (S, W)
+    assert S in (1, 2, 4, 8, 16, 32, 64) and W in (1, 2, 4, 8) and ms > 0
+    o = oracle.Oracle(path)
+    f_o, f_s = o.source(x, p, "conp", scale=True)
+    if mode == "source":
+        check_source(api.eval_source(mech, xs, ps, "conp", "C").cpu().numpy(), f_o, f_s, "autotuned source")
+        return
+    J_o, J_s = o.jacobian(x, p, "conp", scale=True)
+    d = torch.empty_like(xs)
+    if mode == "sparse":
+        j = api.eval_jacobian_sparse(mech, xs, ps, "conp", "C", dstate=d)
+        Jg = api.sparse_to_dense(mech, j.cpu().numpy(), "C")
+    else:
+        Jg = api.eval_jacobian_dense(mech, xs, ps, "conp", "C", dstate=d).cpu().numpy()
+    check_source(d.cpu().numpy(), f_o, f_s, f"autotuned {mode} (source terms)")
+    check_jac(Jg, J_o, J_s, f"autotuned {mode}")
+
+
 def test_one_wave_per_state_is_bitwise_reproducible(torch_cuda, api, mech_dir):
     torch = torch_cuda
     m, path = workload_file("ns53", mech_dir)
