@@ -49,10 +49,10 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload, form, layout, n):
+def measured_traffic(workload, form, layout, n, shape):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this workload, or None if there is none or the kernel sources changed
-    since it was taken."""
+    this workload, or None if there is none, it was taken with another launch
+    shape, or the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"pj_kernel_{workload}_{form}_{layout}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -64,6 +64,8 @@ def measured_traffic(workload, form, layout, n):
                 kv[k.strip()] = v.strip()
     try:
         if kv.get("kernel_sources_sha256") != kernel_sources_sha256() or int(kv["n_states"]) != n:
+            return None
+        if tuple(int(v) for v in kv["launch_shape"].split(",")) != tuple(shape):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -91,11 +93,13 @@ def main():
     ap.add_argument("--n-states", type=int, default=0, help="override the workload's state count")
     ap.add_argument("--form", default="conp", choices=["conp", "conv"])
     ap.add_argument("--layout", default="C", choices=["F", "C"])
-    ap.add_argument("--cpu-sample", type=int, default=2048, help="states timed on the CPU oracle")
+    ap.add_argument("--cpu-sample", type=int, default=12288, help="states timed on the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape instead of autotuning it first")
+    ap.add_argument("--launch", default="",
+                    help="S,W: fix the launch shape (states and waves per workgroup) instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (traffic-counter reference)")
     args = ap.parse_args()
@@ -135,6 +139,10 @@ def main():
     jac = torch.empty(jshape, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     tuned = None
+    if args.launch:
+        S_, W_ = (int(v) for v in args.launch.split(","))
+        mech.set_launch(S_, W_)
+        args.no_autotune = True
     if not args.no_autotune:
         # outside the timed region: pick the fastest launch shape for this batch
         t0 = time.time()
@@ -165,7 +173,7 @@ def main():
     # CSR values out (mechanism tables and intermediates excluded)
     bytes_state = 8 * (N + 1) + 8 * N + 8 * nnz
     achieved = bytes_state * n / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, args.form, args.layout, n)
+    traffic = measured_traffic(args.workload, args.form, args.layout, n, mech.launch_shape(1))
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_state": bytes_state, "algorithmic_bytes_per_launch": bytes_state * n}
