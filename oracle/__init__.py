@@ -60,6 +60,9 @@ def _load():
         lib.ora_jacobian_cs.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, ctypes.c_double, D]
         lib.ora_jacobian_fd.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, ctypes.c_double, D]
         lib.ora_pattern.argtypes = [P, ctypes.POINTER(ctypes.c_ubyte)]
+        lib.ora_adjoint.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, D, D, D, D]
+        lib.ora_param_grad_cs.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, ctypes.c_double, D]
+        lib.ora_jvp_cs.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, ctypes.c_double, D]
         _lib = lib
     return _lib
 
@@ -145,6 +148,40 @@ class Oracle:
         J = np.zeros((x.shape[0], self.N, self.N))
         self._lib.ora_jacobian_fd(self._h, _FORMS[form], x.shape[0], _d(x), _d(p), rel, _d(J))
         return J
+
+    def adjoint(self, x, p, v, form="conp", scale: bool = False):
+        """(J^T v per state [n, N], batch-summed d(v . dPhi/dt)/d(ln A, b, Ea/R)
+        per reaction [3, nr] in description order), with absolute-term scales
+        of both if ``scale``."""
+        x = _f64(x).reshape(-1, self.N)
+        p = _f64(p).reshape(-1)
+        v = _f64(v).reshape(-1, self.N)
+        n = x.shape[0]
+        jtv = np.zeros_like(x)
+        g = np.zeros((3, self.nr))
+        js = np.zeros_like(x) if scale else None
+        gs = np.zeros_like(g) if scale else None
+        self._lib.ora_adjoint(self._h, _FORMS[form], n, _d(x), _d(p), _d(v), _d(jtv), _d(g),
+                              _d(js) if scale else None, _d(gs) if scale else None)
+        return (jtv, g, js, gs) if scale else (jtv, g)
+
+    def param_grad_cs(self, x, p, v, form="conp", hrel: float = 1e-30):
+        """Complex-step d(v . dPhi/dt)/d(ln A, b, Ea/R), summed over states."""
+        x = _f64(x).reshape(-1, self.N)
+        p = _f64(p).reshape(-1)
+        v = _f64(v).reshape(-1, self.N)
+        g = np.zeros((3, self.nr))
+        self._lib.ora_param_grad_cs(self._h, _FORMS[form], x.shape[0], _d(x), _d(p), _d(v), hrel, _d(g))
+        return g
+
+    def jvp_cs(self, x, p, u, form="conp", hstep: float = 1e-30):
+        """Complex-step J u per state."""
+        x = _f64(x).reshape(-1, self.N)
+        p = _f64(p).reshape(-1)
+        u = _f64(u).reshape(-1, self.N)
+        out = np.zeros_like(x)
+        self._lib.ora_jvp_cs(self._h, _FORMS[form], x.shape[0], _d(x), _d(p), _d(u), hstep, _d(out))
+        return out
 
     def pattern(self) -> np.ndarray:
         P = np.zeros((self.N, self.N), dtype=np.uint8)

@@ -21,6 +21,13 @@
 //                              cancellation otherwise; parity tolerances are
 //                              relative to it.
 //
+// The adjoint (the product of the transposed Jacobian with a vector v and
+// the batch-summed derivatives of v . dPhi/dt with respect to every
+// reaction's Arrhenius parameters ln A, b and Ea/R) is written from the same
+// definitions: J^T v from the analytical Jacobian, and the parameter
+// derivatives by the chain rule through the rate of progress (for falloff
+// reactions the parameters are those of the high-pressure limit).
+//
 // Units: SI with kmol.  R_u = 8314.462618 J/(kmol K), P_ref = 101325 Pa.
 // State vector (Sec. 2.2): Phi = (T, V, n_1..n_{Ns-1}) for constant pressure
 // (parameter P) and (T, P, n_1..n_{Ns-1}) for constant volume (parameter V);
@@ -258,6 +265,15 @@ struct RxnEval {
     S dRf_dT, dRr_dT;
     std::vector<S> dq_dC;       // dq/d[C]_m at fixed T
     S dq_dT;                    // dq/dT at fixed concentrations
+    S dq_dlnk;                  // dq/d ln k_f at fixed T and concentrations
+};
+
+// Optional perturbations of a reaction's Arrhenius parameters (ln A, b,
+// Ea/R) of k_f (k_inf for falloff), used by the complex-step check of the
+// parameter derivatives; nullptr everywhere else.
+template <class S>
+struct ParamShift {
+    S lnA, b, theta;
 };
 
 template <class S>
@@ -295,12 +311,19 @@ S mass_action_d(const std::vector<std::pair<int, int>>& side, const std::vector<
 
 template <class S>
 RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
-                         const std::vector<Thermo<S>>& th, bool with_derivs) {
+                         const std::vector<Thermo<S>>& th, bool with_derivs,
+                         const ParamShift<S>* shift = nullptr) {
     int ns = m.ns;
     RxnEval<S> e;
     S T = st.T;
-    e.kf = arrhenius(r.lnA, r.b, r.theta, T);
-    e.dkf_dT = e.kf * (S(r.b) / T + S(r.theta) / (T * T));
+    if (shift) {
+        S bb = S(r.b) + shift->b, tt = S(r.theta) + shift->theta;
+        e.kf = exp(S(r.lnA) + shift->lnA + bb * log(T) - tt / T);
+        e.dkf_dT = e.kf * (bb / T + tt / (T * T));
+    } else {
+        e.kf = arrhenius(r.lnA, r.b, r.theta, T);
+        e.dkf_dT = e.kf * (S(r.b) / T + S(r.theta) / (T * T));
+    }
 
     // reverse rate constant from the equilibrium constant:
     //   ln Kc = -sum_k nu_k G_k/(R T) + (sum_k nu_k) ln(P_ref / (R T))
@@ -340,6 +363,7 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
 
     e.dc_dC.assign(ns, S(0.0));
     e.dc_dT = S(0.0);
+    S Pr_dc_dPr(0.0);   // Pr dc/dPr of a falloff reaction (Pr = k0 [M] / k_f)
     if (r.type == T_ELEM) {
         e.c = S(1.0);
     } else if (r.type == T_THREEBODY) {
@@ -383,8 +407,12 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
         S dc_dPr = F / ((S(1.0) + Pr) * (S(1.0) + Pr)) + Pr / (S(1.0) + Pr) * dF_dPr;
         e.dc_dT = dc_dPr * dPr_dT + Pr / (S(1.0) + Pr) * dF_dT;
         for (int k = 0; k < ns; ++k) e.dc_dC[k] = dc_dPr * k0 * S(alpha[k]) / e.kf;
+        Pr_dc_dPr = Pr * dc_dPr;
     }
     e.q = e.c * (e.Rf - e.Rr);
+    // R = Rf - Rr is proportional to k_f (k_r = k_f / Kc); for falloff
+    // reactions c also depends on k_f through Pr, with dPr/d ln k_f = -Pr
+    e.dq_dlnk = (r.type == T_LINDEMANN || r.type == T_TROE) ? e.q - (e.Rf - e.Rr) * Pr_dc_dPr : e.q;
     if (!with_derivs) return e;
 
     e.dRf_dC.assign(ns, S(0.0));
@@ -425,7 +453,8 @@ struct Eval {
 };
 
 template <class S>
-Eval<S> evaluate(const Mech& m, int form, const S* x, S param, bool with_derivs) {
+Eval<S> evaluate(const Mech& m, int form, const S* x, S param, bool with_derivs,
+                 const std::vector<ParamShift<S>>* shift = nullptr) {
     Eval<S> ev;
     int ns = m.ns, nr = (int)m.rx.size();
     ev.st = make_state(m, form, x, param);
@@ -433,7 +462,8 @@ Eval<S> evaluate(const Mech& m, int form, const S* x, S param, bool with_derivs)
     ev.th.resize(ns);
     for (int k = 0; k < ns; ++k) ev.th[k] = species_thermo(m.sp[k], T);
     ev.rx.resize(nr);
-    for (int i = 0; i < nr; ++i) ev.rx[i] = eval_reaction(m, m.rx[i], ev.st, ev.th, with_derivs);
+    for (int i = 0; i < nr; ++i)
+        ev.rx[i] = eval_reaction(m, m.rx[i], ev.st, ev.th, with_derivs, shift ? &(*shift)[i] : nullptr);
 
     ev.wdot.assign(ns, S(0.0));
     for (int k = 0; k < ns; ++k)
@@ -585,6 +615,61 @@ void jacobian(const Mech& m, int form, const S* x, S param, S* J) {
 
 
 // ---------------------------------------------------------------------------
+// adjoint: J^T v and the derivatives of v . dPhi/dt with respect to the
+// Arrhenius parameters, one state.  dPhi/dt depends on reaction i's
+// parameters only through q_i, so
+//   d(v . f)/d theta_i = lambda_i dq_i/d theta_i,   lambda_i = v . df/dq_i,
+// where df/dq_i follows from the source terms with dwdot_k/dq_i = nu_ki:
+//   dTdot/dq_i = -dE_i / D,  dE_i = sum_k nu_ki e_k (all species),
+//   dOmega/dq_i = sum_{k<Ns} (1 - W_k/W_Ns) nu_ki,
+//   CONP dSdot/dq_i = V/T dTdot/dq_i + V R T/P dOmega/dq_i,
+//   CONV dSdot/dq_i = P/T dTdot/dq_i + R T dOmega/dq_i,
+//   d(dn_k/dt)/dq_i = V nu_ki,
+// and dq_i/d ln A = dq_i/d ln k_f, dq_i/db = ln T dq_i/d ln k_f,
+// dq_i/d(Ea/R) = -dq_i/d ln k_f / T.
+
+template <class S>
+void param_grad(const Mech& m, int form, const S* x, S param, const double* v, S* g /* [3][nr] */) {
+    int ns = m.ns, nr = (int)m.rx.size();
+    Eval<S> ev = evaluate(m, form, x, param, false);
+    S T = ev.st.T, V = ev.st.V, P = ev.st.P;
+    double Wb = m.sp[ns - 1].W;
+    for (int i = 0; i < nr; ++i) {
+        const Reaction& r = m.rx[i];
+        S dE(0.0), dOm(0.0), vn(0.0);
+        for (int k = 0; k < ns; ++k) {
+            int nu = net_nu<S>(r, k);
+            if (!nu) continue;
+            dE = dE + S((double)nu) * ev.e[k];
+            if (k < ns - 1) {
+                dOm = dOm + S((1.0 - m.sp[k].W / Wb) * nu);
+                vn = vn + S(v[2 + k] * nu);
+            }
+        }
+        S dTdot = -dE / ev.D;
+        S dSdot = (form == FORM_CONP) ? V / T * dTdot + V * S(RU) * T / P * dOm
+                                      : P / T * dTdot + S(RU) * T * dOm;
+        S lam = S(v[0]) * dTdot + S(v[1]) * dSdot + V * vn;
+        S gl = lam * ev.rx[i].dq_dlnk;
+        g[i] = gl;
+        g[nr + i] = gl * log(T);
+        g[2 * nr + i] = -gl / T;
+    }
+}
+
+template <class S>
+void jtv(const Mech& m, int form, const S* x, S param, const double* v, S* out) {
+    int N = m.ns + 1;
+    std::vector<S> J((size_t)N * N);
+    jacobian(m, form, x, param, J.data());
+    for (int j = 0; j < N; ++j) {
+        S acc(0.0);
+        for (int i = 0; i < N; ++i) acc = acc + J[(size_t)i * N + j] * S(v[i]);
+        out[j] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // structural sparsity pattern (Sec. 3.4): the temperature and state-parameter
 // rows and columns are dense; species row k has column j when some reaction
 // with a non-zero net coefficient of k has a rate of progress that depends on
@@ -734,5 +819,82 @@ void ora_jacobian_fd(void* h, int form, long n, const double* x, const double* p
 }
 
 void ora_pattern(void* h, unsigned char* P) { pattern(*static_cast<Mech*>(h), P); }
+
+// Adjoint over n states (rows of length N, v likewise): jtv[s] = J(s)^T v[s];
+// grad[3][nr] = sum over states of d(v . dPhi/dt)/d(ln A, b, Ea/R) per reaction
+// in description order.  Optional absolute-term scales of both.
+void ora_adjoint(void* h, int form, long n, const double* x, const double* param, const double* v,
+                 double* jtv_out, double* grad, double* jtv_scale, double* grad_scale) {
+    const Mech& m = *static_cast<Mech*>(h);
+    int N = m.ns + 1, nr = (int)m.rx.size();
+    std::vector<Scaled> gsum(3 * nr, Scaled(0.0));
+    std::vector<double> gd(3 * nr, 0.0);
+    for (long s = 0; s < n; ++s) {
+        const double* xs = x + s * N;
+        const double* vs = v + s * N;
+        if (jtv_scale || grad_scale) {
+            std::vector<Scaled> xx(N), o(N), g(3 * nr);
+            for (int i = 0; i < N; ++i) xx[i] = Scaled(xs[i]);
+            jtv(m, form, xx.data(), Scaled(param[s]), vs, o.data());
+            for (int j = 0; j < N; ++j) {
+                jtv_out[s * N + j] = o[j].v;
+                if (jtv_scale) jtv_scale[s * N + j] = o[j].s;
+            }
+            param_grad(m, form, xx.data(), Scaled(param[s]), vs, g.data());
+            for (int q = 0; q < 3 * nr; ++q) gsum[q] = gsum[q] + g[q];
+        } else {
+            std::vector<double> g(3 * nr);
+            jtv(m, form, xs, param[s], vs, jtv_out + s * N);
+            param_grad(m, form, xs, param[s], vs, g.data());
+            for (int q = 0; q < 3 * nr; ++q) gd[q] += g[q];
+        }
+    }
+    for (int q = 0; q < 3 * nr; ++q) {
+        grad[q] = (jtv_scale || grad_scale) ? gsum[q].v : gd[q];
+        if (grad_scale) grad_scale[q] = gsum[q].s;
+    }
+}
+
+// Complex-step parameter derivatives: for every reaction and parameter,
+// Im(v . f(theta + i h)) / h summed over states, h = hrel * max(|theta|, 1).
+void ora_param_grad_cs(void* h, int form, long n, const double* x, const double* param,
+                       const double* v, double hrel, double* grad) {
+    const Mech& m = *static_cast<Mech*>(h);
+    int N = m.ns + 1, nr = (int)m.rx.size();
+    typedef std::complex<double> C;
+    for (int q = 0; q < 3 * nr; ++q) grad[q] = 0.0;
+    for (long s = 0; s < n; ++s) {
+        std::vector<C> xx(N);
+        for (int i = 0; i < N; ++i) xx[i] = C(x[s * N + i], 0.0);
+        for (int i = 0; i < nr; ++i) {
+            const Reaction& r = m.rx[i];
+            const double base[3] = {r.lnA, r.b, r.theta};
+            for (int a = 0; a < 3; ++a) {
+                std::vector<ParamShift<C>> sh(nr, ParamShift<C>{C(0.0), C(0.0), C(0.0)});
+                double hh = hrel * std::fmax(std::fabs(base[a]), 1.0);
+                C d(0.0, hh);
+                if (a == 0) sh[i].lnA = d; else if (a == 1) sh[i].b = d; else sh[i].theta = d;
+                Eval<C> ev = evaluate(m, form, xx.data(), C(param[s], 0.0), false, &sh);
+                double acc = 0.0;
+                for (int k = 0; k < N; ++k) acc += v[s * N + k] * ev.f[k].imag() / hh;
+                grad[a * nr + i] += acc;
+            }
+        }
+    }
+}
+
+// Complex-step directional derivative: out[s] = Im f(Phi_s + i h u_s) / h = J(s) u_s.
+void ora_jvp_cs(void* h, int form, long n, const double* x, const double* param, const double* u,
+                double hstep, double* out) {
+    const Mech& m = *static_cast<Mech*>(h);
+    int N = m.ns + 1;
+    typedef std::complex<double> C;
+    for (long s = 0; s < n; ++s) {
+        std::vector<C> xx(N);
+        for (int i = 0; i < N; ++i) xx[i] = C(x[s * N + i], hstep * u[s * N + i]);
+        Eval<C> ev = evaluate(m, form, xx.data(), C(param[s], 0.0), false);
+        for (int i = 0; i < N; ++i) out[s * N + i] = ev.f[i].imag() / hstep;
+    }
+}
 
 }  // extern "C"
