@@ -143,6 +143,35 @@ pj_status pj_eval_jacobian_dense(const pj_mech* mech, pj_form form, pj_layout la
                                  double* d_jac, double* d_dstate_or_null, pj_stream stream);
 
 /*
+ * Adjoint (for calibrating the mechanism against data): for every state the
+ * product of the transposed Jacobian with a vector, J^T v, and, summed over
+ * the batch, the derivatives of v . dPhi/dt with respect to every reaction's
+ * Arrhenius parameters ln A, b and Ea/R (Sec. 2.2's rate constants; for
+ * falloff reactions those of the high-pressure limit, the low-pressure limit
+ * held fixed).  The Jacobian is formed on chip as for
+ * pj_eval_jacobian_sparse and never written out.
+ * d_v: N*n doubles, same layout as d_state; d_jtv: N*n doubles, same layout;
+ * d_grad_or_null: NULL, or 3*Nr doubles [ln A (Nr), b (Nr), Ea/R (Nr)] in the
+ * description's reaction order, overwritten with the batch sums (workgroups
+ * add their partial sums with atomics, so the last bits may vary from run to
+ * run); d_dstate_or_null: optional fused source terms.
+ */
+pj_status pj_eval_adjoint(const pj_mech* mech, pj_form form, pj_layout layout, int64_t n_states,
+                          const double* d_state, const double* d_param, const double* d_v,
+                          double* d_jtv, double* d_grad_or_null, double* d_dstate_or_null,
+                          pj_stream stream);
+
+/*
+ * Replace / read the Arrhenius parameters (ln A, b, Ea/R of k_f; of k_inf
+ * for falloff reactions) of all Nr reactions, host arrays in description
+ * order; a NULL array is left unchanged / not written.  Setting updates the
+ * uploaded tables synchronously (the caller orders it against work in
+ * flight that uses the mechanism).
+ */
+pj_status pj_mech_set_arrhenius(pj_mech* mech, const double* lnA, const double* b, const double* theta);
+pj_status pj_mech_get_arrhenius(const pj_mech* mech, double* lnA, double* b, double* theta);
+
+/*
  * Launch shape.  A workgroup evaluates states_per_group consecutive states at
  * once (a power of two up to 64) with waves_per_group waves (1, 2, 4 or 8);
  * 1 state per workgroup is the paper's deep mapping (Sec. 2.1: the lanes of a
@@ -161,7 +190,8 @@ pj_status pj_mech_set_launch(pj_mech* mech, int states_per_group, int waves_per_
 pj_status pj_mech_set_waves_per_state(pj_mech* mech, int waves_per_state);
 /* waves per workgroup when one state per workgroup is used, else -1 */
 int pj_mech_waves_per_state(const pj_mech* mech, int for_jacobian);
-/* launch shape of mode 0 (source), 1 (sparse Jacobian) or 2 (dense Jacobian); -1 on error */
+/* launch shape of mode 0 (source), 1 (sparse Jacobian), 2 (dense Jacobian) or
+ * 3 (adjoint, at most 4 states per workgroup); -1 on error */
 int pj_mech_launch_shape(const pj_mech* mech, int mode, int* states_per_group, int* waves_per_group);
 
 /*

@@ -57,6 +57,13 @@ _lib.pj_eval_jacobian_sparse.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _
 _lib.pj_eval_jacobian_sparse.restype = ctypes.c_int
 _lib.pj_eval_jacobian_dense.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P, _P]
 _lib.pj_eval_jacobian_dense.restype = ctypes.c_int
+_lib.pj_eval_adjoint.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P, _P, _P, _P]
+_lib.pj_eval_adjoint.restype = ctypes.c_int
+_DP = ctypes.POINTER(ctypes.c_double)
+_lib.pj_mech_set_arrhenius.argtypes = [_P, _DP, _DP, _DP]
+_lib.pj_mech_set_arrhenius.restype = ctypes.c_int
+_lib.pj_mech_get_arrhenius.argtypes = [_P, _DP, _DP, _DP]
+_lib.pj_mech_get_arrhenius.restype = ctypes.c_int
 _lib.pj_mech_set_waves_per_state.argtypes = [_P, ctypes.c_int]
 _lib.pj_mech_set_waves_per_state.restype = ctypes.c_int
 _lib.pj_mech_waves_per_state.argtypes = [_P, ctypes.c_int]
@@ -147,6 +154,30 @@ class Mechanism:
         if _lib.pj_mech_launch_shape(self._h, int(mode), ctypes.byref(a), ctypes.byref(b)) != 0:
             raise PjError(1, "pj_mech_launch_shape")
         return a.value, b.value
+
+    def arrhenius(self):
+        """(ln A, b, Ea/R) of every reaction, description order (k_inf for falloff)."""
+        nr = self.n_reactions
+        a, b, t = np.zeros(nr), np.zeros(nr), np.zeros(nr)
+        dp = lambda x: x.ctypes.data_as(_DP)
+        _check(_lib.pj_mech_get_arrhenius(self._h, dp(a), dp(b), dp(t)), "pj_mech_get_arrhenius")
+        return a, b, t
+
+    def set_arrhenius(self, lnA=None, b=None, theta=None):
+        """pj_mech_set_arrhenius: replace any of the three parameter arrays
+        (length n_reactions, description order); synchronous."""
+        nr = self.n_reactions
+        keep = []
+
+        def arr(x):
+            if x is None:
+                return None
+            x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+            if x.shape[0] != nr:
+                raise ValueError(f"expected {nr} values")
+            keep.append(x)
+            return x.ctypes.data_as(_DP)
+        _check(_lib.pj_mech_set_arrhenius(self._h, arr(lnA), arr(b), arr(theta)), "pj_mech_set_arrhenius")
 
     def waves_per_state(self, jacobian: bool = False) -> int:
         return _lib.pj_mech_waves_per_state(self._h, 1 if jacobian else 0)
@@ -256,7 +287,63 @@ def eval_jacobian_dense(mech: Mechanism, state: torch.Tensor, param: torch.Tenso
     return out
 
 
-MODES = {"source": 0, "sparse": 1, "dense": 2}
+MODES = {"source": 0, "sparse": 1, "dense": 2, "adjoint": 3}
+
+
+def eval_adjoint(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, v: torch.Tensor,
+                 form: str = "conp", layout: str = "F", jtv: Optional[torch.Tensor] = None,
+                 grad: Optional[torch.Tensor] = None, with_grad: bool = True,
+                 dstate: Optional[torch.Tensor] = None, stream=None):
+    """pj_eval_adjoint: (J^T v per state in the state layout, batch-summed
+    d(v . dPhi/dt)/d(ln A, b, Ea/R) as a (3, n_reactions) tensor in
+    description order, or None when ``with_grad`` is False)."""
+    n = _n_states(mech, state, layout)
+    _need(state, _state_shape(mech, n, layout), "state", None)
+    _need(param, (n,), "param", state.device)
+    _need(v, _state_shape(mech, n, layout), "v", state.device)
+    if jtv is None:
+        jtv = torch.empty_like(state)
+    _need(jtv, _state_shape(mech, n, layout), "jtv", state.device)
+    if with_grad:
+        if grad is None:
+            grad = torch.empty((3, mech.n_reactions), dtype=torch.float64, device=state.device)
+        _need(grad, (3, mech.n_reactions), "grad", state.device)
+    else:
+        grad = None
+    if dstate is not None:
+        _need(dstate, _state_shape(mech, n, layout), "dstate", state.device)
+    _check(_lib.pj_eval_adjoint(mech.handle, FORMS[form], LAYOUTS[layout], n, _ptr(state), _ptr(param),
+                                _ptr(v), _ptr(jtv), _ptr(grad), _ptr(dstate), _stream(stream)),
+           "pj_eval_adjoint")
+    return jtv, grad
+
+
+class SourceTerms(torch.autograd.Function):
+    """dPhi/dt as a differentiable function of the states and of the
+    mechanism's Arrhenius parameters: forward runs pj_eval_source with the
+    given (ln A, b, Ea/R) installed in the mechanism, backward runs
+    pj_eval_adjoint.  The parameter P (CONP) or V (CONV) gets no gradient."""
+
+    @staticmethod
+    def forward(ctx, state, param, lnA, b, theta, mech, form, layout):
+        mech.set_arrhenius(lnA.detach().cpu().numpy(), b.detach().cpu().numpy(),
+                           theta.detach().cpu().numpy())
+        ctx.mech, ctx.form, ctx.layout = mech, form, layout
+        ctx.save_for_backward(state, param)
+        return eval_source(mech, state, param, form, layout)
+
+    @staticmethod
+    def backward(ctx, v):
+        state, param = ctx.saved_tensors
+        jtv, grad = eval_adjoint(ctx.mech, state, param, v.contiguous(), ctx.form, ctx.layout)
+        g = grad.to(v.device)
+        return jtv, None, g[0], g[1], g[2], None, None, None
+
+
+def source_terms(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, lnA: torch.Tensor,
+                 b: torch.Tensor, theta: torch.Tensor, form: str = "conp", layout: str = "F") -> torch.Tensor:
+    """Differentiable source terms (see SourceTerms)."""
+    return SourceTerms.apply(state, param, lnA, b, theta, mech, form, layout)
 
 
 def autotune(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, form: str = "conp",

@@ -29,10 +29,10 @@ namespace pj {
 // Waves per workgroup for S states per workgroup: enough that a compute unit
 // holds about 8 resident waves given how many workgroups fit in its LDS, and
 // at least S/64 so that every state has a lane.
-static int default_waves(const Mechanism& m, int mode, int S) {
+static int default_waves(const Mechanism& m, int mode, int S, bool gr) {
     int w = S > 64 ? S / 64 : 1;
     while (w < MAX_WAVES) {
-        const int64_t l = lds_bytes(m.dm, mode, S, w);
+        const int64_t l = lds_bytes(m.dm, mode, S, w, gr);
         if (l > m.lds_max || (m.lds_max / l) * w >= 8) break;
         w *= 2;
     }
@@ -42,19 +42,23 @@ static int default_waves(const Mechanism& m, int mode, int S) {
 // Launch shape of each mode.  States per workgroup S: the most (4, 2 or 1)
 // whose interleaved working set fits the LDS of one workgroup; waves per
 // workgroup as default_waves.  A user setting overrides either choice when it
-// fits.
+// fits.  The adjoint keeps its per-reaction parameter sums in LDS when they
+// fit beside one state's working set.
 void choose_launch(Mechanism& m) {
-    for (int mode = 0; mode < 3; ++mode) {
+    m.adj_grad_in_lds = lds_bytes(m.dm, MODE_ADJ, 1, 1, true) <= m.lds_max;
+    for (int mode = 0; mode < N_MODES; ++mode) {
+        const bool gr = mode == MODE_ADJ && m.adj_grad_in_lds;
+        auto L = [&](int S, int w) { return lds_bytes(m.dm, mode, S, w, gr); };
         int S = 1;
         for (int c = 4; c >= 1; c >>= 1)
-            if (lds_bytes(m.dm, mode, c, 1) <= m.lds_max) { S = c; break; }
-        if (m.user_S && lds_bytes(m.dm, mode, m.user_S, m.user_waves ? m.user_waves : 1) <= m.lds_max)
-            S = m.user_S;
-        int w = m.user_waves ? m.user_waves : default_waves(m, mode, S);
-        if (lds_bytes(m.dm, mode, S, w) > m.lds_max) w = default_waves(m, mode, S);
+            if (L(c, 1) <= m.lds_max) { S = c; break; }
+        const bool user_ok = m.user_S && (mode != MODE_ADJ || m.user_S <= MAX_S_ADJ);
+        if (user_ok && L(m.user_S, m.user_waves ? m.user_waves : 1) <= m.lds_max) S = m.user_S;
+        int w = m.user_waves ? m.user_waves : default_waves(m, mode, S, gr);
+        if (L(S, w) > m.lds_max) w = default_waves(m, mode, S, gr);
         m.S[mode] = S;
         m.waves[mode] = w;
-        m.lds[mode] = lds_bytes(m.dm, mode, S, w);
+        m.lds[mode] = L(S, w);
     }
 }
 
@@ -64,7 +68,7 @@ namespace {
 
 pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, int64_t n,
                const double* state, const double* param, double* dstate, double* jac,
-               pj_stream stream) {
+               pj_stream stream, const double* vin = nullptr, double* grad = nullptr) {
     if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
     if (form != PJ_CONP && form != PJ_CONV) return fail(PJ_E_INVALID, "bad form");
     if (layout != PJ_LAYOUT_F && layout != PJ_LAYOUT_C) return fail(PJ_E_INVALID, "bad layout");
@@ -72,7 +76,9 @@ pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, in
     if (n == 0) { g_err.clear(); return PJ_OK; }
     if (!state || !param) return fail(PJ_E_INVALID, "NULL state or parameter");
     if (mode == pj::MODE_SRC && !dstate) return fail(PJ_E_INVALID, "NULL output");
-    if (mode != pj::MODE_SRC && !jac) return fail(PJ_E_INVALID, "NULL Jacobian output");
+    if (mode != pj::MODE_SRC && !jac)
+        return fail(PJ_E_INVALID, mode == pj::MODE_ADJ ? "NULL J^T v output" : "NULL Jacobian output");
+    if (mode == pj::MODE_ADJ && !vin) return fail(PJ_E_INVALID, "NULL vector v");
     const pj::Mechanism& m = mech->m;
     if (!m.dbuf) return fail(PJ_E_INVALID, "mechanism not uploaded to a device");
     int dev = -1;
@@ -82,8 +88,8 @@ pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, in
     if (lds > m.lds_max)
         return fail(PJ_E_UNSUPPORTED, "per-state working set (" + std::to_string(lds) +
                                           " B) exceeds the LDS of one workgroup");
-    hipError_t e = pj::launch(m.dm, mode, form, layout, m.S[mode], n, state, param, dstate, jac,
-                              m.waves[mode], lds, (hipStream_t)stream);
+    hipError_t e = pj::launch(m.dm, mode, form, layout, m.S[mode], n, state, param, dstate, jac, vin,
+                              grad, m.adj_grad_in_lds ? 1 : 0, m.waves[mode], lds, (hipStream_t)stream);
     if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     g_err.clear();
     return PJ_OK;
@@ -183,6 +189,58 @@ pj_status pj_eval_jacobian_dense(const pj_mech* mech, pj_form form, pj_layout la
                 d_jac, stream);
 }
 
+pj_status pj_eval_adjoint(const pj_mech* mech, pj_form form, pj_layout layout, int64_t n_states,
+                          const double* d_state, const double* d_param, const double* d_v,
+                          double* d_jtv, double* d_grad_or_null, double* d_dstate_or_null,
+                          pj_stream stream) {
+    if (n_states == 0 && mech && d_grad_or_null && mech->m.dbuf) {
+        // an empty batch still defines the gradient sums: zero
+        hipError_t e = pj::zero_async(d_grad_or_null, 3 * (int64_t)mech->m.nr, (hipStream_t)stream);
+        if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("zeroing the gradient failed: ") + hipGetErrorString(e));
+    }
+    return eval(mech, pj::MODE_ADJ, form, layout, n_states, d_state, d_param, d_dstate_or_null, d_jtv,
+                stream, d_v, d_grad_or_null);
+}
+
+pj_status pj_mech_set_arrhenius(pj_mech* mech, const double* lnA, const double* b, const double* theta) {
+    if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
+    pj::Mechanism& m = mech->m;
+    for (int i = 0; i < m.nr; ++i) {
+        if (lnA) m.rx[i].lnA = lnA[i];
+        if (b) m.rx[i].b = b[i];
+        if (theta) m.rx[i].theta = theta[i];
+    }
+    if (m.dbuf) {
+        for (int p = 0; p < m.nr; ++p) {
+            const auto& r = m.rx[m.order[p]];
+            m.h_rec[p].lnA = r.lnA;
+            m.h_rec[p].b = r.b;
+            m.h_rec[p].theta = r.theta;
+        }
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (cur != m.device && hipSetDevice(m.device) != hipSuccess)
+            return fail(PJ_E_DEVICE, "cannot select the mechanism's device");
+        hipError_t e = hipMemcpy((unsigned char*)m.dbuf + m.off_rec, m.h_rec.data(),
+                                 m.h_rec.size() * sizeof(pj::RxnRec), hipMemcpyHostToDevice);
+        if (cur >= 0 && cur != m.device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("update of the reaction table failed: ") + hipGetErrorString(e));
+    }
+    g_err.clear();
+    return PJ_OK;
+}
+
+pj_status pj_mech_get_arrhenius(const pj_mech* mech, double* lnA, double* b, double* theta) {
+    if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
+    for (int i = 0; i < mech->m.nr; ++i) {
+        if (lnA) lnA[i] = mech->m.rx[i].lnA;
+        if (b) b[i] = mech->m.rx[i].b;
+        if (theta) theta[i] = mech->m.rx[i].theta;
+    }
+    g_err.clear();
+    return PJ_OK;
+}
+
 pj_status pj_mech_set_launch(pj_mech* mech, int states_per_group, int waves_per_group) {
     if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
     if (states_per_group && !pow2_upto(states_per_group, MAX_S))
@@ -195,8 +253,9 @@ pj_status pj_mech_set_launch(pj_mech* mech, int states_per_group, int waves_per_
         pj::choose_launch(mech->m);
     } else {
         // provisional until the upload measures the LDS the modes need
-        for (int mode = 0; mode < 3; ++mode) {
+        for (int mode = 0; mode < pj::N_MODES; ++mode) {
             mech->m.S[mode] = states_per_group ? states_per_group : 1;
+            if (mode == pj::MODE_ADJ && mech->m.S[mode] > pj::MAX_S_ADJ) mech->m.S[mode] = pj::MAX_S_ADJ;
             mech->m.waves[mode] = waves_per_group ? waves_per_group : 1;
         }
     }
@@ -217,7 +276,7 @@ int pj_mech_waves_per_state(const pj_mech* mech, int for_jacobian) {
 }
 
 int pj_mech_launch_shape(const pj_mech* mech, int mode, int* states_per_group, int* waves_per_group) {
-    if (!mech || mode < 0 || mode > 2) return -1;
+    if (!mech || mode < 0 || mode >= pj::N_MODES) return -1;
     if (states_per_group) *states_per_group = mech->m.S[mode];
     if (waves_per_group) *waves_per_group = mech->m.waves[mode];
     return 0;
@@ -250,10 +309,10 @@ pj_status pj_mech_autotune(pj_mech* mech, int mode, pj_form form, pj_layout layo
         for (int w = S > 64 ? S / 64 : 1; w <= MAX_WAVES; w *= 2) {
             const int64_t l = pj::lds_bytes(m.dm, mode, S, w);
             if (l > m.lds_max) continue;
-            hipError_t e = pj::launch(m.dm, mode, form, layout, S, n_states, d_state, d_param, dst, jac, w, l, hs);
+            hipError_t e = pj::launch(m.dm, mode, form, layout, S, n_states, d_state, d_param, dst, jac, nullptr, nullptr, 0, w, l, hs);
             if (e == hipSuccess) e = hipEventRecord(e0, hs);
             for (int r = 0; r < reps && e == hipSuccess; ++r)
-                e = pj::launch(m.dm, mode, form, layout, S, n_states, d_state, d_param, dst, jac, w, l, hs);
+                e = pj::launch(m.dm, mode, form, layout, S, n_states, d_state, d_param, dst, jac, nullptr, nullptr, 0, w, l, hs);
             if (e == hipSuccess) e = hipEventRecord(e1, hs);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float t = 0.0f;

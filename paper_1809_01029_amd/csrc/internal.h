@@ -96,6 +96,8 @@ struct DevMech {
 
     // pattern
     const int32_t* row_ptr;   // [N + 1]
+    const uint16_t* row_of;   // [nnz] row (state index) of each CSR entry
+    const int32_t* orig;      // [nr] description index of each kernel-order reaction
     const uint16_t* col_idx;  // [nnz]
     const int32_t* dense_rows;// [n_dense_rows] species index k of bath-dense rows
 };
@@ -128,8 +130,13 @@ struct Mechanism {
     DevMech dm{};
     // launch shape per mode (source, sparse, dense): states per workgroup,
     // waves per workgroup, and the LDS bytes that needs
-    int S[3] = {1, 1, 1}, waves[3] = {1, 1, 1};
-    int64_t lds[3] = {0, 0, 0};
+    int S[4] = {1, 1, 1, 1}, waves[4] = {1, 1, 1, 1};
+    int64_t lds[4] = {0, 0, 0, 0};
+    bool adj_grad_in_lds = true;           // adjoint parameter sums kept in LDS
+    // host copy of the reaction records and their byte offset in the device
+    // buffer (Arrhenius parameters can be replaced after the upload)
+    std::vector<RxnRec> h_rec;
+    size_t off_rec = 0;
     int user_S = 0, user_waves = 0;        // 0 = automatic
     int lds_max = 0;
 };
@@ -139,11 +146,16 @@ pj_status build_mechanism(const char* path, Mechanism& m, std::string& err);
 pj_status upload_mechanism(Mechanism& m, std::string& err);
 
 // kernels.hip
-enum Mode : int { MODE_SRC = 0, MODE_SPARSE = 1, MODE_DENSE = 2 };
-int64_t lds_bytes(const DevMech& dm, int mode, int S, int waves);
+enum Mode : int { MODE_SRC = 0, MODE_SPARSE = 1, MODE_DENSE = 2, MODE_ADJ = 3 };
+constexpr int N_MODES = 4;
+constexpr int MAX_S_ADJ = 4;      // states per workgroup of the adjoint mode
+// grad_in_lds: the adjoint keeps its parameter sums in LDS (mode MODE_ADJ only)
+int64_t lds_bytes(const DevMech& dm, int mode, int S, int waves, bool grad_in_lds = true);
 hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
-                  const double* state, const double* param, double* dstate, double* jac, int waves,
-                  int64_t lds, hipStream_t stream);
+                  const double* state, const double* param, double* dstate, double* jac,
+                  const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,
+                  hipStream_t stream);
+hipError_t zero_async(double* p, int64_t n, hipStream_t stream);
 // api.cpp
 void choose_launch(Mechanism& m);
 

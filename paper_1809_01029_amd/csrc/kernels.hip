@@ -23,6 +23,9 @@
 //     TQ, SQ           [Ns+1] energy- and mole-weighted concentration
 //                      partials, kept in the space of CSR rows 0 and 1,
 //                      which are written to the output from registers
+//     VV, JTV          [N]    (adjoint) the vector v and J^T v
+//     GR               [3 Nr] (adjoint, per workgroup, not per state) the
+//                      workgroup's sums of the Arrhenius-parameter derivatives
 // Reactions scatter into these with LDS FP64 atomics (ds_add_f64).  Because
 // the S states of one reaction sit in adjacent words, one atomic instruction
 // touches 64/S reactions in S-word blocks, which keeps LDS bank conflicts and
@@ -42,6 +45,18 @@
 // follows from differentiating dT/dt = -N/D and the V/P row from the ideal-gas
 // form of dV/dt or dP/dt; both need sum_i dE_i Q_ij and sum_i dOmega_i Q_ij,
 // accumulated in TQ and SQ.
+//
+// Adjoint.  J^T v is formed from the Jacobian as assembled in LDS (never
+// written to HBM): the T and V/P rows contribute v_T J_0j + v_S J_1j per
+// column, every species-row entry J_kj adds J_kj v_k to column j.  The
+// Arrhenius-parameter derivatives of v . dPhi/dt use that the source terms
+// depend on reaction i's parameters only through q_i:
+//     d(v . f)/d theta_i = lambda_i dq_i/d theta_i,
+//     lambda_i = v_T dTdot/dq_i + v_S dSdot/dq_i + V sum_k v_k nu_ki,
+//     dTdot/dq_i = -T dE_i / D',  CONP dSdot/dq_i = V/T dTdot/dq_i + V R T/P dOmega_i,
+//     CONV dSdot/dq_i = P/T dTdot/dq_i + R T dOmega_i,
+//     dq_i/d ln A = q_i - (Rf - Rr) Pr dc/dPr (falloff; q_i otherwise),
+//     dq_i/db = ln T dq_i/d ln A,  dq_i/d(Ea/R) = -dq_i/d ln A / T.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -179,11 +194,20 @@ __device__ inline void powd(double c, int nu, double& f, double& d) {
 
 }  // namespace
 
-int64_t lds_bytes(const DevMech& dm, int mode, int S, int waves) {
+int64_t lds_bytes(const DevMech& dm, int mode, int S, int waves, bool grad_in_lds) {
     int64_t d = 5 * (int64_t)(dm.ns + 1);
     if (mode != MODE_SRC) d += dm.nnz + dm.ns;
     if (mode == MODE_DENSE) d += dm.N;
-    return (d * S + (int64_t)RED_PER_WAVE * waves * S) * 8;
+    if (mode == MODE_ADJ) d += 2 * (int64_t)dm.N;
+    const int64_t per_group = mode == MODE_ADJ && grad_in_lds ? 3 * (int64_t)dm.nr_pad : 0;
+    return (d * S + (int64_t)RED_PER_WAVE * waves * S + per_group) * 8;
+}
+
+// zero n doubles (a kernel rather than a memset, so the call can be captured
+// in a graph)
+__global__ void pj_zero(double* __restrict__ p, long n) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        p[i] = 0.0;
 }
 
 template <int FORM, int LAYOUT, int MODE, int S>
@@ -191,9 +215,13 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
                                                           const double* __restrict__ state,
                                                           const double* __restrict__ param,
                                                           double* __restrict__ dstate,
-                                                          double* __restrict__ jac) {
+                                                          double* __restrict__ jac,
+                                                          const double* __restrict__ vin,
+                                                          double* __restrict__ grad,
+                                                          const int grad_in_lds) {
     extern __shared__ double lds[];
     constexpr bool JAC = MODE != MODE_SRC;
+    constexpr bool ADJ = MODE == MODE_ADJ;   // jac receives J^T v (state layout)
     const int ns = dm.ns, N = dm.N, bath = dm.bath, nnz = dm.nnz;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, nwave = nthr >> 6;
@@ -210,6 +238,9 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
     double* J = red + RED_PER_WAVE * nwave * S;
     double* B = J + (size_t)nnz * S;
     double* ROW = B + (size_t)ns * S;
+    double* VV = ROW;                     // adjoint: v, then J^T v
+    double* JTV = VV + (size_t)N * S;
+    double* GR = JTV + (size_t)N * S;     // adjoint: [3][nr_pad], per workgroup
     // The T and V/P rows (the first 2N CSR slots) go to the output straight
     // from registers; their LDS space holds the energy- and mole-weighted
     // partial sums meanwhile.
@@ -228,6 +259,13 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
         q0 = ngroups * x / 8 + (blockIdx.x >> 3);
         q1 = ngroups * (x + 1) / 8;
         qstep = gridDim.x >> 3;
+    }
+    // adjoint parameter sums: in LDS per workgroup when they fit (added to
+    // the output once at the end), else added to the output per group
+    const bool gr_lds = ADJ && grad && grad_in_lds;
+    if (gr_lds) {
+        for (int i = tid; i < 3 * dm.nr_pad; i += nthr) GR[i] = 0.0;
+        __syncthreads();
     }
     for (long qg = q0; qg < q1; qg += qstep) {
         const long st = qg * S + s;           // this thread's state
@@ -256,6 +294,10 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
         if (JAC) {
             for (int e = g; e < nnz; e += G) AT(J, e) = 0.0;
             for (int k = g; k < ns; k += G) AT(B, k) = 0.0;
+        }
+        if (ADJ) {
+            for (int i = g; i < N; i += G)
+                AT(VV, i) = LAYOUT == PJ_LAYOUT_F ? vin[(long)i * n + sc] : vin[sc * (long)N + i];
         }
         acc = block_dd_sum<S>(acc, red, wave, nwave, s);
         const double nsum = acc.hi;
@@ -297,6 +339,7 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
         const double Dp = tsum[0];
         const double dDpdT = tsum[1];
         __syncthreads();
+        const double vT = ADJ ? AT(VV, 0) : 0.0, vS = ADJ ? AT(VV, 1) : 0.0;
 
         // ---- reactions: rates of progress and Jacobian sub-products
         double racc[4] = {0.0, 0.0, 0.0, 0.0};  // TT, TS, ST, SS
@@ -359,6 +402,7 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
 
             // pressure modification
             double c = 1.0, dcdM = 0.0, dcdT = 0.0;
+            double Pr_dcdPr = 0.0;   // falloff: Pr dc/dPr (adjoint)
             if (kind != K_ELEM) {
                 const double M = Ctot + Meff;
                 if (kind == K_THREEBODY) {
@@ -397,6 +441,7 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
                     if (JAC) {
                         const double dc_dPr = F * ip * ip + F * ip * dlF_dlP;
                         dcdM = dc_dPr * rk;
+                        Pr_dcdPr = Pr * dc_dPr;
                         const double dlnPr = (fr_.b0 + fr_.theta0 * invT) * invT - (bexp + th * invT) * invT;
                         dcdT = dc_dPr * Pr * dlnPr + c * LN10 * dlF_dT;
                     }
@@ -446,6 +491,44 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
             racc[1] += dE * dqdS;
             racc[2] += dOm * dqdT;
             racc[3] += dOm * dqdS;
+
+            if (ADJ && grad) {
+                // lambda_i = v . df/dq_i, times dq_i/d ln A; summed over the
+                // workgroup's states (the S lanes of this reaction are adjacent)
+                double vn = 0.0;
+#pragma unroll
+                for (int a = 0; a < NSLOT; ++a) {
+                    if (!((cmask >> a) & 1)) continue;
+                    const bool row = nu[a] && spc[a] != bath;
+                    const double vk = AT(VV, row ? 2 + spc[a] : 0);
+                    vn += row ? sg[a] * vk : 0.0;
+                }
+                const double dTdq = -T * dE / Dp;
+                const double dSdq = FORM == PJ_CONP ? V * invT * dTdq + V * RU * T / P * dOm
+                                                    : P * invT * dTdq + RU * T * dOm;
+                const double lam = vT * dTdq + vS * dSdq + V * vn;
+                // each state's own ln T and 1/T, before the sum over states
+                double g0 = valid ? lam * (q - R * Pr_dcdPr) : 0.0;
+                double g1 = g0 * lnT, g2 = -g0 * invT;
+#pragma unroll
+                for (int o = 1; o < S; o <<= 1) {
+                    g0 += __shfl_xor(g0, o, 64);
+                    g1 += __shfl_xor(g1, o, 64);
+                    g2 += __shfl_xor(g2, o, 64);
+                }
+                if (s == 0) {
+                    if (gr_lds) {
+                        GR[p] += g0;
+                        GR[dm.nr_pad + p] += g1;
+                        GR[2 * dm.nr_pad + p] += g2;
+                    } else {
+                        const int o = dm.orig[p];
+                        atomicAdd(&grad[o], g0);
+                        atomicAdd(&grad[dm.nr + o], g1);
+                        atomicAdd(&grad[2 * dm.nr + o], g2);
+                    }
+                }
+            }
 
             // energy / mole weighted partials (T and V/P rows)
 #pragma unroll
@@ -577,7 +660,9 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
                     j1 = FORM == PJ_CONP ? V * invT * j0 + RTP * (AT(SQ, k) - sqb)
                                          : P * invT * j0 + RU * T * (AT(SQ, k) - sqb) * invV;
                 }
-                if (MODE == MODE_SPARSE) {
+                if (ADJ) {
+                    AT(JTV, j) = vT * j0 + vS * j1;
+                } else if (MODE == MODE_SPARSE) {
                     if (LAYOUT == PJ_LAYOUT_F) {
                         jac[(long)j * n + st] = j0;
                         jac[(long)(N + j) * n + st] = j1;
@@ -609,7 +694,17 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
         }
         __syncthreads();
 
-        if (MODE == MODE_SPARSE) {
+        if (ADJ) {
+            // species rows: J_kj v_k into column j
+            for (int e = 2 * N + g; e < nnz; e += G)
+                atomicAdd(&AT(JTV, dm.col_idx[e]), AT(J, e) * AT(VV, dm.row_of[e]));
+            __syncthreads();
+            if (valid)
+                for (int i = g; i < N; i += G) {
+                    if (LAYOUT == PJ_LAYOUT_F) jac[(long)i * n + st] = AT(JTV, i);
+                    else jac[st * (long)N + i] = AT(JTV, i);
+                }
+        } else if (MODE == MODE_SPARSE) {
             if (LAYOUT == PJ_LAYOUT_F) {
                 // S consecutive states of one slot are contiguous
                 if (valid)
@@ -644,12 +739,22 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
         }
         __syncthreads();
     }
+    if (gr_lds) {
+        // the workgroup's sums into the batch sums, in description order
+        for (int i = tid; i < dm.nr; i += nthr) {
+            const int o = dm.orig[i];
+            atomicAdd(&grad[o], GR[i]);
+            atomicAdd(&grad[dm.nr + o], GR[dm.nr_pad + i]);
+            atomicAdd(&grad[2 * dm.nr + o], GR[2 * dm.nr_pad + i]);
+        }
+    }
 #undef AT
 }
 
 template <int FORM, int LAYOUT, int MODE, int S>
 static hipError_t launch_t(const DevMech& dm, int64_t n, const double* state, const double* param,
-                           double* dstate, double* jac, int waves, int64_t lds, hipStream_t stream) {
+                           double* dstate, double* jac, const double* vin, double* grad,
+                           int grad_in_lds, int waves, int64_t lds, hipStream_t stream) {
     auto k = pj_kernel<FORM, LAYOUT, MODE, S>;
     if (lds > 65536) {
         // allow the kernel the device's whole LDS per workgroup
@@ -662,28 +767,44 @@ static hipError_t launch_t(const DevMech& dm, int64_t n, const double* state, co
     // one workgroup per group of S states, rounded down to a multiple of 8
     // (the XCD count)
     const int64_t groups = (n + S - 1) / S;
-    int64_t grid = groups < (1 << 30) ? groups : (1 << 30);
+    // the adjoint's workgroups each add their parameter sums to the output
+    // once: a bounded, persistent grid keeps those atomics few
+    const int64_t cap = MODE == MODE_ADJ ? 2048 : (1 << 30);
+    int64_t grid = groups < cap ? groups : cap;
     if (grid >= 8) grid &= ~(int64_t)7;
+    if (MODE == MODE_ADJ && grad) {
+        hipError_t e = zero_async(grad, 3 * (int64_t)dm.nr, stream);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * waves), (size_t)lds, stream, dm, (long)n,
-                       state, param, dstate, jac);
+                       state, param, dstate, jac, vin, grad, grad_in_lds);
+    return hipGetLastError();
+}
+
+hipError_t zero_async(double* p, int64_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(pj_zero, dim3(8), dim3(256), 0, stream, p, (long)n);
     return hipGetLastError();
 }
 
 hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
-                  const double* state, const double* param, double* dstate, double* jac, int waves,
-                  int64_t lds, hipStream_t stream) {
+                  const double* state, const double* param, double* dstate, double* jac,
+                  const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,
+                  hipStream_t stream) {
 #define PJ_CASE(F, L, M, SS)                                                                 \
     if (form == F && layout == L && mode == M && S == SS)                                    \
-        return launch_t<F, L, M, SS>(dm, n, state, param, dstate, jac, waves, lds, stream);
+        return launch_t<F, L, M, SS>(dm, n, state, param, dstate, jac, vin, grad, grad_in_lds, waves, \
+                                     lds, stream);
 #define PJ_S(F, L, M)                                                                        \
     PJ_CASE(F, L, M, 1) PJ_CASE(F, L, M, 2) PJ_CASE(F, L, M, 4) PJ_CASE(F, L, M, 8)          \
     PJ_CASE(F, L, M, 16) PJ_CASE(F, L, M, 32) PJ_CASE(F, L, M, 64)
-#define PJ_MODES(F, L) PJ_S(F, L, MODE_SRC) PJ_S(F, L, MODE_SPARSE) PJ_S(F, L, MODE_DENSE)
+#define PJ_SA(F, L) PJ_CASE(F, L, MODE_ADJ, 1) PJ_CASE(F, L, MODE_ADJ, 2) PJ_CASE(F, L, MODE_ADJ, 4)
+#define PJ_MODES(F, L) PJ_S(F, L, MODE_SRC) PJ_S(F, L, MODE_SPARSE) PJ_S(F, L, MODE_DENSE) PJ_SA(F, L)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_F)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_C)
     PJ_MODES(PJ_CONV, PJ_LAYOUT_F)
     PJ_MODES(PJ_CONV, PJ_LAYOUT_C)
 #undef PJ_MODES
+#undef PJ_SA
 #undef PJ_S
 #undef PJ_CASE
     return hipErrorInvalidValue;

@@ -439,6 +439,10 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     std::vector<int32_t> dense_rows;
     for (int k = 0; k < ns; ++k) if (dense_row[k]) dense_rows.push_back(k);
     std::vector<uint16_t> col16(m.col_idx.begin(), m.col_idx.end());
+    std::vector<uint16_t> row16(m.nnz);
+    for (int i = 0; i < N; ++i)
+        for (int e = m.row_ptr[i]; e < m.row_ptr[i + 1]; ++e) row16[e] = (uint16_t)i;
+    std::vector<int32_t> orig(m.order.begin(), m.order.end());
     const int n_dense = (int)dense_rows.size();
     if (dense_rows.empty()) dense_rows.push_back(-1);
 
@@ -452,6 +456,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     size_t o_eff = place(effrec.size() * sizeof(EffRec));
     size_t o_rowp = place(m.row_ptr.size() * 4), o_col = place(col16.size() * 2),
            o_dr = place(dense_rows.size() * 4);
+    size_t o_rowof = place(row16.size() * 2), o_orig = place(orig.size() * 4);
     std::vector<unsigned char> host(total, 0);
     auto put = [&](size_t off, const void* src, size_t bytes) { std::memcpy(host.data() + off, src, bytes); };
     put(o_th, th.data(), th.size() * sizeof(ThermoRec));
@@ -464,6 +469,8 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     put(o_rowp, m.row_ptr.data(), m.row_ptr.size() * 4);
     put(o_col, col16.data(), col16.size() * 2);
     put(o_dr, dense_rows.data(), dense_rows.size() * 4);
+    put(o_rowof, row16.data(), row16.size() * 2);
+    put(o_orig, orig.data(), orig.size() * 4);
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) { err = "no HIP device"; return PJ_E_DEVICE; }
@@ -495,6 +502,10 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.row_ptr = (const int32_t*)P(o_rowp);
     dm.col_idx = (const uint16_t*)P(o_col);
     dm.dense_rows = (const int32_t*)P(o_dr);
+    dm.row_of = (const uint16_t*)P(o_rowof);
+    dm.orig = (const int32_t*)P(o_orig);
+    m.h_rec = rec;
+    m.off_rec = o_rec;
 
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)

@@ -154,3 +154,31 @@ def test_launch_shape_and_autotune_argument_checks(api, tmp_path):
     assert lib.pj_mech_autotune(h, 1, *no_states) == 1
     assert lib.pj_mech_autotune(h, 1, *args) == 1
     assert b"not uploaded" in lib.pj_last_error()
+
+
+def test_adjoint_and_arrhenius_argument_checks(api, tmp_path):
+    lib = api.library()
+    m = synth.make_mechanism(7, 10, 3, mix=synth.MixSpec(0.1, 0.2, 0.2), zipf=0.5)
+    mech = api.Mechanism(_write(tmp_path, synth.dumps(m)), upload=False)
+    h = mech.handle
+    dummy = ctypes.c_void_p(16)
+    # NULL v, NULL J^T v, not uploaded, bad enums
+    assert lib.pj_eval_adjoint(h, 0, 0, 4, dummy, dummy, None, dummy, None, None, None) == 1
+    assert b"NULL vector" in lib.pj_last_error()
+    assert lib.pj_eval_adjoint(h, 0, 0, 4, dummy, dummy, dummy, None, None, None, None) == 1
+    assert lib.pj_eval_adjoint(h, 2, 0, 4, dummy, dummy, dummy, dummy, None, None, None) == 1
+    assert lib.pj_eval_adjoint(h, 0, 0, 4, dummy, dummy, dummy, dummy, None, None, None) == 1
+    assert b"not uploaded" in lib.pj_last_error()
+    assert lib.pj_eval_adjoint(None, 0, 0, 4, dummy, dummy, dummy, dummy, None, None, None) == 1
+    # parameters round-trip on the host, in description order
+    lnA, b, th = mech.arrhenius()
+    np.testing.assert_array_equal(lnA, [r.lnA for r in m.reactions])
+    np.testing.assert_array_equal(th, [r.theta for r in m.reactions])
+    mech.set_arrhenius(lnA=lnA + 1.0)
+    a2, b2, t2 = mech.arrhenius()
+    np.testing.assert_array_equal(a2, lnA + 1.0)
+    np.testing.assert_array_equal(b2, b)
+    assert lib.pj_mech_set_arrhenius(None, None, None, None) == 1
+    # the adjoint mode keeps at most 4 states per workgroup
+    mech.set_launch(16, 1)
+    assert mech.launch_shape(3)[0] <= 4
