@@ -215,6 +215,45 @@ pj_status pj_mech_autotune(pj_mech* mech, int mode, pj_form form, pj_layout layo
 /* Bytes of LDS one workgroup needs for source terms (0) or the sparse Jacobian (1). */
 int64_t pj_mech_lds_bytes(const pj_mech* mech, int for_jacobian);
 
+/*
+ * Ragged multi-mechanism batches: segments of states of different mechanisms
+ * (all uploaded on one device) evaluated by one persistent launch whose
+ * workgroups take groups of states of any segment; the launch can be
+ * captured once into a HIP graph and replayed.  Modes: 0 source terms
+ * (d_out unused, source terms into d_dstate), 1 sparse Jacobian (d_out: CSR
+ * values, d_dstate optional fused source terms), 3 adjoint (d_out: J^T v,
+ * d_v required, d_grad optional 3*Nr parameter sums of that segment).
+ * Buffers are caller-owned device memory in the layout given at evaluation,
+ * and must stay valid while the batch (or its graph) may run.  States per
+ * workgroup are at most 4 and shared by all segments; the LDS a workgroup
+ * gets is that of the largest segment.
+ *
+ * pj_batch_add records a segment (n_states may be 0); adding or clearing
+ * segments, or changing the launch shape, discards a captured graph.
+ * pj_batch_eval enqueues the batch on `stream` (the first call for a launch
+ * shape uploads a small segment table synchronously).  pj_batch_eval_graph
+ * captures the same work once per (mode, form, layout, shape) on a private
+ * stream and launches the graph on `stream`; later calls replay it.
+ * pj_batch_autotune times every fitting shape (as pj_mech_autotune) and keeps
+ * the fastest for that mode.  Errors as for the per-mechanism calls, with the
+ * segment index in the message (pj_batch_last_error).
+ */
+typedef struct pj_batch pj_batch; /* opaque, library-owned */
+pj_status pj_batch_create(pj_batch** out);
+void pj_batch_free(pj_batch* batch); /* NULL-safe */
+pj_status pj_batch_add(pj_batch* batch, const pj_mech* mech, int64_t n_states, const double* d_state,
+                       const double* d_param, double* d_out, double* d_dstate_or_null,
+                       const double* d_v_or_null, double* d_grad_or_null);
+pj_status pj_batch_clear(pj_batch* batch);
+int pj_batch_size(const pj_batch* batch); /* segments, -1 for NULL */
+pj_status pj_batch_set_launch(pj_batch* batch, int mode, int states_per_group, int waves_per_group);
+int pj_batch_launch_shape(const pj_batch* batch, int mode, int* states_per_group, int* waves_per_group);
+pj_status pj_batch_eval(pj_batch* batch, int mode, pj_form form, pj_layout layout, pj_stream stream);
+pj_status pj_batch_eval_graph(pj_batch* batch, int mode, pj_form form, pj_layout layout, pj_stream stream);
+pj_status pj_batch_autotune(pj_batch* batch, int mode, pj_form form, pj_layout layout, int reps,
+                            pj_stream stream, int* states_per_group, int* waves_per_group, float* ms);
+const char* pj_batch_last_error(void);
+
 /* Thread-local description of the last error ("" if none). */
 const char* pj_last_error(void);
 

@@ -64,6 +64,30 @@ _lib.pj_mech_set_arrhenius.argtypes = [_P, _DP, _DP, _DP]
 _lib.pj_mech_set_arrhenius.restype = ctypes.c_int
 _lib.pj_mech_get_arrhenius.argtypes = [_P, _DP, _DP, _DP]
 _lib.pj_mech_get_arrhenius.restype = ctypes.c_int
+_lib.pj_batch_create.argtypes = [ctypes.POINTER(_P)]
+_lib.pj_batch_create.restype = ctypes.c_int
+_lib.pj_batch_free.argtypes = [_P]
+_lib.pj_batch_free.restype = None
+_lib.pj_batch_add.argtypes = [_P, _P, _I64, _P, _P, _P, _P, _P, _P]
+_lib.pj_batch_add.restype = ctypes.c_int
+_lib.pj_batch_clear.argtypes = [_P]
+_lib.pj_batch_clear.restype = ctypes.c_int
+_lib.pj_batch_size.argtypes = [_P]
+_lib.pj_batch_size.restype = ctypes.c_int
+_lib.pj_batch_set_launch.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+_lib.pj_batch_set_launch.restype = ctypes.c_int
+_lib.pj_batch_launch_shape.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.pj_batch_launch_shape.restype = ctypes.c_int
+_lib.pj_batch_eval.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P]
+_lib.pj_batch_eval.restype = ctypes.c_int
+_lib.pj_batch_eval_graph.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P]
+_lib.pj_batch_eval_graph.restype = ctypes.c_int
+_lib.pj_batch_autotune.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P,
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_float)]
+_lib.pj_batch_autotune.restype = ctypes.c_int
+_lib.pj_batch_last_error.argtypes = []
+_lib.pj_batch_last_error.restype = ctypes.c_char_p
 _lib.pj_mech_set_waves_per_state.argtypes = [_P, ctypes.c_int]
 _lib.pj_mech_set_waves_per_state.restype = ctypes.c_int
 _lib.pj_mech_waves_per_state.argtypes = [_P, ctypes.c_int]
@@ -370,6 +394,70 @@ def autotune(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, form: st
                                  _ptr(out), _ptr(dstate) if m else None, int(reps), _stream(stream),
                                  ctypes.byref(S), ctypes.byref(W), ctypes.byref(ms)), "pj_mech_autotune")
     return S.value, W.value, ms.value
+
+
+class Batch:
+    """A ragged multi-mechanism batch (pj_batch_*): segments of states of
+    different mechanisms evaluated by one launch, or by a captured HIP graph.
+    The tensors of every segment are kept referenced here while the batch
+    lives.  ``mode``: "source", "sparse" or "adjoint"."""
+
+    def __init__(self):
+        h = _P()
+        _check(_lib.pj_batch_create(ctypes.byref(h)), "pj_batch_create")
+        self._h = h
+        self._keep = []
+
+    def _bcheck(self, st, where):
+        if st != 0:
+            raise PjError(st, f"{where}: {_lib.pj_batch_last_error().decode()}")
+
+    def add(self, mech: Mechanism, state: torch.Tensor, param: torch.Tensor, layout: str,
+            out: Optional[torch.Tensor] = None, dstate: Optional[torch.Tensor] = None,
+            v: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None):
+        n = _n_states(mech, state, layout)
+        _need(state, _state_shape(mech, n, layout), "state", None)
+        _need(param, (n,), "param", state.device)
+        self._keep.append((mech, state, param, out, dstate, v, grad))
+        self._bcheck(_lib.pj_batch_add(self._h, mech.handle, n, _ptr(state), _ptr(param), _ptr(out), _ptr(dstate),
+                                       _ptr(v), _ptr(grad)), "pj_batch_add")
+
+    def clear(self):
+        self._keep = []
+        self._bcheck(_lib.pj_batch_clear(self._h), "pj_batch_clear")
+
+    def __len__(self):
+        return _lib.pj_batch_size(self._h)
+
+    def set_launch(self, mode: str, states_per_group: int = 0, waves_per_group: int = 0):
+        self._bcheck(_lib.pj_batch_set_launch(self._h, MODES[mode], states_per_group, waves_per_group),
+                     "pj_batch_set_launch")
+
+    def launch_shape(self, mode: str):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        if _lib.pj_batch_launch_shape(self._h, MODES[mode], ctypes.byref(a), ctypes.byref(b)) != 0:
+            raise PjError(1, "pj_batch_launch_shape")
+        return a.value, b.value
+
+    def eval(self, mode: str, form: str = "conp", layout: str = "F", graph: bool = False, stream=None):
+        f = _lib.pj_batch_eval_graph if graph else _lib.pj_batch_eval
+        self._bcheck(f(self._h, MODES[mode], FORMS[form], LAYOUTS[layout], _stream(stream)),
+                     "pj_batch_eval_graph" if graph else "pj_batch_eval")
+
+    def autotune(self, mode: str, form: str = "conp", layout: str = "F", reps: int = 2, stream=None):
+        S, W, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+        self._bcheck(_lib.pj_batch_autotune(self._h, MODES[mode], FORMS[form], LAYOUTS[layout], reps,
+                                            _stream(stream), ctypes.byref(S), ctypes.byref(W), ctypes.byref(ms)),
+                     "pj_batch_autotune")
+        return S.value, W.value, ms.value
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pj_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 def dense_as_sij(jac: torch.Tensor, layout: str) -> torch.Tensor:

@@ -33,7 +33,7 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src in ("mech.cpp", "api.cpp"):
+    for src in ("mech.cpp", "api.cpp", "batch.cpp"):
         o = os.path.join(BUILD, src + ".o")
         _run([HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)

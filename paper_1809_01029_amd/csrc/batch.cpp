@@ -1,0 +1,361 @@
+// C-ABI of ragged multi-mechanism batches (declared in include/pjac.h):
+// segments of states of different mechanisms evaluated by one persistent
+// launch, optionally captured once into a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+pj_status fail(pj_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+bool batch_mode(int mode) { return mode == pj::MODE_SRC || mode == pj::MODE_SPARSE || mode == pj::MODE_ADJ; }
+
+}  // namespace
+
+struct pj_batch {
+    struct Seg {
+        const pj_mech* mech;
+        int64_t n;
+        const double* state;
+        const double* param;
+        double* out;
+        double* dstate;
+        const double* v;
+        double* grad;
+    };
+    std::vector<Seg> segs;
+    int device = -1;
+    int user_S[pj::N_MODES] = {0, 0, 0, 0}, user_W[pj::N_MODES] = {0, 0, 0, 0};
+    // device copy of the segment table, for the shape it was built with
+    pj::BatchSeg* d_segs = nullptr;
+    size_t d_cap = 0;
+    int table_S = 0, table_nseg = 0;
+    int64_t table_total = 0;
+    bool table_valid = false;
+    // captured graph and what it was captured for
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int g_mode = -1, g_form = -1, g_layout = -1, g_S = 0, g_W = 0;
+    hipStream_t capture_stream = nullptr;
+
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        g_mode = -1;
+    }
+};
+
+namespace {
+
+int64_t seg_lds(const pj_batch::Seg& sg, int mode, int S, int W) {
+    return pj::lds_bytes(sg.mech->m.dm, mode, S, W, false);
+}
+
+int lds_max_of(const pj_batch* b) { return b->segs.empty() ? 0 : b->segs[0].mech->m.lds_max; }
+
+int64_t batch_lds_states(const pj_batch* b, int mode, int S, int W) {
+    int64_t l = 0;
+    for (auto& sg : b->segs) l = std::max(l, seg_lds(sg, mode, S, W));
+    return l;
+}
+
+int lds_max_of(const pj_batch* b);
+
+// adjoint: room for the largest segment's parameter sums after the per-state
+// arrays, when it fits; gr_off receives their offset in doubles, or -1
+int64_t batch_lds(const pj_batch* b, int mode, int S, int W, int64_t* gr_off = nullptr) {
+    const int64_t l = batch_lds_states(b, mode, S, W);
+    if (gr_off) *gr_off = -1;
+    if (mode != pj::MODE_ADJ) return l;
+    int64_t nrp = 0;
+    for (auto& sg : b->segs) nrp = std::max<int64_t>(nrp, sg.mech->m.dm.nr_pad);
+    const int64_t with = l + 3 * nrp * 8;
+    if (with > lds_max_of(b)) return l;
+    if (gr_off) *gr_off = l / 8;
+    return with;
+}
+
+// launch shape of the batch for a mode: the user's if it fits, else the most
+// states per workgroup (<= 4) that fit every segment's working set, with
+// enough waves for about 8 resident waves per compute unit
+void batch_shape(const pj_batch* b, int mode, int& S, int& W) {
+    const int mx = lds_max_of(b);
+    S = 1;
+    for (int c = 4; c >= 1; c >>= 1)
+        if (batch_lds(b, mode, c, 1) <= mx) { S = c; break; }
+    if (b->user_S[mode] && b->user_S[mode] <= 4 &&
+        batch_lds(b, mode, b->user_S[mode], b->user_W[mode] ? b->user_W[mode] : 1) <= mx)
+        S = b->user_S[mode];
+    W = 1;
+    while (W < 8) {
+        const int64_t l = batch_lds(b, mode, S, W);
+        if (l > mx || (mx / l) * W >= 8) break;
+        W *= 2;
+    }
+    if (b->user_W[mode] && batch_lds(b, mode, S, b->user_W[mode]) <= mx) W = b->user_W[mode];
+}
+
+pj_status check_segments(const pj_batch* b, int mode, pj_form form, pj_layout layout) {
+    if (!batch_mode(mode)) return fail(PJ_E_INVALID, "batch mode must be 0 (source), 1 (sparse) or 3 (adjoint)");
+    if (form != PJ_CONP && form != PJ_CONV) return fail(PJ_E_INVALID, "bad form");
+    if (layout != PJ_LAYOUT_F && layout != PJ_LAYOUT_C) return fail(PJ_E_INVALID, "bad layout");
+    int dev = -1;
+    for (size_t i = 0; i < b->segs.size(); ++i) {
+        const auto& sg = b->segs[i];
+        const std::string at = "segment " + std::to_string(i) + ": ";
+        if (!sg.mech->m.dbuf) return fail(PJ_E_INVALID, at + "mechanism not uploaded to a device");
+        if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(PJ_E_DEVICE, "no HIP device");
+        if (sg.mech->m.device != dev)
+            return fail(PJ_E_INVALID, at + "the current HIP device is not the one the mechanism was loaded on");
+        if (sg.n == 0) continue;
+        if (!sg.state || !sg.param) return fail(PJ_E_INVALID, at + "NULL state or parameter");
+        if (mode == pj::MODE_SRC && !sg.dstate) return fail(PJ_E_INVALID, at + "NULL source-term output");
+        if (mode != pj::MODE_SRC && !sg.out) return fail(PJ_E_INVALID, at + "NULL output");
+        if (mode == pj::MODE_ADJ && !sg.v) return fail(PJ_E_INVALID, at + "NULL vector v");
+    }
+    return PJ_OK;
+}
+
+// (re)build the device segment table for S states per workgroup
+pj_status upload_table(pj_batch* b, int S) {
+    if (b->table_valid && b->table_S == S) return PJ_OK;
+    std::vector<pj::BatchSeg> t;
+    long g0 = 0;
+    for (auto& sg : b->segs) {
+        if (sg.n == 0) continue;
+        pj::BatchSeg x{};
+        x.dm = sg.mech->m.dm;
+        x.n = (long)sg.n;
+        x.state = sg.state;
+        x.param = sg.param;
+        x.dstate = sg.dstate;
+        x.out = sg.out;
+        x.vin = sg.v;
+        x.grad = sg.grad;
+        x.g0 = g0;
+        g0 += (long)((sg.n + S - 1) / S);
+        t.push_back(x);
+    }
+    const size_t bytes = std::max<size_t>(1, t.size()) * sizeof(pj::BatchSeg);
+    if (bytes > b->d_cap) {
+        if (b->d_segs) (void)hipFree(b->d_segs);
+        b->d_segs = nullptr;
+        b->d_cap = 0;
+        if (hipMalloc(&b->d_segs, bytes) != hipSuccess) return fail(PJ_E_DEVICE, "hipMalloc of the segment table failed");
+        b->d_cap = bytes;
+    }
+    if (!t.empty() && hipMemcpy(b->d_segs, t.data(), t.size() * sizeof(pj::BatchSeg), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(PJ_E_DEVICE, "upload of the segment table failed");
+    b->table_S = S;
+    b->table_nseg = (int)t.size();
+    b->table_total = g0;
+    b->table_valid = true;
+    return PJ_OK;
+}
+
+// enqueue the whole batch (zeroing of the adjoint sums, then one launch)
+pj_status enqueue(pj_batch* b, int mode, pj_form form, pj_layout layout, int S, int W, hipStream_t st) {
+    pj_status r = upload_table(b, S);
+    if (r != PJ_OK) return r;
+    if (mode == pj::MODE_ADJ)
+        for (auto& sg : b->segs)
+            if (sg.grad) {
+                hipError_t e = pj::zero_async(sg.grad, 3 * (int64_t)sg.mech->m.nr, st);
+                if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("zeroing failed: ") + hipGetErrorString(e));
+            }
+    if (b->table_total == 0) return PJ_OK;
+    int64_t gr_off = -1;
+    const int64_t lds = batch_lds(b, mode, S, W, &gr_off);
+    hipError_t e = pj::launch_batch(mode, form, layout, S, W, lds, b->d_segs, b->table_nseg, b->table_total,
+                                    gr_off, st);
+    if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
+    return PJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pj_status pj_batch_create(pj_batch** out) {
+    if (!out) return fail(PJ_E_INVALID, "NULL output handle");
+    *out = new (std::nothrow) pj_batch();
+    if (!*out) return fail(PJ_E_NOMEM, "out of host memory");
+    g_err.clear();
+    return PJ_OK;
+}
+
+void pj_batch_free(pj_batch* b) {
+    if (!b) return;
+    b->drop_graph();
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->d_segs) (void)hipFree(b->d_segs);
+    delete b;
+}
+
+pj_status pj_batch_add(pj_batch* b, const pj_mech* mech, int64_t n_states, const double* d_state,
+                       const double* d_param, double* d_out, double* d_dstate_or_null,
+                       const double* d_v_or_null, double* d_grad_or_null) {
+    if (!b || !mech) return fail(PJ_E_INVALID, "NULL batch or mechanism");
+    if (n_states < 0) return fail(PJ_E_INVALID, "negative n_states");
+    if (!b->segs.empty() && mech->m.device != b->segs[0].mech->m.device)
+        return fail(PJ_E_INVALID, "all mechanisms of a batch must live on one device");
+    b->segs.push_back({mech, n_states, d_state, d_param, d_out, d_dstate_or_null, d_v_or_null, d_grad_or_null});
+    b->table_valid = false;
+    b->drop_graph();
+    g_err.clear();
+    return PJ_OK;
+}
+
+pj_status pj_batch_clear(pj_batch* b) {
+    if (!b) return fail(PJ_E_INVALID, "NULL batch");
+    b->segs.clear();
+    b->table_valid = false;
+    b->drop_graph();
+    g_err.clear();
+    return PJ_OK;
+}
+
+int pj_batch_size(const pj_batch* b) { return b ? (int)b->segs.size() : -1; }
+
+pj_status pj_batch_set_launch(pj_batch* b, int mode, int states_per_group, int waves_per_group) {
+    if (!b) return fail(PJ_E_INVALID, "NULL batch");
+    if (!batch_mode(mode)) return fail(PJ_E_INVALID, "bad mode");
+    if (states_per_group != 0 && states_per_group != 1 && states_per_group != 2 && states_per_group != 4)
+        return fail(PJ_E_INVALID, "states_per_group must be 0, 1, 2 or 4");
+    if (waves_per_group != 0 && waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4 &&
+        waves_per_group != 8)
+        return fail(PJ_E_INVALID, "waves_per_group must be 0, 1, 2, 4 or 8");
+    b->user_S[mode] = states_per_group;
+    b->user_W[mode] = waves_per_group;
+    b->drop_graph();
+    g_err.clear();
+    return PJ_OK;
+}
+
+int pj_batch_launch_shape(const pj_batch* b, int mode, int* states_per_group, int* waves_per_group) {
+    if (!b || !batch_mode(mode) || b->segs.empty()) return -1;
+    int S, W;
+    batch_shape(b, mode, S, W);
+    if (states_per_group) *states_per_group = S;
+    if (waves_per_group) *waves_per_group = W;
+    return 0;
+}
+
+pj_status pj_batch_eval(pj_batch* b, int mode, pj_form form, pj_layout layout, pj_stream stream) {
+    if (!b) return fail(PJ_E_INVALID, "NULL batch");
+    pj_status r = check_segments(b, mode, form, layout);
+    if (r != PJ_OK) return r;
+    if (b->segs.empty()) { g_err.clear(); return PJ_OK; }
+    int S, W;
+    batch_shape(b, mode, S, W);
+    if (batch_lds(b, mode, S, W) > lds_max_of(b))
+        return fail(PJ_E_UNSUPPORTED, "a segment's working set exceeds the LDS of one workgroup");
+    r = enqueue(b, mode, form, layout, S, W, (hipStream_t)stream);
+    if (r == PJ_OK) g_err.clear();
+    return r;
+}
+
+pj_status pj_batch_eval_graph(pj_batch* b, int mode, pj_form form, pj_layout layout, pj_stream stream) {
+    if (!b) return fail(PJ_E_INVALID, "NULL batch");
+    pj_status r = check_segments(b, mode, form, layout);
+    if (r != PJ_OK) return r;
+    if (b->segs.empty()) { g_err.clear(); return PJ_OK; }
+    int S, W;
+    batch_shape(b, mode, S, W);
+    if (batch_lds(b, mode, S, W) > lds_max_of(b))
+        return fail(PJ_E_UNSUPPORTED, "a segment's working set exceeds the LDS of one workgroup");
+    if (!b->exec || b->g_mode != mode || b->g_form != form || b->g_layout != layout || b->g_S != S || b->g_W != W) {
+        b->drop_graph();
+        r = upload_table(b, S);   // synchronous, outside the capture
+        if (r != PJ_OK) return r;
+        if (!b->capture_stream && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(PJ_E_DEVICE, "hipStreamCreate failed");
+        hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+        r = enqueue(b, mode, form, layout, S, W, b->capture_stream);
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(b->capture_stream, &gr);
+        if (r != PJ_OK) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return r;
+        }
+        if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        b->graph = gr;
+        e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            b->drop_graph();
+            return fail(PJ_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        b->g_mode = mode;
+        b->g_form = form;
+        b->g_layout = layout;
+        b->g_S = S;
+        b->g_W = W;
+    }
+    hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    g_err.clear();
+    return PJ_OK;
+}
+
+pj_status pj_batch_autotune(pj_batch* b, int mode, pj_form form, pj_layout layout, int reps, pj_stream stream,
+                            int* states_per_group, int* waves_per_group, float* ms) {
+    if (!b) return fail(PJ_E_INVALID, "NULL batch");
+    if (reps < 1) return fail(PJ_E_INVALID, "reps must be at least 1");
+    pj_status r = check_segments(b, mode, form, layout);
+    if (r != PJ_OK) return r;
+    if (b->segs.empty()) return fail(PJ_E_INVALID, "empty batch");
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(PJ_E_DEVICE, "hipEventCreate failed");
+    }
+    const int mx = lds_max_of(b);
+    int bS = 0, bW = 0;
+    float best = -1.0f;
+    pj_status err = PJ_OK;
+    for (int S = 1; S <= 4 && err == PJ_OK; S *= 2)
+        for (int W = 1; W <= 8 && err == PJ_OK; W *= 2) {
+            if (batch_lds(b, mode, S, W) > mx) continue;
+            err = enqueue(b, mode, form, layout, S, W, st);   // warm-up
+            hipError_t e = err == PJ_OK ? hipEventRecord(e0, st) : hipSuccess;
+            for (int k = 0; k < reps && err == PJ_OK && e == hipSuccess; ++k) err = enqueue(b, mode, form, layout, S, W, st);
+            if (err != PJ_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) { err = fail(PJ_E_DEVICE, std::string("autotuning: ") + hipGetErrorString(e)); break; }
+            t /= (float)reps;
+            if (best < 0.0f || t < best) { best = t; bS = S; bW = W; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != PJ_OK) return err;
+    b->user_S[mode] = bS;
+    b->user_W[mode] = bW;
+    b->drop_graph();
+    if (states_per_group) *states_per_group = bS;
+    if (waves_per_group) *waves_per_group = bW;
+    if (ms) *ms = best;
+    g_err.clear();
+    return PJ_OK;
+}
+
+const char* pj_batch_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

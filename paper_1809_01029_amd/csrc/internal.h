@@ -141,6 +141,20 @@ struct Mechanism {
     int lds_max = 0;
 };
 
+// One segment of a ragged multi-mechanism batch, as the batch kernel reads
+// it from device memory.
+struct BatchSeg {
+    DevMech dm;
+    long n;                    // states of this segment
+    const double* state;
+    const double* param;
+    double* dstate;            // source terms (source mode) or fused source output
+    double* out;               // CSR values (sparse) or J^T v (adjoint)
+    const double* vin;         // adjoint: v
+    double* grad;              // adjoint: parameter sums (3 Nr) or NULL
+    long g0;                   // first global group index of this segment
+};
+
 // mech.cpp
 pj_status build_mechanism(const char* path, Mechanism& m, std::string& err);
 pj_status upload_mechanism(Mechanism& m, std::string& err);
@@ -156,6 +170,11 @@ hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int6
                   const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,
                   hipStream_t stream);
 hipError_t zero_async(double* p, int64_t n, hipStream_t stream);
+// batch kernel (modes source, sparse, adjoint; S = 1, 2, 4)
+// gr_off: LDS offset (doubles) of the adjoint's per-segment parameter sums, or -1
+hipError_t launch_batch(int mode, int form, int layout, int S, int waves, int64_t lds,
+                        const BatchSeg* d_segs, int nseg, int64_t total_groups, int64_t gr_off,
+                        hipStream_t stream);
 // api.cpp
 void choose_launch(Mechanism& m);
 

@@ -210,15 +210,19 @@ __global__ void pj_zero(double* __restrict__ p, long n) {
         p[i] = 0.0;
 }
 
+// One group of S consecutive states (group index qg of a batch of n): the
+// body shared by the per-mechanism kernel and the ragged multi-mechanism
+// kernel.  GR / gr_lds: the adjoint's per-workgroup parameter sums in LDS (or
+// per-group device atomics when gr_lds is false).
 template <int FORM, int LAYOUT, int MODE, int S>
-__global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const long n,
-                                                          const double* __restrict__ state,
-                                                          const double* __restrict__ param,
-                                                          double* __restrict__ dstate,
-                                                          double* __restrict__ jac,
-                                                          const double* __restrict__ vin,
-                                                          double* __restrict__ grad,
-                                                          const int grad_in_lds) {
+__device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
+                                           const double* __restrict__ state,
+                                           const double* __restrict__ param,
+                                           double* __restrict__ dstate,
+                                           double* __restrict__ jac,
+                                           const double* __restrict__ vin,
+                                           double* __restrict__ grad,
+                                           const bool gr_lds, double* GR, const long qg) {
     extern __shared__ double lds[];
     constexpr bool JAC = MODE != MODE_SRC;
     constexpr bool ADJ = MODE == MODE_ADJ;   // jac receives J^T v (state layout)
@@ -240,7 +244,6 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
     double* ROW = B + (size_t)ns * S;
     double* VV = ROW;                     // adjoint: v, then J^T v
     double* JTV = VV + (size_t)N * S;
-    double* GR = JTV + (size_t)N * S;     // adjoint: [3][nr_pad], per workgroup
     // The T and V/P rows (the first 2N CSR slots) go to the output straight
     // from registers; their LDS space holds the energy- and mole-weighted
     // partial sums meanwhile.
@@ -248,26 +251,7 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
     double* SQ = J + (size_t)N * S;
 #define AT(arr, i) (arr)[(size_t)(i) * S + s]
 
-    // Groups of S consecutive states.  Consecutive groups go to workgroups of
-    // the same XCD (workgroups are handed to the 8 XCDs round-robin), so that
-    // the partial cache lines of layout-F arrays of neighbouring states meet
-    // in one L2: XCD x takes the contiguous range [ng x/8, ng (x+1)/8).
-    const long ngroups = (n + S - 1) / S;
-    long q0 = blockIdx.x, q1 = ngroups, qstep = gridDim.x;
-    if (gridDim.x >= 8 && (gridDim.x & 7) == 0) {
-        const long x = blockIdx.x & 7;
-        q0 = ngroups * x / 8 + (blockIdx.x >> 3);
-        q1 = ngroups * (x + 1) / 8;
-        qstep = gridDim.x >> 3;
-    }
-    // adjoint parameter sums: in LDS per workgroup when they fit (added to
-    // the output once at the end), else added to the output per group
-    const bool gr_lds = ADJ && grad && grad_in_lds;
-    if (gr_lds) {
-        for (int i = tid; i < 3 * dm.nr_pad; i += nthr) GR[i] = 0.0;
-        __syncthreads();
-    }
-    for (long qg = q0; qg < q1; qg += qstep) {
+    {
         const long st = qg * S + s;           // this thread's state
         const bool valid = st < n;
         const long sc = valid ? st : n - 1;   // states past the end compute a copy of the last
@@ -628,7 +612,7 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
         }
         if (!JAC) {
             __syncthreads();
-            continue;
+            return;
         }
 
         // ---- Jacobian: T and V/P rows, closure of the species rows
@@ -738,7 +722,55 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
             }
         }
         __syncthreads();
+        }
+#undef AT
+}
+
+// LDS offset (doubles) of the adjoint's per-workgroup parameter sums
+__device__ inline size_t gr_offset(const DevMech& dm, int S, int nwave) {
+    return ((size_t)5 * (dm.ns + 1) + (size_t)RED_PER_WAVE * nwave + dm.nnz + dm.ns + 2 * (size_t)dm.N) * S;
+}
+
+// Groups of S consecutive states.  Consecutive groups go to workgroups of
+// the same XCD (workgroups are handed to the 8 XCDs round-robin), so that the
+// partial cache lines of layout-F arrays of neighbouring states meet in one
+// L2: XCD x takes the contiguous range [ng x/8, ng (x+1)/8).
+__device__ inline void group_range(long ngroups, long& q0, long& q1, long& qstep) {
+    q0 = blockIdx.x;
+    q1 = ngroups;
+    qstep = gridDim.x;
+    if (gridDim.x >= 8 && (gridDim.x & 7) == 0) {
+        const long x = blockIdx.x & 7;
+        q0 = ngroups * x / 8 + (blockIdx.x >> 3);
+        q1 = ngroups * (x + 1) / 8;
+        qstep = gridDim.x >> 3;
     }
+}
+
+template <int FORM, int LAYOUT, int MODE, int S>
+__global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const long n,
+                                                          const double* __restrict__ state,
+                                                          const double* __restrict__ param,
+                                                          double* __restrict__ dstate,
+                                                          double* __restrict__ jac,
+                                                          const double* __restrict__ vin,
+                                                          double* __restrict__ grad,
+                                                          const int grad_in_lds) {
+    extern __shared__ double lds[];
+    constexpr bool ADJ = MODE == MODE_ADJ;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    double* GR = lds + gr_offset(dm, S, nthr >> 6);
+    long q0, q1, qstep;
+    group_range((n + S - 1) / S, q0, q1, qstep);
+    // adjoint parameter sums: in LDS per workgroup when they fit (added to
+    // the output once at the end), else added to the output per group
+    const bool gr_lds = ADJ && grad && grad_in_lds;
+    if (gr_lds) {
+        for (int i = tid; i < 3 * dm.nr_pad; i += nthr) GR[i] = 0.0;
+        __syncthreads();
+    }
+    for (long qg = q0; qg < q1; qg += qstep)
+        eval_group<FORM, LAYOUT, MODE, S>(dm, n, state, param, dstate, jac, vin, grad, gr_lds, GR, qg);
     if (gr_lds) {
         // the workgroup's sums into the batch sums, in description order
         for (int i = tid; i < dm.nr; i += nthr) {
@@ -748,7 +780,53 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
             atomicAdd(&grad[2 * dm.nr + o], GR[2 * dm.nr_pad + i]);
         }
     }
-#undef AT
+}
+
+// Ragged batch: the segments (each a mechanism with its own states and
+// outputs) share one launch; the global group index runs over the segments'
+// groups in order, so every workgroup of the persistent grid takes groups of
+// any segment.
+// Adjoint parameter sums of one segment, kept in LDS, into its output.
+__device__ inline void flush_gr(const BatchSeg& b, const double* GR) {
+    __syncthreads();
+    if (b.grad)
+        for (int i = threadIdx.x; i < b.dm.nr; i += blockDim.x) {
+            const int o = b.dm.orig[i];
+            atomicAdd(&b.grad[o], GR[i]);
+            atomicAdd(&b.grad[b.dm.nr + o], GR[b.dm.nr_pad + i]);
+            atomicAdd(&b.grad[2 * b.dm.nr + o], GR[2 * b.dm.nr_pad + i]);
+        }
+    __syncthreads();
+}
+
+template <int FORM, int LAYOUT, int MODE, int S>
+__global__ void __launch_bounds__(MAX_THREADS) pj_batch_kernel(const BatchSeg* __restrict__ segs,
+                                                                const int nseg, const long total,
+                                                                const long gr_off) {
+    extern __shared__ double lds[];
+    long q0, q1, qstep;
+    group_range(total, q0, q1, qstep);
+    // adjoint: the parameter sums of the segment in hand live in LDS at gr_off
+    // (gr_off < 0: added to the output per group); the groups of a workgroup
+    // run through the segments in order, so it flushes at most once per
+    // segment
+    const bool use_gr = MODE == MODE_ADJ && gr_off >= 0;
+    double* GR = use_gr ? lds + gr_off : nullptr;
+    int cur = -1;
+    for (long gq = q0; gq < q1; gq += qstep) {
+        int k = 0;
+        while (k + 1 < nseg && segs[k + 1].g0 <= gq) ++k;
+        const BatchSeg& b = segs[k];
+        if (use_gr && k != cur) {
+            if (cur >= 0) flush_gr(segs[cur], GR);
+            for (int i = threadIdx.x; i < 3 * b.dm.nr_pad; i += blockDim.x) GR[i] = 0.0;
+            __syncthreads();
+            cur = k;
+        }
+        eval_group<FORM, LAYOUT, MODE, S>(b.dm, b.n, b.state, b.param, b.dstate, b.out, b.vin, b.grad,
+                                          use_gr && b.grad, GR, gq - b.g0);
+    }
+    if (use_gr && cur >= 0) flush_gr(segs[cur], GR);
 }
 
 template <int FORM, int LAYOUT, int MODE, int S>
@@ -779,6 +857,42 @@ static hipError_t launch_t(const DevMech& dm, int64_t n, const double* state, co
     hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * waves), (size_t)lds, stream, dm, (long)n,
                        state, param, dstate, jac, vin, grad, grad_in_lds);
     return hipGetLastError();
+}
+
+template <int FORM, int LAYOUT, int MODE, int S>
+static hipError_t launch_batch_t(int waves, int64_t lds, const BatchSeg* segs, int nseg, int64_t total,
+                                 int64_t gr_off, hipStream_t stream) {
+    auto k = pj_batch_kernel<FORM, LAYOUT, MODE, S>;
+    if (lds > 65536) {
+        int dev = 0, mx = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        if (e != hipSuccess) return e;
+    }
+    // a persistent grid over the segments' groups (a multiple of 8, the XCD count)
+    int64_t grid = total < 8192 ? total : 8192;
+    if (grid >= 8) grid &= ~(int64_t)7;
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * waves), (size_t)lds, stream, segs, nseg, (long)total,
+                       (long)gr_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(int mode, int form, int layout, int S, int waves, int64_t lds,
+                        const BatchSeg* d_segs, int nseg, int64_t total, int64_t gr_off, hipStream_t stream) {
+#define PJ_BCASE(F, L, M, SS)                                                            \
+    if (form == F && layout == L && mode == M && S == SS)                                \
+        return launch_batch_t<F, L, M, SS>(waves, lds, d_segs, nseg, total, gr_off, stream);
+#define PJ_BS(F, L, M) PJ_BCASE(F, L, M, 1) PJ_BCASE(F, L, M, 2) PJ_BCASE(F, L, M, 4)
+#define PJ_BMODES(F, L) PJ_BS(F, L, MODE_SRC) PJ_BS(F, L, MODE_SPARSE) PJ_BS(F, L, MODE_ADJ)
+    PJ_BMODES(PJ_CONP, PJ_LAYOUT_F)
+    PJ_BMODES(PJ_CONP, PJ_LAYOUT_C)
+    PJ_BMODES(PJ_CONV, PJ_LAYOUT_F)
+    PJ_BMODES(PJ_CONV, PJ_LAYOUT_C)
+#undef PJ_BMODES
+#undef PJ_BS
+#undef PJ_BCASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t zero_async(double* p, int64_t n, hipStream_t stream) {

@@ -182,3 +182,28 @@ def test_adjoint_and_arrhenius_argument_checks(api, tmp_path):
     # the adjoint mode keeps at most 4 states per workgroup
     mech.set_launch(16, 1)
     assert mech.launch_shape(3)[0] <= 4
+
+
+def test_batch_argument_checks(api, tmp_path):
+    lib = api.library()
+    m = synth.make_mechanism(7, 10, 3, mix=synth.MixSpec(0.1, 0.2, 0.2), zipf=0.5)
+    mech = api.Mechanism(_write(tmp_path, synth.dumps(m)), upload=False)
+    dummy = ctypes.c_void_p(16)
+    b = ctypes.c_void_p()
+    assert lib.pj_batch_create(ctypes.byref(b)) == 0
+    assert lib.pj_batch_size(b) == 0
+    assert lib.pj_batch_launch_shape(b, 1, None, None) == -1     # empty
+    assert lib.pj_batch_add(b, None, 4, dummy, dummy, dummy, None, None, None) == 1
+    assert lib.pj_batch_add(b, mech.handle, -1, dummy, dummy, dummy, None, None, None) == 1
+    assert lib.pj_batch_add(b, mech.handle, 4, dummy, dummy, dummy, None, None, None) == 0
+    assert lib.pj_batch_size(b) == 1
+    for mode, S, W in ((2, 1, 1), (1, 8, 1), (1, 3, 1), (1, 1, 3)):
+        assert lib.pj_batch_set_launch(b, mode, S, W) == 1
+    assert lib.pj_batch_set_launch(b, 1, 2, 4) == 0
+    # modes: 0, 1, 3 only; a mechanism that is not uploaded is reported by segment
+    assert lib.pj_batch_eval(b, 2, 0, 0, None) == 1
+    assert lib.pj_batch_eval(b, 1, 0, 0, None) == 1
+    assert b"segment 0" in lib.pj_batch_last_error() and b"not uploaded" in lib.pj_batch_last_error()
+    assert lib.pj_batch_clear(b) == 0 and lib.pj_batch_size(b) == 0
+    lib.pj_batch_free(b)
+    lib.pj_batch_free(None)

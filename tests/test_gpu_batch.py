@@ -1,0 +1,170 @@
+"""Ragged multi-mechanism batches (pj_batch_*): one launch over segments of
+states of different mechanisms, and its captured HIP graph.
+
+Every segment's outputs are checked against the oracle under the same gates
+as the per-mechanism calls; with one wave per workgroup the batch reproduces
+the per-mechanism launch of the same shape bit for bit; graph replays, with
+eager work and synchronisation between them, reproduce the eager batch.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_01029_amd import synth
+from conftest import workload_file
+
+pytestmark = pytest.mark.gpu
+
+SEGMENTS = [("ns13", 300), ("ns53", 150), ("empty", 0), ("ns111", 60)]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def api(torch_cuda):
+    from paper_1809_01029_amd import api as a
+    return a
+
+
+def note(*a):
+    print(*a, flush=True)
+
+
+def _dev(torch, a_c, layout):
+    a = a_c if layout == "C" else np.ascontiguousarray(a_c.T)
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _host(t, layout):
+    a = t.cpu().numpy()
+    return a if layout == "C" else a.T
+
+
+def build(torch, api, mech_dir, form, layout, mode):
+    segs = []
+    b = api.Batch()
+    for name, n in SEGMENTS:
+        nm = "ns13" if name == "empty" else name
+        m, path = workload_file(nm, mech_dir)
+        mech = api.load_mechanism(path)
+        st = synth.make_states(m, n, 500 + n)
+        x, p = synth.pack_state(st, form, "C")
+        v = np.random.default_rng(n).standard_normal(x.shape)
+        xs, ps, vs = _dev(torch, x, layout), torch.from_numpy(p.copy()).cuda(), _dev(torch, v, layout)
+        d = torch.zeros_like(xs)
+        if mode == "sparse":
+            out = torch.zeros((mech.nnz, n) if layout == "F" else (n, mech.nnz), dtype=torch.float64, device="cuda")
+        elif mode == "adjoint":
+            out = torch.zeros_like(xs)
+        else:
+            out = None
+        grad = torch.zeros((3, mech.n_reactions), dtype=torch.float64, device="cuda") if mode == "adjoint" else None
+        b.add(mech, xs, ps, layout, out=out, dstate=d, v=vs if mode == "adjoint" else None, grad=grad)
+        segs.append(dict(name=nm, path=path, mech=mech, x=x, p=p, v=v, xs=xs, ps=ps, vs=vs, d=d, out=out, grad=grad))
+    return b, segs
+
+
+def check_against_oracle(api, segs, form, layout, mode):
+    for sg in segs:
+        if sg["x"].shape[0] == 0:
+            continue
+        o = oracle.Oracle(sg["path"])
+        x, p = sg["x"], sg["p"]
+        f_o, f_s = o.source(x, p, form, scale=True)
+        assert np.all(np.abs(_host(sg["d"], layout) - f_o) <= 1e-10 * f_s), f"{sg['name']} source terms"
+        if mode == "sparse":
+            J_o, J_s = o.jacobian(x, p, form, scale=True)
+            Jg = api.sparse_to_dense(sg["mech"], sg["out"].cpu().numpy(), layout)
+            assert np.all(np.abs(Jg - J_o) <= 1e-8 * J_s + 1e-20), f"{sg['name']} Jacobian"
+        if mode == "adjoint":
+            j_o, g_o, j_s, g_s = o.adjoint(x, p, sg["v"], form, scale=True)
+            assert np.all(np.abs(_host(sg["out"], layout) - j_o) <= 1e-8 * j_s + 1e-20), f"{sg['name']} J^T v"
+            assert np.all(np.abs(sg["grad"].cpu().numpy() - g_o) <= 1e-8 * g_s + 1e-20), f"{sg['name']} grad"
+
+
+@pytest.mark.parametrize("layout", ["F", "C"])
+@pytest.mark.parametrize("form,mode", [("conp", "source"), ("conp", "sparse"), ("conv", "sparse"),
+                                       ("conp", "adjoint"), ("conv", "adjoint")])
+def test_batch_matches_oracle(torch_cuda, api, form, mode, layout, mech_dir):
+    torch = torch_cuda
+    b, segs = build(torch, api, mech_dir, form, layout, mode)
+    note(f"batch {form} {mode} {layout} shape {b.launch_shape(mode)}")
+    b.eval(mode, form, layout)
+    torch.cuda.synchronize()
+    check_against_oracle(api, segs, form, layout, mode)
+
+
+@pytest.mark.parametrize("mode", ["source", "sparse"])
+def test_batch_equals_per_mechanism_launch(torch_cuda, api, mode, mech_dir):
+    """One wave per workgroup: every accumulation in program order, so the
+    batch gives the per-mechanism launch's bits."""
+    torch = torch_cuda
+    b, segs = build(torch, api, mech_dir, "conp", "C", mode)
+    for S in (1, 2):
+        b.set_launch(mode, S, 1)
+        b.eval(mode, "conp", "C")
+        for sg in segs:
+            if sg["x"].shape[0] == 0:
+                continue
+            sg["mech"].set_launch(S, 1)
+            if mode == "source":
+                ref = api.eval_source(sg["mech"], sg["xs"], sg["ps"], "conp", "C")
+                torch.cuda.synchronize()
+                assert torch.equal(ref, sg["d"]), sg["name"]
+            else:
+                dref = torch.empty_like(sg["xs"])
+                ref = api.eval_jacobian_sparse(sg["mech"], sg["xs"], sg["ps"], "conp", "C", dstate=dref)
+                torch.cuda.synchronize()
+                assert torch.equal(ref, sg["out"]) and torch.equal(dref, sg["d"]), sg["name"]
+
+
+@pytest.mark.parametrize("mode", ["sparse", "adjoint"])
+def test_batch_graph_replays(torch_cuda, api, mode, mech_dir):
+    torch = torch_cuda
+    b, segs = build(torch, api, mech_dir, "conp", "F", mode)
+    b.set_launch(mode, 2, 1)
+    b.eval(mode, "conp", "F")
+    torch.cuda.synchronize()
+    ref = [(sg["d"].clone(), None if sg["out"] is None else sg["out"].clone(),
+            None if sg["grad"] is None else sg["grad"].clone()) for sg in segs]
+    for r in range(3):
+        # eager work and a synchronisation between replays
+        for sg in segs:
+            sg["d"].zero_()
+            if sg["out"] is not None:
+                sg["out"].fill_(float("nan"))
+            if sg["grad"] is not None:
+                sg["grad"].fill_(3.0)
+        api.eval_source(segs[0]["mech"], segs[0]["xs"], segs[0]["ps"], "conp", "F")
+        torch.cuda.synchronize()
+        b.eval(mode, "conp", "F", graph=True)
+        torch.cuda.synchronize()
+        note(f"graph replay {r}")
+        for sg, (d0, o0, g0) in zip(segs, ref):
+            assert torch.equal(sg["d"], d0), (r, sg["name"])
+            if o0 is not None:
+                assert torch.equal(sg["out"], o0), (r, sg["name"])
+            if g0 is not None:
+                # parameter sums are added with device atomics: equal to rounding
+                torch.testing.assert_close(sg["grad"], g0, rtol=1e-12, atol=1e-300)
+    check_against_oracle(api, segs, "conp", "F", mode)
+
+
+def test_batch_autotune(torch_cuda, api, mech_dir):
+    torch = torch_cuda
+    b, segs = build(torch, api, mech_dir, "conp", "C", "sparse")
+    S, W, ms = b.autotune("sparse", "conp", "C", reps=1)
+    note(f"batch autotune: S={S} W={W} {ms:.4f} ms")
+    assert b.launch_shape("sparse") == (S, W) and S in (1, 2, 4) and W in (1, 2, 4, 8)
+    for sg in segs:
+        if sg["out"] is not None:
+            sg["out"].zero_()
+    b.eval("sparse", "conp", "C")
+    torch.cuda.synchronize()
+    check_against_oracle(api, segs, "conp", "C", "sparse")
