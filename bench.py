@@ -72,6 +72,61 @@ def measured_traffic(workload, form, layout, n, shape):
         return None
 
 
+def ragged_batch(api, synth, torch, tmp, args, stream, timeit):
+    """Source terms and adjoint over 3,000 / 70,000 / 20,000 states of the 13-,
+    53- and 111-species mechanisms: three per-mechanism launches (each with
+    its own autotuned shape) against one ragged-batch launch and its HIP
+    graph."""
+    segs = []
+    for name, count, seed in (("ns13", 3000, 2013), ("ns53", 70000, 2053), ("ns111", 20000, 2111)):
+        w = synth.WORKLOADS[name]
+        mm = synth.workload_mechanism(name)
+        pth = os.path.join(tmp, f"ragged_{name}.pjm")
+        synth.write_mechanism(mm, pth)
+        st = synth.make_states(mm, count, seed, T_range=w.T_range, P_range_atm=w.P_range_atm)
+        x, p = synth.pack_state(st, args.form, args.layout)
+        me = api.load_mechanism(pth)
+        xs = torch.from_numpy(x).cuda()
+        segs.append(dict(mech=me, xs=xs, ps=torch.from_numpy(p).cuda(), d=torch.empty_like(xs),
+                         v=torch.randn_like(xs), jtv=torch.empty_like(xs),
+                         g=torch.empty((3, me.n_reactions), dtype=torch.float64, device="cuda")))
+    out = {"states": [3000, 70000, 20000]}
+    for mode in ("source", "adjoint"):
+        for sg in segs:
+            if mode == "source":
+                api.autotune(sg["mech"], sg["xs"], sg["ps"], args.form, args.layout, mode="source", reps=1,
+                             stream=stream)
+
+        def plain():
+            for sg in segs:
+                if mode == "source":
+                    api.eval_source(sg["mech"], sg["xs"], sg["ps"], args.form, args.layout, out=sg["d"],
+                                    stream=stream)
+                else:
+                    api.eval_adjoint(sg["mech"], sg["xs"], sg["ps"], sg["v"], args.form, args.layout,
+                                     jtv=sg["jtv"], grad=sg["g"], stream=stream)
+        if mode == "adjoint":
+            for sg in segs:
+                api.autotune(sg["mech"], sg["xs"], sg["ps"], args.form, args.layout, mode="adjoint", reps=1,
+                             stream=stream)
+        b = api.Batch()
+        for sg in segs:
+            if mode == "source":
+                b.add(sg["mech"], sg["xs"], sg["ps"], args.layout, dstate=sg["d"])
+            else:
+                b.add(sg["mech"], sg["xs"], sg["ps"], args.layout, out=sg["jtv"], v=sg["v"], grad=sg["g"])
+        b.autotune(mode, args.form, args.layout, reps=1, stream=stream)
+        t_plain = timeit(plain)
+        t_batch = timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream))
+        t_graph = timeit(lambda: b.eval(mode, args.form, args.layout, graph=True, stream=stream))
+        out[mode] = {"per_mechanism_ms": round(t_plain, 4), "batch_ms": round(t_batch, 4),
+                     "graph_ms": round(t_graph, 4), "batch_shape": list(b.launch_shape(mode))}
+        b.close()
+    for sg in segs:
+        sg["mech"].close()
+    return out
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """A plain device-to-device copy of ``nbytes``, ``reps`` times."""
     import torch
@@ -250,6 +305,20 @@ def main():
                                           "launch_shape": list(mech53.launch_shape(1))}
             del xs4, ps4, jac4, d4
             mech53.close()
+        # adjoint (J^T v + Arrhenius-parameter sums) on the same batch
+        if not args.no_autotune:
+            api.autotune(mech, xs, ps, args.form, args.layout, mode="adjoint", reps=1, stream=stream)
+        vv = torch.randn_like(xs)
+        jtv = torch.empty_like(xs)
+        grad = torch.empty((3, m.n_reactions), dtype=torch.float64, device="cuda")
+        t = timeit(lambda: api.eval_adjoint(mech, xs, ps, vv, args.form, args.layout, jtv=jtv, grad=grad,
+                                            stream=stream))
+        variants["adjoint"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3),
+                               "launch_shape": list(mech.launch_shape(3)),
+                               "vs_sparse_jacobian": round(t / ms, 3)}
+        del vv, jtv, grad
+        if args.workload == "ns111" and not args.n_states:
+            variants["ragged_13_53_111"] = ragged_batch(api, synth, torch, tmp, args, stream, timeit)
         log(f"variants: {json.dumps(variants)}")
 
     cpu = None

@@ -212,6 +212,13 @@ pj_status pj_mech_autotune(pj_mech* mech, int mode, pj_form form, pj_layout layo
                            double* d_dstate_or_null, int reps, pj_stream stream,
                            int* states_per_group, int* waves_per_group, float* ms);
 
+/* The autotuner for pj_eval_adjoint (states per workgroup at most 4), with
+ * that call's buffers, which it overwrites. */
+pj_status pj_mech_autotune_adjoint(pj_mech* mech, pj_form form, pj_layout layout, int64_t n_states,
+                                   const double* d_state, const double* d_param, const double* d_v,
+                                   double* d_jtv, double* d_grad_or_null, int reps, pj_stream stream,
+                                   int* states_per_group, int* waves_per_group, float* ms);
+
 /* Bytes of LDS one workgroup needs for source terms (0) or the sparse Jacobian (1). */
 int64_t pj_mech_lds_bytes(const pj_mech* mech, int for_jacobian);
 

@@ -100,6 +100,10 @@ _lib.pj_mech_autotune.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, 
                                   ctypes.c_int, _P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(ctypes.c_float)]
 _lib.pj_mech_autotune.restype = ctypes.c_int
+_lib.pj_mech_autotune_adjoint.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P, _P, ctypes.c_int,
+                                          _P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_float)]
+_lib.pj_mech_autotune_adjoint.restype = ctypes.c_int
 _lib.pj_mech_lds_bytes.argtypes = [_P, ctypes.c_int]
 _lib.pj_mech_lds_bytes.restype = _I64
 _lib.pj_last_error.argtypes = []
@@ -373,13 +377,23 @@ def source_terms(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, lnA:
 def autotune(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, form: str = "conp",
              layout: str = "F", mode: str = "sparse", reps: int = 2, stream=None):
     """pj_mech_autotune: time every launch shape of ``mode`` ("source",
-    "sparse", "dense") on this batch and keep the fastest for that mode.
+    "sparse", "dense", "adjoint") on this batch and keep the fastest for that mode.
     Returns (states per workgroup, waves per workgroup, ms per launch).
     Scratch outputs are allocated here and discarded."""
     n = _n_states(mech, state, layout)
     _need(state, _state_shape(mech, n, layout), "state", None)
     _need(param, (n,), "param", state.device)
     m = MODES[mode]
+    S, W, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    if m == 3:
+        # the adjoint: time with v = the states themselves and the parameter sums
+        jtv = torch.empty_like(state)
+        grad = torch.empty((3, mech.n_reactions), dtype=torch.float64, device=state.device)
+        _check(_lib.pj_mech_autotune_adjoint(mech.handle, FORMS[form], LAYOUTS[layout], n, _ptr(state),
+                                             _ptr(param), _ptr(state), _ptr(jtv), _ptr(grad), int(reps),
+                                             _stream(stream), ctypes.byref(S), ctypes.byref(W), ctypes.byref(ms)),
+               "pj_mech_autotune_adjoint")
+        return S.value, W.value, ms.value
     dstate = torch.empty_like(state)
     if m == 0:
         out = dstate
@@ -389,7 +403,6 @@ def autotune(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, form: st
     else:
         out = torch.empty((mech.N, mech.N, n) if layout == "F" else (n, mech.N, mech.N), dtype=torch.float64,
                           device=state.device)
-    S, W, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
     _check(_lib.pj_mech_autotune(mech.handle, m, FORMS[form], LAYOUTS[layout], n, _ptr(state), _ptr(param),
                                  _ptr(out), _ptr(dstate) if m else None, int(reps), _stream(stream),
                                  ctypes.byref(S), ctypes.byref(W), ctypes.byref(ms)), "pj_mech_autotune")

@@ -282,20 +282,23 @@ int pj_mech_launch_shape(const pj_mech* mech, int mode, int* states_per_group, i
     return 0;
 }
 
-pj_status pj_mech_autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int64_t n_states,
-                           const double* d_state, const double* d_param, double* d_out,
-                           double* d_dstate_or_null, int reps, pj_stream stream,
-                           int* states_per_group, int* waves_per_group, float* ms) {
-    if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
-    if (mode < pj::MODE_SRC || mode > pj::MODE_DENSE) return fail(PJ_E_INVALID, "bad mode");
+}  // extern "C"
+
+namespace {
+
+// time every launch shape that fits for `mode` and keep the fastest
+pj_status autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int64_t n_states,
+                   const double* d_state, const double* d_param, double* dst, double* jac, const double* vin,
+                   double* grad, int reps, pj_stream stream, int* states_per_group, int* waves_per_group,
+                   float* ms) {
     if (reps < 1) return fail(PJ_E_INVALID, "reps must be at least 1");
     if (n_states < 1) return fail(PJ_E_INVALID, "autotuning needs at least one state");
     pj::Mechanism& m = mech->m;
-    double* dst = mode == pj::MODE_SRC ? d_out : d_dstate_or_null;
-    double* jac = mode == pj::MODE_SRC ? nullptr : d_out;
     // validate the arguments once with the current shape
-    pj_status st = eval(mech, mode, form, layout, n_states, d_state, d_param, dst, jac, stream);
+    pj_status st = eval(mech, mode, form, layout, n_states, d_state, d_param, dst, jac, stream, vin, grad);
     if (st != PJ_OK) return st;
+    const bool gr = mode == pj::MODE_ADJ && m.adj_grad_in_lds;
+    const int maxS = mode == pj::MODE_ADJ ? pj::MAX_S_ADJ : MAX_S;
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -305,14 +308,17 @@ pj_status pj_mech_autotune(pj_mech* mech, int mode, pj_form form, pj_layout layo
     int best_S = m.S[mode], best_w = m.waves[mode];
     float best = -1.0f;
     std::string err;
-    for (int S = 1; S <= MAX_S && err.empty(); S *= 2) {
+    for (int S = 1; S <= maxS && err.empty(); S *= 2) {
         for (int w = S > 64 ? S / 64 : 1; w <= MAX_WAVES; w *= 2) {
-            const int64_t l = pj::lds_bytes(m.dm, mode, S, w);
+            const int64_t l = pj::lds_bytes(m.dm, mode, S, w, gr);
             if (l > m.lds_max) continue;
-            hipError_t e = pj::launch(m.dm, mode, form, layout, S, n_states, d_state, d_param, dst, jac, nullptr, nullptr, 0, w, l, hs);
+            auto go = [&]() {
+                return pj::launch(m.dm, mode, form, layout, S, n_states, d_state, d_param, dst, jac, vin, grad,
+                                  gr ? 1 : 0, w, l, hs);
+            };
+            hipError_t e = go();
             if (e == hipSuccess) e = hipEventRecord(e0, hs);
-            for (int r = 0; r < reps && e == hipSuccess; ++r)
-                e = pj::launch(m.dm, mode, form, layout, S, n_states, d_state, d_param, dst, jac, nullptr, nullptr, 0, w, l, hs);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = go();
             if (e == hipSuccess) e = hipEventRecord(e1, hs);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float t = 0.0f;
@@ -330,12 +336,37 @@ pj_status pj_mech_autotune(pj_mech* mech, int mode, pj_form form, pj_layout layo
     if (!err.empty()) return fail(PJ_E_DEVICE, err);
     m.S[mode] = best_S;
     m.waves[mode] = best_w;
-    m.lds[mode] = pj::lds_bytes(m.dm, mode, best_S, best_w);
+    m.lds[mode] = pj::lds_bytes(m.dm, mode, best_S, best_w, gr);
     if (states_per_group) *states_per_group = best_S;
     if (waves_per_group) *waves_per_group = best_w;
     if (ms) *ms = best;
     g_err.clear();
     return PJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pj_status pj_mech_autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int64_t n_states,
+                           const double* d_state, const double* d_param, double* d_out,
+                           double* d_dstate_or_null, int reps, pj_stream stream,
+                           int* states_per_group, int* waves_per_group, float* ms) {
+    if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
+    if (mode < pj::MODE_SRC || mode > pj::MODE_DENSE) return fail(PJ_E_INVALID, "bad mode");
+    double* dst = mode == pj::MODE_SRC ? d_out : d_dstate_or_null;
+    double* jac = mode == pj::MODE_SRC ? nullptr : d_out;
+    return autotune(mech, mode, form, layout, n_states, d_state, d_param, dst, jac, nullptr, nullptr, reps, stream,
+                    states_per_group, waves_per_group, ms);
+}
+
+pj_status pj_mech_autotune_adjoint(pj_mech* mech, pj_form form, pj_layout layout, int64_t n_states,
+                                   const double* d_state, const double* d_param, const double* d_v,
+                                   double* d_jtv, double* d_grad_or_null, int reps, pj_stream stream,
+                                   int* states_per_group, int* waves_per_group, float* ms) {
+    if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
+    return autotune(mech, pj::MODE_ADJ, form, layout, n_states, d_state, d_param, nullptr, d_jtv, d_v,
+                    d_grad_or_null, reps, stream, states_per_group, waves_per_group, ms);
 }
 
 int64_t pj_mech_lds_bytes(const pj_mech* mech, int for_jacobian) {

@@ -193,3 +193,21 @@ def test_adjoint_full_size_sampled(torch_cuda, api, mech_dir):
     g, gs = grad.cpu().numpy(), (g1 + g2).cpu().numpy()
     np.testing.assert_allclose(g, gs, rtol=1e-9, atol=1e-12 * np.abs(g).max())
     assert torch.isfinite(jtv).all()
+
+
+def test_adjoint_autotune(torch_cuda, api, mech_dir):
+    torch = torch_cuda
+    m, path = workload_file("ns53", mech_dir)
+    st = synth.make_states(m, 1500, 61)
+    x, p = synth.pack_state(st, "conv", "C")
+    v = np.random.default_rng(4).standard_normal(x.shape)
+    mech = api.load_mechanism(path)
+    xs, ps, vs = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda(), torch.from_numpy(v).cuda()
+    S, W, ms = api.autotune(mech, xs, ps, "conv", "C", mode="adjoint", reps=1)
+    note(f"adjoint autotune: S={S} W={W} {ms:.4f} ms")
+    assert mech.launch_shape(3) == (S, W) and S in (1, 2, 4) and W in (1, 2, 4, 8)
+    jtv, grad = api.eval_adjoint(mech, xs, ps, vs, "conv", "C")
+    torch.cuda.synchronize()
+    j_o, g_o, j_s, g_s = oracle.Oracle(path).adjoint(x, p, v, "conv", scale=True)
+    check(jtv.cpu().numpy(), j_o, j_s, "tuned J^T v")
+    check(grad.cpu().numpy(), g_o, g_s, "tuned parameter derivatives")
