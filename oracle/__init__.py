@@ -60,6 +60,9 @@ def _load():
         lib.ora_jacobian_cs.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, ctypes.c_double, D]
         lib.ora_jacobian_fd.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, ctypes.c_double, D]
         lib.ora_pattern.argtypes = [P, ctypes.POINTER(ctypes.c_ubyte)]
+        lib.ora_jacobian_ex.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, D, ctypes.c_int]
+        lib.ora_jacobian_cs_ex.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, ctypes.c_double, D, ctypes.c_int]
+        lib.ora_pattern_ex.argtypes = [P, ctypes.POINTER(ctypes.c_ubyte), ctypes.c_int]
         lib.ora_adjoint.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, D, D, D, D]
         lib.ora_param_grad_cs.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, ctypes.c_double, D]
         lib.ora_jvp_cs.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, ctypes.c_double, D]
@@ -125,21 +128,23 @@ class Oracle:
                              _d(s) if scale else None)
         return (f, s) if scale else f
 
-    def jacobian(self, x, p, form="conp", scale: bool = False):
+    def jacobian(self, x, p, form="conp", scale: bool = False, approx: bool = False):
+        """Analytical Jacobian [n, N, N]; ``approx``: the approximate form
+        (the bath gas's moles held fixed against the other species')."""
         x = _f64(x).reshape(-1, self.N)
         p = _f64(p).reshape(-1)
         n = x.shape[0]
         J = np.zeros((n, self.N, self.N))
         s = np.zeros_like(J) if scale else None
-        self._lib.ora_jacobian(self._h, _FORMS[form], n, _d(x), _d(p), _d(J),
-                               _d(s) if scale else None)
+        self._lib.ora_jacobian_ex(self._h, _FORMS[form], n, _d(x), _d(p), _d(J),
+                                  _d(s) if scale else None, int(approx))
         return (J, s) if scale else J
 
-    def jacobian_cs(self, x, p, form="conp", hrel: float = 1e-30):
+    def jacobian_cs(self, x, p, form="conp", hrel: float = 1e-30, approx: bool = False):
         x = _f64(x).reshape(-1, self.N)
         p = _f64(p).reshape(-1)
         J = np.zeros((x.shape[0], self.N, self.N))
-        self._lib.ora_jacobian_cs(self._h, _FORMS[form], x.shape[0], _d(x), _d(p), hrel, _d(J))
+        self._lib.ora_jacobian_cs_ex(self._h, _FORMS[form], x.shape[0], _d(x), _d(p), hrel, _d(J), int(approx))
         return J
 
     def jacobian_fd(self, x, p, form="conp", rel: float = 1e-6):
@@ -183,14 +188,14 @@ class Oracle:
         self._lib.ora_jvp_cs(self._h, _FORMS[form], x.shape[0], _d(x), _d(p), _d(u), hstep, _d(out))
         return out
 
-    def pattern(self) -> np.ndarray:
+    def pattern(self, approx: bool = False) -> np.ndarray:
         P = np.zeros((self.N, self.N), dtype=np.uint8)
-        self._lib.ora_pattern(self._h, P.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+        self._lib.ora_pattern_ex(self._h, P.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)), int(approx))
         return P.astype(bool)
 
-    def csr(self):
+    def csr(self, approx: bool = False):
         """The structural pattern as CSR (row_ptr[N+1], col_idx[nnz]), columns ascending."""
-        P = self.pattern()
+        P = self.pattern(approx)
         rows, cols = np.nonzero(P)
         row_ptr = np.zeros(self.N + 1, dtype=np.int64)
         np.add.at(row_ptr, rows + 1, 1)

@@ -28,6 +28,11 @@
 // derivatives by the chain rule through the rate of progress (for falloff
 // reactions the parameters are those of the high-pressure limit).
 //
+// The "approximate" Jacobian (Sec. 3.4) neglects the dependence of the bath
+// gas's concentration on the other species' moles: d[C]_Ns/dn_j = 0 for
+// j < Ns, while its dependence on T and V (or P) is kept; this removes the
+// dense rows the bath gas would otherwise create.
+//
 // Units: SI with kmol.  R_u = 8314.462618 J/(kmol K), P_ref = 101325 Pa.
 // State vector (Sec. 2.2): Phi = (T, V, n_1..n_{Ns-1}) for constant pressure
 // (parameter P) and (T, P, n_1..n_{Ns-1}) for constant volume (parameter V);
@@ -234,15 +239,26 @@ struct State {
 
 // [C]_k = n_k / V (Sec. 2.2); the bath gas from the ideal gas law P V = n R T:
 // n_Ns = P V / (R T) - RN(sum_{k<Ns} n_k).
+// frozen = true: the bath gas's moles do not follow the other species' moles
+// (the sum's imaginary part is dropped), the complex-step form of the
+// approximate Jacobian
+inline std::complex<double> frozen_sum(const std::complex<double>* v, int n) {
+    std::vector<double> x(n);
+    for (int k = 0; k < n; ++k) x[k] = v[k].real();
+    return std::complex<double>(rn_sum(x.data(), n), 0.0);
+}
 template <class S>
-State<S> make_state(const Mech& m, int form, const S* x, S param) {
+S frozen_sum(const S* v, int n) { return exact_sum(v, n); }
+
+template <class S>
+State<S> make_state(const Mech& m, int form, const S* x, S param, bool frozen = false) {
     State<S> st;
     int ns = m.ns;
     st.T = x[0];
     if (form == FORM_CONP) { st.V = x[1]; st.P = param; }
     else { st.P = x[1]; st.V = param; }
     S ntot = (st.P * st.V) / (S(RU) * st.T);
-    S sum = exact_sum(x + 2, ns - 1);
+    S sum = frozen ? frozen_sum(x + 2, ns - 1) : exact_sum(x + 2, ns - 1);
     st.n.resize(ns);
     st.C.resize(ns);
     for (int k = 0; k < ns - 1; ++k) st.n[k] = x[2 + k];
@@ -260,10 +276,12 @@ struct RxnEval {
     // derivatives, used by the Jacobian
     S dkf_dT, dkr_dT;
     S dc_dT;                    // at fixed concentrations
-    std::vector<S> dc_dC;       // dc/d[C]_m, all species
+    std::vector<S> dc_dC;       // dc/d[C]_m, all species, at fixed C_tot
+    S dc_dCtot;                 // dc/dC_tot at fixed species concentrations
     std::vector<S> dRf_dC, dRr_dC;
     S dRf_dT, dRr_dT;
-    std::vector<S> dq_dC;       // dq/d[C]_m at fixed T
+    std::vector<S> dq_dC;       // dq/d[C]_m at fixed T and C_tot
+    S dq_dCtot;                 // dq/dC_tot at fixed T and concentrations
     S dq_dT;                    // dq/dT at fixed concentrations
     S dq_dlnk;                  // dq/d ln k_f at fixed T and concentrations
 };
@@ -357,18 +375,27 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
     // pressure modification
     std::vector<double> alpha(ns, 1.0);
     for (auto& p : r.eff) alpha[p.first] = p.second;
+    // third-body concentration [M] = C_tot + sum_k (alpha_k - 1) [C]_k with the
+    // total concentration C_tot = P / (R T), a function of T and P only (equal
+    // to sum_k alpha_k [C]_k; written this way, a species of default efficiency
+    // does not enter [M] through the concentrations)
     S M(0.0);
-    if (r.type != T_ELEM)
-        for (int k = 0; k < ns; ++k) M = M + S(alpha[k]) * st.C[k];
+    if (r.type != T_ELEM) {
+        M = st.P / (S(RU) * T);
+        for (int k = 0; k < ns; ++k)
+            if (alpha[k] != 1.0) M = M + S(alpha[k] - 1.0) * st.C[k];
+    }
 
     e.dc_dC.assign(ns, S(0.0));
+    e.dc_dCtot = S(0.0);
     e.dc_dT = S(0.0);
     S Pr_dc_dPr(0.0);   // Pr dc/dPr of a falloff reaction (Pr = k0 [M] / k_f)
     if (r.type == T_ELEM) {
         e.c = S(1.0);
     } else if (r.type == T_THREEBODY) {
         e.c = M;
-        for (int k = 0; k < ns; ++k) e.dc_dC[k] = S(alpha[k]);
+        for (int k = 0; k < ns; ++k) e.dc_dC[k] = S(alpha[k] - 1.0);
+        e.dc_dCtot = S(1.0);
     } else {
         S k0 = arrhenius(r.lnA0, r.b0, r.theta0, T);
         S dk0_dT = k0 * (S(r.b0) / T + S(r.theta0) / (T * T));
@@ -406,7 +433,8 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
         e.c = F / (S(1.0) + S(1.0) / Pr);
         S dc_dPr = F / ((S(1.0) + Pr) * (S(1.0) + Pr)) + Pr / (S(1.0) + Pr) * dF_dPr;
         e.dc_dT = dc_dPr * dPr_dT + Pr / (S(1.0) + Pr) * dF_dT;
-        for (int k = 0; k < ns; ++k) e.dc_dC[k] = dc_dPr * k0 * S(alpha[k]) / e.kf;
+        for (int k = 0; k < ns; ++k) e.dc_dC[k] = dc_dPr * k0 * S(alpha[k] - 1.0) / e.kf;
+        e.dc_dCtot = dc_dPr * k0 / e.kf;
         Pr_dc_dPr = Pr * dc_dPr;
     }
     e.q = e.c * (e.Rf - e.Rr);
@@ -426,6 +454,7 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
     e.dq_dC.assign(ns, S(0.0));
     for (int k = 0; k < ns; ++k)
         e.dq_dC[k] = e.dc_dC[k] * (e.Rf - e.Rr) + e.c * (e.dRf_dC[k] - e.dRr_dC[k]);
+    e.dq_dCtot = e.dc_dCtot * (e.Rf - e.Rr);
     e.dq_dT = e.dc_dT * (e.Rf - e.Rr) + e.c * (e.dRf_dT - e.dRr_dT);
     return e;
 }
@@ -454,10 +483,10 @@ struct Eval {
 
 template <class S>
 Eval<S> evaluate(const Mech& m, int form, const S* x, S param, bool with_derivs,
-                 const std::vector<ParamShift<S>>* shift = nullptr) {
+                 const std::vector<ParamShift<S>>* shift = nullptr, bool frozen = false) {
     Eval<S> ev;
     int ns = m.ns, nr = (int)m.rx.size();
-    ev.st = make_state(m, form, x, param);
+    ev.st = make_state(m, form, x, param, frozen);
     S T = ev.st.T;
     ev.th.resize(ns);
     for (int k = 0; k < ns; ++k) ev.th[k] = species_thermo(m.sp[k], T);
@@ -512,7 +541,7 @@ Eval<S> evaluate(const Mech& m, int form, const S* x, S param, bool with_derivs,
 // rule through the concentrations.
 
 template <class S>
-void jacobian(const Mech& m, int form, const S* x, S param, S* J) {
+void jacobian(const Mech& m, int form, const S* x, S param, S* J, bool approx = false) {
     int ns = m.ns, nr = (int)m.rx.size(), N = ns + 1, bath = ns - 1;
     Eval<S> ev = evaluate(m, form, x, param, true);
     const State<S>& st = ev.st;
@@ -535,7 +564,7 @@ void jacobian(const Mech& m, int form, const S* x, S param, S* J) {
     }
     for (int j = 0; j < ns - 1; ++j) {
         set(j, 2 + j, S(1.0) / V);
-        set(bath, 2 + j, -S(1.0) / V);
+        if (!approx) set(bath, 2 + j, -S(1.0) / V);
     }
 
     // dq_i/dPhi_j = sum_k dq_i/d[C]_k d[C]_k/dPhi_j (+ dq_i/dT at fixed [C] for j = T),
@@ -544,11 +573,16 @@ void jacobian(const Mech& m, int form, const S* x, S param, S* J) {
     for (int j = 0; j < N; ++j)
         for (int k = 0; k < ns; ++k)
             if (nz[(size_t)k * N + j]) colnz[j].push_back(k);
+    // dC_tot/dPhi_j, C_tot = P / (R T): T and, for CONV, P
+    std::vector<S> dCtot(N, S(0.0));
+    dCtot[0] = -(P / (S(RU) * T)) / T;
+    if (form == FORM_CONV) dCtot[1] = S(1.0) / (S(RU) * T);
     std::vector<S> dq((size_t)nr * N, S(0.0));
     for (int i = 0; i < nr; ++i)
         for (int j = 0; j < N; ++j) {
             S acc = (j == 0) ? ev.rx[i].dq_dT : S(0.0);
             for (int k : colnz[j]) acc = acc + ev.rx[i].dq_dC[k] * dc(k, j);
+            if (j < 2) acc = acc + ev.rx[i].dq_dCtot * dCtot[j];
             dq[(size_t)i * N + j] = acc;
         }
 
@@ -677,7 +711,7 @@ void jtv(const Mech& m, int form, const S* x, S param, const double* v, S* out) 
 // with an efficiency other than the bath gas's); a rate that depends on the
 // bath gas makes the row dense.  The diagonal is always present.
 
-void pattern(const Mech& m, unsigned char* P) {
+void pattern(const Mech& m, unsigned char* P, bool approx = false) {
     int ns = m.ns, N = ns + 1, bath = ns - 1;
     std::memset(P, 0, (size_t)N * N);
     for (int j = 0; j < N; ++j) { P[0 * N + j] = 1; P[1 * N + j] = 1; P[j * N + 0] = 1; P[j * N + 1] = 1; P[j * N + j] = 1; }
@@ -688,13 +722,14 @@ void pattern(const Mech& m, unsigned char* P) {
         if (r.type != T_ELEM) {
             std::vector<double> alpha(ns, 1.0);
             for (auto& p : r.eff) alpha[p.first] = p.second;
-            for (int k = 0; k < ns; ++k) if (alpha[k] != alpha[bath]) dep[k] = 1;
+            // exact: d[M]/dn_k = (alpha_k - alpha_Ns)/V; approximate: (alpha_k - 1)/V
+            for (int k = 0; k < ns; ++k) if (alpha[k] != (approx ? 1.0 : alpha[bath])) dep[k] = 1;
             if (alpha[bath] != 1.0) dep[bath] = 1;
         }
         for (int k = 0; k < ns - 1; ++k) {
             if (net_nu<double>(r, k) == 0) continue;
             for (int j = 0; j < ns - 1; ++j)
-                if (dep[j] || dep[bath]) P[(size_t)(2 + k) * N + 2 + j] = 1;
+                if (dep[j] || (dep[bath] && !approx)) P[(size_t)(2 + k) * N + 2 + j] = 1;
         }
     }
 }
@@ -759,9 +794,10 @@ void ora_source(void* h, int form, long n, const double* x, const double* param,
     }
 }
 
-// Analytical Jacobian, dense row-major N*N per state, optional scales.
-void ora_jacobian(void* h, int form, long n, const double* x, const double* param,
-                  double* J, double* scale) {
+// Analytical Jacobian, dense row-major N*N per state, optional scales;
+// approx != 0: the approximate form.
+void ora_jacobian_ex(void* h, int form, long n, const double* x, const double* param,
+                     double* J, double* scale, int approx) {
     const Mech& m = *static_cast<Mech*>(h);
     int N = m.ns + 1;
     size_t NN = (size_t)N * N;
@@ -770,18 +806,22 @@ void ora_jacobian(void* h, int form, long n, const double* x, const double* para
         if (scale) {
             std::vector<Scaled> xx(N), JJ(NN);
             for (int i = 0; i < N; ++i) xx[i] = Scaled(xs[i]);
-            jacobian(m, form, xx.data(), Scaled(param[s]), JJ.data());
+            jacobian(m, form, xx.data(), Scaled(param[s]), JJ.data(), approx != 0);
             for (size_t e = 0; e < NN; ++e) { J[s * NN + e] = JJ[e].v; scale[s * NN + e] = JJ[e].s; }
         } else {
-            jacobian(m, form, xs, param[s], J + s * NN);
+            jacobian(m, form, xs, param[s], J + s * NN, approx != 0);
         }
     }
 }
 
+void ora_jacobian(void* h, int form, long n, const double* x, const double* param, double* J, double* scale) {
+    ora_jacobian_ex(h, form, n, x, param, J, scale, 0);
+}
+
 // Complex-step Jacobian: column j = Im f(Phi + i h_j e_j) / h_j with
 // h_j = hrel * max(|Phi_j|, 1e-300).
-void ora_jacobian_cs(void* h, int form, long n, const double* x, const double* param,
-                     double hrel, double* J) {
+void ora_jacobian_cs_ex(void* h, int form, long n, const double* x, const double* param,
+                        double hrel, double* J, int approx) {
     const Mech& m = *static_cast<Mech*>(h);
     int N = m.ns + 1;
     typedef std::complex<double> C;
@@ -792,10 +832,14 @@ void ora_jacobian_cs(void* h, int form, long n, const double* x, const double* p
             for (int i = 0; i < N; ++i) xx[i] = C(xs[i], 0.0);
             double hj = hrel * std::fmax(std::fabs(xs[j]), 1e-300);
             xx[j] = C(xs[j], hj);
-            Eval<C> ev = evaluate(m, form, xx.data(), C(param[s], 0.0), false);
+            Eval<C> ev = evaluate<C>(m, form, xx.data(), C(param[s], 0.0), false, nullptr, approx != 0);
             for (int i = 0; i < N; ++i) J[(size_t)s * N * N + (size_t)i * N + j] = ev.f[i].imag() / hj;
         }
     }
+}
+
+void ora_jacobian_cs(void* h, int form, long n, const double* x, const double* param, double hrel, double* J) {
+    ora_jacobian_cs_ex(h, form, n, x, param, hrel, J, 0);
 }
 
 // Central finite-difference Jacobian with step h_j = rel * max(|Phi_j|, 1e-300).
@@ -819,6 +863,7 @@ void ora_jacobian_fd(void* h, int form, long n, const double* x, const double* p
 }
 
 void ora_pattern(void* h, unsigned char* P) { pattern(*static_cast<Mech*>(h), P); }
+void ora_pattern_ex(void* h, unsigned char* P, int approx) { pattern(*static_cast<Mech*>(h), P, approx != 0); }
 
 // Adjoint over n states (rows of length N, v likewise): jtv[s] = J(s)^T v[s];
 // grad[3][nr] = sum over states of d(v . dPhi/dt)/d(ln A, b, Ea/R) per reaction
