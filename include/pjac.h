@@ -86,6 +86,33 @@ typedef enum {
 pj_status pj_mech_load(const char* desc_path, pj_mech** out);
 
 /*
+ * pj_mech_load with options (bitwise or; 0 = pj_mech_load):
+ *   PJ_OPT_APPROX_JACOBIAN  the "approximate" Jacobian of Sec. 3.4: the bath
+ *       gas's moles are held fixed against the other species' moles (their
+ *       dependence on T and V or P kept), so a reaction of the bath gas, or a
+ *       bath-gas efficiency other than one, no longer makes rows dense; the
+ *       pattern is that form's.
+ *   PJ_OPT_CCS  sparse values in column order (the compressed-column storage
+ *       the paper pairs with layout F): value k of a state is the entry
+ *       (row_idx[k], column c) with col_ptr[c] <= k < col_ptr[c+1], see
+ *       pj_mech_jac_pattern_ccs; the CSR arrays still describe the pattern.
+ *   PJ_OPT_LINEAR_SEARCH  species-row entries find their CSR slot by
+ *       searching the row at run time (the lookup the paper times, Sec. 3.4)
+ *       instead of the static slot map: same values, for comparison.
+ */
+enum { PJ_OPT_APPROX_JACOBIAN = 1, PJ_OPT_CCS = 2, PJ_OPT_LINEAR_SEARCH = 4 };
+pj_status pj_mech_load_ex(const char* desc_path, int options, pj_mech** out);
+pj_status pj_mech_parse_ex(const char* desc_path, int options, pj_mech** out);
+int pj_mech_options(const pj_mech* mech); /* -1 for NULL */
+
+/*
+ * The pattern in column order: col_ptr has N+1 entries, row_idx nnz entries
+ * with ascending rows in each column; host arrays owned by the mechanism.
+ */
+pj_status pj_mech_jac_pattern_ccs(const pj_mech* mech, int64_t* nnz, const int32_t** col_ptr,
+                                  const int32_t** row_idx);
+
+/*
  * The two halves of pj_mech_load.  pj_mech_parse parses, validates and
  * derives the CSR pattern on the host only (no device needed): the handle can
  * be queried (sizes, pattern) and freed, but not evaluated.  pj_mech_upload

@@ -41,6 +41,15 @@ _lib.pj_mech_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(_P)]
 _lib.pj_mech_load.restype = ctypes.c_int
 _lib.pj_mech_parse.argtypes = [ctypes.c_char_p, ctypes.POINTER(_P)]
 _lib.pj_mech_parse.restype = ctypes.c_int
+_lib.pj_mech_load_ex.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(_P)]
+_lib.pj_mech_load_ex.restype = ctypes.c_int
+_lib.pj_mech_parse_ex.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(_P)]
+_lib.pj_mech_parse_ex.restype = ctypes.c_int
+_lib.pj_mech_options.argtypes = [_P]
+_lib.pj_mech_options.restype = ctypes.c_int
+_lib.pj_mech_jac_pattern_ccs.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
+                                         ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))]
+_lib.pj_mech_jac_pattern_ccs.restype = ctypes.c_int
 _lib.pj_mech_upload.argtypes = [_P]
 _lib.pj_mech_upload.restype = ctypes.c_int
 _lib.pj_mech_free.argtypes = [_P]
@@ -133,14 +142,19 @@ def library() -> ctypes.CDLL:
     return _lib
 
 
-class Mechanism:
-    """A mechanism description loaded by the library (pj_mech_load), or only
-    parsed on the host (``upload=False``, pj_mech_parse)."""
+OPT_APPROX_JACOBIAN, OPT_CCS, OPT_LINEAR_SEARCH = 1, 2, 4
 
-    def __init__(self, path: str, upload: bool = True):
+
+class Mechanism:
+    """A mechanism description loaded by the library (pj_mech_load_ex), or
+    only parsed on the host (``upload=False``, pj_mech_parse_ex).  ``options``:
+    OPT_APPROX_JACOBIAN, OPT_CCS, OPT_LINEAR_SEARCH (bitwise or)."""
+
+    def __init__(self, path: str, upload: bool = True, options: int = 0):
         h = _P()
-        fn = _lib.pj_mech_load if upload else _lib.pj_mech_parse
-        _check(fn(os.fsencode(path), ctypes.byref(h)), "pj_mech_load" if upload else "pj_mech_parse")
+        fn = _lib.pj_mech_load_ex if upload else _lib.pj_mech_parse_ex
+        _check(fn(os.fsencode(path), int(options), ctypes.byref(h)), "pj_mech_load_ex" if upload else "pj_mech_parse_ex")
+        self.options = int(options)
         self._h = h
         self.path = path
         self.n_species = _lib.pj_mech_n_species(h)
@@ -154,6 +168,12 @@ class Mechanism:
         self.nnz = int(nnz.value)
         self.row_ptr = np.ctypeslib.as_array(rp, shape=(self.N + 1,)).astype(np.int64)
         self.col_idx = np.ctypeslib.as_array(ci, shape=(self.nnz,)).astype(np.int64)
+        cp = ctypes.POINTER(ctypes.c_int32)()
+        ri = ctypes.POINTER(ctypes.c_int32)()
+        _check(_lib.pj_mech_jac_pattern_ccs(h, ctypes.byref(nnz), ctypes.byref(cp), ctypes.byref(ri)),
+               "pj_mech_jac_pattern_ccs")
+        self.col_ptr = np.ctypeslib.as_array(cp, shape=(self.N + 1,)).astype(np.int64)
+        self.row_idx = np.ctypeslib.as_array(ri, shape=(self.nnz,)).astype(np.int64)
 
     def upload(self):
         _check(_lib.pj_mech_upload(self._h), "pj_mech_upload")
@@ -222,8 +242,8 @@ class Mechanism:
         self.close()
 
 
-def load_mechanism(path: str) -> Mechanism:
-    return Mechanism(path, upload=True)
+def load_mechanism(path: str, options: int = 0) -> Mechanism:
+    return Mechanism(path, upload=True, options=options)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -479,10 +499,15 @@ def dense_as_sij(jac: torch.Tensor, layout: str) -> torch.Tensor:
 
 
 def sparse_to_dense(mech: Mechanism, vals: np.ndarray, layout: str) -> np.ndarray:
-    """Host helper: CSR values (numpy, library layout) -> dense [s, i, j]."""
+    """Host helper: sparse values (numpy, library layout; column order when
+    the mechanism was loaded with OPT_CCS) -> dense [s, i, j]."""
     v = vals.T if layout == "F" else vals
     n = v.shape[0]
     out = np.zeros((n, mech.N, mech.N))
-    rows = np.repeat(np.arange(mech.N), np.diff(mech.row_ptr))
-    out[:, rows, mech.col_idx] = v
+    if mech.options & OPT_CCS:
+        cols = np.repeat(np.arange(mech.N), np.diff(mech.col_ptr))
+        out[:, mech.row_idx, cols] = v
+    else:
+        rows = np.repeat(np.arange(mech.N), np.diff(mech.row_ptr))
+        out[:, rows, mech.col_idx] = v
     return out

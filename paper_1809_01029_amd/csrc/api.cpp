@@ -99,12 +99,15 @@ pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, in
 
 extern "C" {
 
-pj_status pj_mech_parse(const char* desc_path, pj_mech** out) {
+pj_status pj_mech_parse_ex(const char* desc_path, int options, pj_mech** out) {
     if (!out) return fail(PJ_E_INVALID, "NULL output handle");
     *out = nullptr;
     if (!desc_path) return fail(PJ_E_INVALID, "NULL path");
+    if (options & ~(PJ_OPT_APPROX_JACOBIAN | PJ_OPT_CCS | PJ_OPT_LINEAR_SEARCH))
+        return fail(PJ_E_INVALID, "unknown option bits");
     pj_mech* h = new (std::nothrow) pj_mech();
     if (!h) return fail(PJ_E_NOMEM, "out of host memory");
+    h->m.opts = options;
     std::string err;
     pj_status st = pj::build_mechanism(desc_path, h->m, err);
     if (st != PJ_OK) {
@@ -129,8 +132,14 @@ pj_status pj_mech_upload(pj_mech* mech) {
     return PJ_OK;
 }
 
-pj_status pj_mech_load(const char* desc_path, pj_mech** out) {
-    pj_status st = pj_mech_parse(desc_path, out);
+pj_status pj_mech_parse(const char* desc_path, pj_mech** out) { return pj_mech_parse_ex(desc_path, 0, out); }
+
+int pj_mech_options(const pj_mech* mech) { return mech ? mech->m.opts : -1; }
+
+pj_status pj_mech_load(const char* desc_path, pj_mech** out) { return pj_mech_load_ex(desc_path, 0, out); }
+
+pj_status pj_mech_load_ex(const char* desc_path, int options, pj_mech** out) {
+    pj_status st = pj_mech_parse_ex(desc_path, options, out);
     if (st != PJ_OK) return st;
     st = pj_mech_upload(*out);
     if (st != PJ_OK) {
@@ -164,6 +173,16 @@ pj_status pj_mech_jac_pattern(const pj_mech* mech, int64_t* nnz, const int32_t**
     *nnz = mech->m.nnz;
     *row_ptr = mech->m.row_ptr.data();
     *col_idx = mech->m.col_idx.data();
+    g_err.clear();
+    return PJ_OK;
+}
+
+pj_status pj_mech_jac_pattern_ccs(const pj_mech* mech, int64_t* nnz, const int32_t** col_ptr,
+                                  const int32_t** row_idx) {
+    if (!mech || !nnz || !col_ptr || !row_idx) return fail(PJ_E_INVALID, "NULL argument");
+    *nnz = mech->m.nnz;
+    *col_ptr = mech->m.col_ptr.data();
+    *row_idx = mech->m.row_idx.data();
     g_err.clear();
     return PJ_OK;
 }

@@ -97,6 +97,9 @@ struct DevMech {
     // pattern
     const int32_t* row_ptr;   // [N + 1]
     const uint16_t* row_of;   // [nnz] row (state index) of each CSR entry
+    const uint16_t* ccs_pos;  // [nnz] position of CSR entry e in column order, or NULL
+    int approx;               // approximate Jacobian (bath gas held against n_j)
+    int lsearch;              // find CSR slots by a run-time row search
     const int32_t* orig;      // [nr] description index of each kernel-order reaction
     const uint16_t* col_idx;  // [nnz]
     const int32_t* dense_rows;// [n_dense_rows] species index k of bath-dense rows
@@ -119,9 +122,11 @@ struct Mechanism {
     };
     std::vector<Rxn> rx;
 
+    int opts = 0;                          // PJ_OPT_* given at parse time
     // derived
     std::vector<int> order;                // kernel position -> description index
     std::vector<int32_t> row_ptr, col_idx; // CSR pattern
+    std::vector<int32_t> col_ptr, row_idx; // the same pattern in column order (CCS)
     int nnz = 0;
 
     // device

@@ -185,6 +185,15 @@ __device__ inline int eff_species(const uint32_t (&sp)[MAXEFF / 2], int e) {
     return (sp[e >> 1] >> (16 * (e & 1))) & 0xFFFF;
 }
 
+// CSR slot of (row, col) by a search of the row (the run-time lookup the
+// static slot map replaces; used only when the mechanism asks for it)
+__device__ inline uint16_t csr_lookup(const DevMech& dm, int row, int col) {
+    const int r0 = dm.row_ptr[row], r1 = dm.row_ptr[row + 1];
+    for (int e = r0; e < r1; ++e)
+        if (dm.col_idx[e] == col) return (uint16_t)e;
+    return NOSLOT;
+}
+
 // c^nu and d(c^nu)/dc for nu in {0, 1, 2} with selects instead of branches;
 // an empty slot (nu = 0) reads the sentinel concentration 1, giving f = 1
 __device__ inline void powd(double c, int nu, double& f, double& d) {
@@ -552,7 +561,10 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
 #pragma unroll
                 for (int b = 0; b < NSLOT; ++b) {
                     if (!((cmask >> b) & 1) || (b >= MAXSIDE && !any_rev)) continue;
-                    const uint16_t sl = jr.slot[a * NSLOT + b];
+                    uint16_t sl = jr.slot[a * NSLOT + b];
+                    if (dm.lsearch)
+                        sl = nu[b] && (b < MAXSIDE || rev) && spc[b] != bath
+                                 ? csr_lookup(dm, 2 + spc[a], 2 + spc[b]) : NOSLOT;
                     if (sl != NOSLOT) atomicAdd(&AT(J, sl), sg[a] * Qs[b]);
                 }
                 if (neffc) {
@@ -562,12 +574,16 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
 #pragma unroll
                     for (int e = 0; e < MAXEFF; ++e) {
                         if (e >= neffc) break;
-                        const uint32_t sl = (sw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+                        uint32_t sl = (sw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+                        if (dm.lsearch) {
+                            const int sp = eff_species(esp, e);
+                            sl = sp < bath ? csr_lookup(dm, 2 + spc[a], 2 + sp) : NOSLOT;
+                        }
                         if (sl != NOSLOT) atomicAdd(&AT(J, sl), sg[a] * qe[e]);
                     }
                 }
             }
-            if (w & INFO_BATH) {
+            if ((w & INFO_BATH) && !dm.approx) {
                 // bath-gas columns of these rows go to the per-row sum B
 #pragma unroll
                 for (int a = 0; a < NSLOT; ++a) {
@@ -626,7 +642,10 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             const double J00 = -(T * TT + Scw + Tdot * dDdT) / Dp;
             const double J01 = -(T * TS + Tdot * dDdS) / Dp;
             const double RTP = RU * T / P;
-            const double tqb = AT(TQ, bath), sqb = AT(SQ, bath);
+            // species columns: d/dn_j through [C]_j and, unless the
+            // approximate form holds it fixed, the bath gas's [C]_Ns
+            const double tqb = dm.approx ? 0.0 : AT(TQ, bath), sqb = dm.approx ? 0.0 : AT(SQ, bath);
+            const double cpb_n = dm.approx ? 0.0 : cpb;
             for (int j = g; j < N && valid; j += G) {
                 double j0, j1;
                 if (j == 0) {
@@ -640,19 +659,21 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                                          : Tdot * invT + P * invT * J01 + RU * T * SS;
                 } else {
                     const int k = j - 2;
-                    j0 = -(T * (AT(TQ, k) - tqb) + Tdot * (AT(CP, k) - cpb)) * invV / Dp;
+                    j0 = -(T * (AT(TQ, k) - tqb) + Tdot * (AT(CP, k) - cpb_n)) * invV / Dp;
                     j1 = FORM == PJ_CONP ? V * invT * j0 + RTP * (AT(SQ, k) - sqb)
                                          : P * invT * j0 + RU * T * (AT(SQ, k) - sqb) * invV;
                 }
                 if (ADJ) {
                     AT(JTV, j) = vT * j0 + vS * j1;
                 } else if (MODE == MODE_SPARSE) {
+                    const int p0 = dm.ccs_pos ? dm.ccs_pos[j] : j;
+                    const int p1 = dm.ccs_pos ? dm.ccs_pos[N + j] : N + j;
                     if (LAYOUT == PJ_LAYOUT_F) {
-                        jac[(long)j * n + st] = j0;
-                        jac[(long)(N + j) * n + st] = j1;
+                        jac[(long)p0 * n + st] = j0;
+                        jac[(long)p1 * n + st] = j1;
                     } else {
-                        jac[st * (long)nnz + j] = j0;
-                        jac[st * (long)nnz + N + j] = j1;
+                        jac[st * (long)nnz + p0] = j0;
+                        jac[st * (long)nnz + p1] = j1;
                     }
                 } else {
                     if (LAYOUT == PJ_LAYOUT_F) {
@@ -691,15 +712,24 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
         } else if (MODE == MODE_SPARSE) {
             if (LAYOUT == PJ_LAYOUT_F) {
                 // S consecutive states of one slot are contiguous
-                if (valid)
-                    for (int e = 2 * N + g; e < nnz; e += G) jac[(long)e * n + st] = AT(J, e);
+                if (valid) {
+                    if (dm.ccs_pos)
+                        for (int e = 2 * N + g; e < nnz; e += G) jac[(long)dm.ccs_pos[e] * n + st] = AT(J, e);
+                    else
+                        for (int e = 2 * N + g; e < nnz; e += G) jac[(long)e * n + st] = AT(J, e);
+                }
             } else {
                 // one state's slots are contiguous: threads of one state take
                 // consecutive slots
                 const int s2 = tid / G, g2 = tid % G;
                 const long st2 = qg * S + s2;
-                if (st2 < n)
-                    for (int e = 2 * N + g2; e < nnz; e += G) jac[st2 * (long)nnz + e] = J[(size_t)e * S + s2];
+                if (st2 < n) {
+                    if (dm.ccs_pos)
+                        for (int e = 2 * N + g2; e < nnz; e += G)
+                            jac[st2 * (long)nnz + dm.ccs_pos[e]] = J[(size_t)e * S + s2];
+                    else
+                        for (int e = 2 * N + g2; e < nnz; e += G) jac[st2 * (long)nnz + e] = J[(size_t)e * S + s2];
+                }
             }
         } else {
             const int s2 = tid / G, g2 = tid % G;

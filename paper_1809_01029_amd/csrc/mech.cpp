@@ -185,9 +185,11 @@ bool depends_on_bath(const Mechanism& m, const Mechanism::Rxn& r) {
     return false;
 }
 
-// The Jacobian pattern (Sec. 3.4).
+// The Jacobian pattern (Sec. 3.4).  Approximate form: no dense rows from the
+// bath gas (its moles are held fixed against the other species').
 void build_pattern(Mechanism& m) {
     int ns = m.ns, N = ns + 1, bath = ns - 1;
+    const bool approx = (m.opts & PJ_OPT_APPROX_JACOBIAN) != 0;
     std::vector<std::vector<char>> P(N, std::vector<char>(N, 0));
     for (int i = 0; i < N; ++i) { P[0][i] = P[1][i] = P[i][0] = P[i][1] = P[i][i] = 1; }
     for (const auto& r : m.rx) {
@@ -195,7 +197,7 @@ void build_pattern(Mechanism& m) {
         for (auto& a : r.reac) deps.push_back(a.first);
         if (r.rev) for (auto& b : r.prod) deps.push_back(b.first);
         if (r.kind != K_ELEM) for (auto& e : enhanced(r)) deps.push_back(e.first);
-        bool dense = depends_on_bath(m, r);
+        bool dense = !approx && depends_on_bath(m, r);
         auto row = [&](int k) {
             if (k == bath) return;
             if (dense) { for (int j = 2; j < N; ++j) P[2 + k][j] = 1; return; }
@@ -211,6 +213,13 @@ void build_pattern(Mechanism& m) {
         m.row_ptr[i + 1] = (int32_t)m.col_idx.size();
     }
     m.nnz = (int)m.col_idx.size();
+    // column order (CCS): rows ascending in each column
+    m.col_ptr.assign(N + 1, 0);
+    m.row_idx.clear();
+    for (int j = 0; j < N; ++j) {
+        for (int i = 0; i < N; ++i) if (P[i][j]) m.row_idx.push_back(i);
+        m.col_ptr[j + 1] = (int32_t)m.row_idx.size();
+    }
 }
 
 int csr_find(const Mechanism& m, int row, int col) {
@@ -393,7 +402,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
         for (int a = 0; a < NSLOT; ++a) {
             if (!nua[a] || spa[a] == bath) continue;
             Jr.rowbase[a] = (uint16_t)m.row_ptr[2 + spa[a]];
-            if (bathdep) dense_row[spa[a]] = 1;
+            if (bathdep && !(m.opts & PJ_OPT_APPROX_JACOBIAN)) dense_row[spa[a]] = 1;
             for (int b = 0; b < NSLOT; ++b) {
                 bool dep = nua[b] && (b < 3 || r.rev) && spa[b] != bath;
                 if (!dep) continue;
@@ -443,6 +452,13 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     for (int i = 0; i < N; ++i)
         for (int e = m.row_ptr[i]; e < m.row_ptr[i + 1]; ++e) row16[e] = (uint16_t)i;
     std::vector<int32_t> orig(m.order.begin(), m.order.end());
+    // CSR position -> column-order position
+    std::vector<uint16_t> ccs(m.nnz);
+    {
+        std::vector<int32_t> next(m.col_ptr.begin(), m.col_ptr.end() - 1);
+        for (int i = 0; i < N; ++i)
+            for (int e = m.row_ptr[i]; e < m.row_ptr[i + 1]; ++e) ccs[e] = (uint16_t)next[m.col_idx[e]]++;
+    }
     const int n_dense = (int)dense_rows.size();
     if (dense_rows.empty()) dense_rows.push_back(-1);
 
@@ -456,7 +472,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     size_t o_eff = place(effrec.size() * sizeof(EffRec));
     size_t o_rowp = place(m.row_ptr.size() * 4), o_col = place(col16.size() * 2),
            o_dr = place(dense_rows.size() * 4);
-    size_t o_rowof = place(row16.size() * 2), o_orig = place(orig.size() * 4);
+    size_t o_rowof = place(row16.size() * 2), o_orig = place(orig.size() * 4), o_ccs = place(ccs.size() * 2);
     std::vector<unsigned char> host(total, 0);
     auto put = [&](size_t off, const void* src, size_t bytes) { std::memcpy(host.data() + off, src, bytes); };
     put(o_th, th.data(), th.size() * sizeof(ThermoRec));
@@ -471,6 +487,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     put(o_dr, dense_rows.data(), dense_rows.size() * 4);
     put(o_rowof, row16.data(), row16.size() * 2);
     put(o_orig, orig.data(), orig.size() * 4);
+    put(o_ccs, ccs.data(), ccs.size() * 2);
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) { err = "no HIP device"; return PJ_E_DEVICE; }
@@ -504,6 +521,9 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.dense_rows = (const int32_t*)P(o_dr);
     dm.row_of = (const uint16_t*)P(o_rowof);
     dm.orig = (const int32_t*)P(o_orig);
+    dm.ccs_pos = (m.opts & PJ_OPT_CCS) ? (const uint16_t*)P(o_ccs) : nullptr;
+    dm.approx = (m.opts & PJ_OPT_APPROX_JACOBIAN) ? 1 : 0;
+    dm.lsearch = (m.opts & PJ_OPT_LINEAR_SEARCH) ? 1 : 0;
     m.h_rec = rec;
     m.off_rec = o_rec;
 

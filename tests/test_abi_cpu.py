@@ -207,3 +207,39 @@ def test_batch_argument_checks(api, tmp_path):
     assert lib.pj_batch_clear(b) == 0 and lib.pj_batch_size(b) == 0
     lib.pj_batch_free(b)
     lib.pj_batch_free(None)
+
+
+@pytest.mark.parametrize("name", ["ns13", "ns53", "ns111", "ns360"])
+def test_approximate_pattern_matches_oracle(api, name, mech_dir):
+    m, path = workload_file(name, mech_dir)
+    mech = api.Mechanism(path, upload=False, options=api.OPT_APPROX_JACOBIAN)
+    assert mech.options == api.OPT_APPROX_JACOBIAN
+    np.testing.assert_array_equal(mech.pattern_dense(), oracle.Oracle(path).pattern(approx=True))
+
+
+@pytest.mark.parametrize("seed", TINY_SEEDS)
+def test_approximate_pattern_matches_oracle_tiny(api, seed, mech_dir):
+    m, path = tiny_file(seed, mech_dir, bath_reactions=1, bath_efficiency=True)
+    mech = api.Mechanism(path, upload=False, options=api.OPT_APPROX_JACOBIAN)
+    np.testing.assert_array_equal(mech.pattern_dense(), oracle.Oracle(path).pattern(approx=True))
+
+
+def test_column_order_arrays_and_options(api, mech_dir, tmp_path):
+    m, path = workload_file("ns53", mech_dir)
+    mech = api.Mechanism(path, upload=False, options=api.OPT_CCS)
+    P = np.zeros((mech.N, mech.N), dtype=bool)
+    cols = np.repeat(np.arange(mech.N), np.diff(mech.col_ptr))
+    P[mech.row_idx, cols] = True
+    np.testing.assert_array_equal(P, mech.pattern_dense())
+    for c in range(mech.N):   # rows ascending within each column
+        assert np.all(np.diff(mech.row_idx[mech.col_ptr[c]:mech.col_ptr[c + 1]]) > 0)
+    # CCS of a dense matrix recovers it through sparse_to_dense
+    rng = np.random.default_rng(0)
+    D = rng.standard_normal((2, mech.N, mech.N)) * mech.pattern_dense()
+    vals = D[:, mech.row_idx, cols]
+    np.testing.assert_array_equal(api.sparse_to_dense(mech, vals, "C"), D)
+    lib = api.library()
+    h = ctypes.c_void_p()
+    assert lib.pj_mech_parse_ex(os.fsencode(path), 8, ctypes.byref(h)) == 1
+    assert b"option" in lib.pj_last_error()
+    assert lib.pj_mech_options(None) == -1
