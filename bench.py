@@ -317,6 +317,21 @@ def main():
                                "launch_shape": list(mech.launch_shape(3)),
                                "vs_sparse_jacobian": round(t / ms, 3)}
         del vv, jtv, grad
+        # the Jacobian variants of the paper on the same batch: approximate
+        # form, column-ordered values, run-time slot search (the lookup the
+        # static map replaces)
+        for label, opt in (("approximate_jacobian", api.OPT_APPROX_JACOBIAN), ("ccs_output", api.OPT_CCS),
+                           ("run_time_slot_search", api.OPT_LINEAR_SEARCH)):
+            mv = api.load_mechanism(path, options=opt)
+            mv.set_launch(*mech.launch_shape(1))
+            jv = torch.empty((mv.nnz, n) if args.layout == "F" else (n, mv.nnz), dtype=torch.float64,
+                             device="cuda")
+            t = timeit(lambda: api.eval_jacobian_sparse(mv, xs, ps, args.form, args.layout, out=jv, dstate=dstate,
+                                                        stream=stream), k=3)
+            variants[label] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3), "nnz": mv.nnz,
+                               "vs_static_csr": round(t / ms, 3)}
+            del jv
+            mv.close()
         if args.workload == "ns111" and not args.n_states:
             variants["ragged_13_53_111"] = ragged_batch(api, synth, torch, tmp, args, stream, timeit)
         log(f"variants: {json.dumps(variants)}")

@@ -3,6 +3,7 @@
 // except pj_mech_load, which uploads the tables.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -88,8 +89,16 @@ pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, in
     if (lds > m.lds_max)
         return fail(PJ_E_UNSUPPORTED, "per-state working set (" + std::to_string(lds) +
                                           " B) exceeds the LDS of one workgroup");
-    hipError_t e = pj::launch(m.dm, mode, form, layout, m.S[mode], n, state, param, dstate, jac, vin,
-                              grad, m.adj_grad_in_lds ? 1 : 0, m.waves[mode], lds, (hipStream_t)stream);
+    // the run-time slot search is its own kernel (the hot loop of the static
+    // map carries no trace of it), with at most 4 states per workgroup
+    int kmode = mode, S = m.S[mode];
+    if (mode == pj::MODE_SPARSE && m.dm.lsearch) {
+        kmode = pj::MODE_SPARSE_LS;
+        S = std::min(S, 4);
+    }
+    hipError_t e = pj::launch(m.dm, kmode, form, layout, S, n, state, param, dstate, jac, vin, grad,
+                              m.adj_grad_in_lds ? 1 : 0, m.waves[mode], pj::lds_bytes(m.dm, mode, S, m.waves[mode],
+                              m.adj_grad_in_lds), (hipStream_t)stream);
     if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     g_err.clear();
     return PJ_OK;

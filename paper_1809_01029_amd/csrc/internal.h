@@ -165,8 +165,9 @@ pj_status build_mechanism(const char* path, Mechanism& m, std::string& err);
 pj_status upload_mechanism(Mechanism& m, std::string& err);
 
 // kernels.hip
-enum Mode : int { MODE_SRC = 0, MODE_SPARSE = 1, MODE_DENSE = 2, MODE_ADJ = 3 };
-constexpr int N_MODES = 4;
+enum Mode : int { MODE_SRC = 0, MODE_SPARSE = 1, MODE_DENSE = 2, MODE_ADJ = 3,
+                  MODE_SPARSE_LS = 4 /* sparse with run-time slot search; launch shape of MODE_SPARSE */ };
+constexpr int N_MODES = 4;        // modes with a launch shape of their own
 constexpr int MAX_S_ADJ = 4;      // states per workgroup of the adjoint mode
 // grad_in_lds: the adjoint keeps its parameter sums in LDS (mode MODE_ADJ only)
 int64_t lds_bytes(const DevMech& dm, int mode, int S, int waves, bool grad_in_lds = true);

@@ -235,6 +235,8 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
     extern __shared__ double lds[];
     constexpr bool JAC = MODE != MODE_SRC;
     constexpr bool ADJ = MODE == MODE_ADJ;   // jac receives J^T v (state layout)
+    constexpr bool LS = MODE == MODE_SPARSE_LS;   // sparse, slots found by a row search
+    constexpr bool SPARSE = MODE == MODE_SPARSE || LS;
     const int ns = dm.ns, N = dm.N, bath = dm.bath, nnz = dm.nnz;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, nwave = nthr >> 6;
@@ -562,7 +564,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 for (int b = 0; b < NSLOT; ++b) {
                     if (!((cmask >> b) & 1) || (b >= MAXSIDE && !any_rev)) continue;
                     uint16_t sl = jr.slot[a * NSLOT + b];
-                    if (dm.lsearch)
+                    if (LS)
                         sl = nu[b] && (b < MAXSIDE || rev) && spc[b] != bath
                                  ? csr_lookup(dm, 2 + spc[a], 2 + spc[b]) : NOSLOT;
                     if (sl != NOSLOT) atomicAdd(&AT(J, sl), sg[a] * Qs[b]);
@@ -575,7 +577,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                     for (int e = 0; e < MAXEFF; ++e) {
                         if (e >= neffc) break;
                         uint32_t sl = (sw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-                        if (dm.lsearch) {
+                        if (LS) {
                             const int sp = eff_species(esp, e);
                             sl = sp < bath ? csr_lookup(dm, 2 + spc[a], 2 + sp) : NOSLOT;
                         }
@@ -665,7 +667,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 }
                 if (ADJ) {
                     AT(JTV, j) = vT * j0 + vS * j1;
-                } else if (MODE == MODE_SPARSE) {
+                } else if (SPARSE) {
                     const int p0 = dm.ccs_pos ? dm.ccs_pos[j] : j;
                     const int p1 = dm.ccs_pos ? dm.ccs_pos[N + j] : N + j;
                     if (LAYOUT == PJ_LAYOUT_F) {
@@ -709,7 +711,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                     if (LAYOUT == PJ_LAYOUT_F) jac[(long)i * n + st] = AT(JTV, i);
                     else jac[st * (long)N + i] = AT(JTV, i);
                 }
-        } else if (MODE == MODE_SPARSE) {
+        } else if (SPARSE) {
             if (LAYOUT == PJ_LAYOUT_F) {
                 // S consecutive states of one slot are contiguous
                 if (valid) {
@@ -942,12 +944,14 @@ hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int6
     PJ_CASE(F, L, M, 1) PJ_CASE(F, L, M, 2) PJ_CASE(F, L, M, 4) PJ_CASE(F, L, M, 8)          \
     PJ_CASE(F, L, M, 16) PJ_CASE(F, L, M, 32) PJ_CASE(F, L, M, 64)
 #define PJ_SA(F, L) PJ_CASE(F, L, MODE_ADJ, 1) PJ_CASE(F, L, MODE_ADJ, 2) PJ_CASE(F, L, MODE_ADJ, 4)
-#define PJ_MODES(F, L) PJ_S(F, L, MODE_SRC) PJ_S(F, L, MODE_SPARSE) PJ_S(F, L, MODE_DENSE) PJ_SA(F, L)
+#define PJ_SL(F, L) PJ_CASE(F, L, MODE_SPARSE_LS, 1) PJ_CASE(F, L, MODE_SPARSE_LS, 2) PJ_CASE(F, L, MODE_SPARSE_LS, 4)
+#define PJ_MODES(F, L) PJ_S(F, L, MODE_SRC) PJ_S(F, L, MODE_SPARSE) PJ_S(F, L, MODE_DENSE) PJ_SA(F, L) PJ_SL(F, L)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_F)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_C)
     PJ_MODES(PJ_CONV, PJ_LAYOUT_F)
     PJ_MODES(PJ_CONV, PJ_LAYOUT_C)
 #undef PJ_MODES
+#undef PJ_SL
 #undef PJ_SA
 #undef PJ_S
 #undef PJ_CASE
