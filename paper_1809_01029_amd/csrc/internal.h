@@ -17,6 +17,7 @@ constexpr double PREF = 101325.0;        // Pa
 constexpr int MAXSIDE = 3;               // species per reaction side
 constexpr int NSLOT = 2 * MAXSIDE;       // reactant slots 0..2, product slots 3..5
 constexpr uint16_t NOSLOT = 0xFFFF;
+constexpr uint16_t DMAP_SKIP = 0xFFFE;   // dense map: entry written elsewhere
 
 enum RxnKind : int { K_ELEM = 0, K_THREEBODY = 1, K_LINDEMANN = 2, K_TROE = 3 };
 
@@ -98,6 +99,8 @@ struct DevMech {
     const int32_t* row_ptr;   // [N + 1]
     const uint16_t* row_of;   // [nnz] row (state index) of each CSR entry
     const uint16_t* ccs_pos;  // [nnz] position of CSR entry e in column order, or NULL
+    const uint16_t* dmap_rm;  // [N*N] CSR slot of (i, j) at i*N + j, NOSLOT if none
+    const uint16_t* dmap_cm;  // [N*N] the same at i + N*j; DMAP_SKIP for rows 0 and 1
     int approx;               // approximate Jacobian (bath gas held against n_j)
     int lsearch;              // find CSR slots by a run-time row search
     const int32_t* orig;      // [nr] description index of each kernel-order reaction

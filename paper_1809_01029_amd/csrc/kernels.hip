@@ -206,7 +206,6 @@ __device__ inline void powd(double c, int nu, double& f, double& d) {
 int64_t lds_bytes(const DevMech& dm, int mode, int S, int waves, bool grad_in_lds) {
     int64_t d = 5 * (int64_t)(dm.ns + 1);
     if (mode != MODE_SRC) d += dm.nnz + dm.ns;
-    if (mode == MODE_DENSE) d += dm.N;
     if (mode == MODE_ADJ) d += 2 * (int64_t)dm.N;
     const int64_t per_group = mode == MODE_ADJ && grad_in_lds ? 3 * (int64_t)dm.nr_pad : 0;
     return (d * S + (int64_t)RED_PER_WAVE * waves * S + per_group) * 8;
@@ -252,8 +251,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
     double* red = W + (ns + 1) * S;
     double* J = red + RED_PER_WAVE * nwave * S;
     double* B = J + (size_t)nnz * S;
-    double* ROW = B + (size_t)ns * S;
-    double* VV = ROW;                     // adjoint: v, then J^T v
+    double* VV = B + (size_t)ns * S;      // adjoint: v, then J^T v
     double* JTV = VV + (size_t)N * S;
     // The T and V/P rows (the first 2N CSR slots) go to the output straight
     // from registers; their LDS space holds the energy- and mole-weighted
@@ -734,23 +732,25 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 }
             }
         } else {
-            const int s2 = tid / G, g2 = tid % G;
-            const long st2 = qg * S + s2;
-            for (int i = 2; i < N; ++i) {
-                for (int j = g; j < N; j += G) AT(ROW, j) = 0.0;
-                __syncthreads();
-                const int r0 = dm.row_ptr[i], r1 = dm.row_ptr[i + 1];
-                for (int e = r0 + g; e < r1; e += G) AT(ROW, dm.col_idx[e]) = AT(J, e);
-                __syncthreads();
-                if (LAYOUT == PJ_LAYOUT_F) {
-                    if (valid)
-                        for (int j = g; j < N; j += G) jac[st + n * ((long)i + (long)N * j)] = AT(ROW, j);
-                } else {
-                    if (st2 < n)
-                        for (int j = g2; j < N; j += G)
-                            jac[st2 * (long)N * N + (long)i * N + j] = ROW[(size_t)j * S + s2];
-                }
-                __syncthreads();
+            // dense: every entry of the species rows in output order, from the
+            // accumulator through the (row, column) -> CSR slot maps (0 off
+            // the pattern); the T and V/P rows were written above
+            const long NN = (long)N * N;
+            if (LAYOUT == PJ_LAYOUT_F) {
+                if (valid)
+                    for (long f = g; f < NN; f += G) {
+                        const uint16_t e = dm.dmap_cm[f];
+                        if (e == DMAP_SKIP) continue;
+                        jac[st + n * f] = e == NOSLOT ? 0.0 : AT(J, e);
+                    }
+            } else {
+                const int s2 = tid / G, g2 = tid % G;
+                const long st2 = qg * S + s2;
+                if (st2 < n)
+                    for (long f = 2 * (long)N + g2; f < NN; f += G) {
+                        const uint16_t e = dm.dmap_rm[f];
+                        jac[st2 * NN + f] = e == NOSLOT ? 0.0 : J[(size_t)e * S + s2];
+                    }
             }
         }
         __syncthreads();

@@ -472,7 +472,16 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     size_t o_eff = place(effrec.size() * sizeof(EffRec));
     size_t o_rowp = place(m.row_ptr.size() * 4), o_col = place(col16.size() * 2),
            o_dr = place(dense_rows.size() * 4);
+    // dense maps: CSR slot of every (row, column), row-major and column-major
+    std::vector<uint16_t> dmrm((size_t)N * N, NOSLOT), dmcm((size_t)N * N, NOSLOT);
+    for (int i = 0; i < N; ++i)
+        for (int e = m.row_ptr[i]; e < m.row_ptr[i + 1]; ++e) {
+            dmrm[(size_t)i * N + m.col_idx[e]] = (uint16_t)e;
+            dmcm[(size_t)i + (size_t)N * m.col_idx[e]] = (uint16_t)e;
+        }
+    for (int j = 0; j < N; ++j) dmcm[(size_t)N * j] = dmcm[1 + (size_t)N * j] = DMAP_SKIP;
     size_t o_rowof = place(row16.size() * 2), o_orig = place(orig.size() * 4), o_ccs = place(ccs.size() * 2);
+    size_t o_dmrm = place(dmrm.size() * 2), o_dmcm = place(dmcm.size() * 2);
     std::vector<unsigned char> host(total, 0);
     auto put = [&](size_t off, const void* src, size_t bytes) { std::memcpy(host.data() + off, src, bytes); };
     put(o_th, th.data(), th.size() * sizeof(ThermoRec));
@@ -488,6 +497,8 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     put(o_rowof, row16.data(), row16.size() * 2);
     put(o_orig, orig.data(), orig.size() * 4);
     put(o_ccs, ccs.data(), ccs.size() * 2);
+    put(o_dmrm, dmrm.data(), dmrm.size() * 2);
+    put(o_dmcm, dmcm.data(), dmcm.size() * 2);
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) { err = "no HIP device"; return PJ_E_DEVICE; }
@@ -522,6 +533,8 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.row_of = (const uint16_t*)P(o_rowof);
     dm.orig = (const int32_t*)P(o_orig);
     dm.ccs_pos = (m.opts & PJ_OPT_CCS) ? (const uint16_t*)P(o_ccs) : nullptr;
+    dm.dmap_rm = (const uint16_t*)P(o_dmrm);
+    dm.dmap_cm = (const uint16_t*)P(o_dmcm);
     dm.approx = (m.opts & PJ_OPT_APPROX_JACOBIAN) ? 1 : 0;
     dm.lsearch = (m.opts & PJ_OPT_LINEAR_SEARCH) ? 1 : 0;
     m.h_rec = rec;
