@@ -665,24 +665,11 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 }
                 if (ADJ) {
                     AT(JTV, j) = vT * j0 + vS * j1;
-                } else if (SPARSE) {
-                    const int p0 = dm.ccs_pos ? dm.ccs_pos[j] : j;
-                    const int p1 = dm.ccs_pos ? dm.ccs_pos[N + j] : N + j;
-                    if (LAYOUT == PJ_LAYOUT_F) {
-                        jac[(long)p0 * n + st] = j0;
-                        jac[(long)p1 * n + st] = j1;
-                    } else {
-                        jac[st * (long)nnz + p0] = j0;
-                        jac[st * (long)nnz + p1] = j1;
-                    }
                 } else {
-                    if (LAYOUT == PJ_LAYOUT_F) {
-                        jac[st + n * ((long)N * j)] = j0;
-                        jac[st + n * (1 + (long)N * j)] = j1;
-                    } else {
-                        jac[st * (long)N * N + j] = j0;
-                        jac[st * (long)N * N + N + j] = j1;
-                    }
+                    // staged in the g and h arrays (no longer needed) and
+                    // written with the species rows, in output order
+                    AT(Gg, j) = j0;
+                    AT(H, j) = j1;
                 }
             }
             // bath-gas dependent rows are dense: subtract their bath partial
@@ -710,13 +697,18 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                     else jac[st * (long)N + i] = AT(JTV, i);
                 }
         } else if (SPARSE) {
+            // CSR slot e of state s: the T row (e < N) and V/P row (N <= e < 2N)
+            // from their staging, the species rows from the accumulator
+            auto val = [&](int e, int ss) -> double {
+                return e < N ? Gg[(size_t)e * S + ss] : e < 2 * N ? H[(size_t)(e - N) * S + ss] : J[(size_t)e * S + ss];
+            };
             if (LAYOUT == PJ_LAYOUT_F) {
                 // S consecutive states of one slot are contiguous
                 if (valid) {
                     if (dm.ccs_pos)
-                        for (int e = 2 * N + g; e < nnz; e += G) jac[(long)dm.ccs_pos[e] * n + st] = AT(J, e);
+                        for (int e = g; e < nnz; e += G) jac[(long)dm.ccs_pos[e] * n + st] = val(e, s);
                     else
-                        for (int e = 2 * N + g; e < nnz; e += G) jac[(long)e * n + st] = AT(J, e);
+                        for (int e = g; e < nnz; e += G) jac[(long)e * n + st] = val(e, s);
                 }
             } else {
                 // one state's slots are contiguous: threads of one state take
@@ -725,31 +717,41 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 const long st2 = qg * S + s2;
                 if (st2 < n) {
                     if (dm.ccs_pos)
-                        for (int e = 2 * N + g2; e < nnz; e += G)
-                            jac[st2 * (long)nnz + dm.ccs_pos[e]] = J[(size_t)e * S + s2];
+                        for (int e = g2; e < nnz; e += G) jac[st2 * (long)nnz + dm.ccs_pos[e]] = val(e, s2);
                     else
-                        for (int e = 2 * N + g2; e < nnz; e += G) jac[st2 * (long)nnz + e] = J[(size_t)e * S + s2];
+                        for (int e = g2; e < nnz; e += G) jac[st2 * (long)nnz + e] = val(e, s2);
                 }
             }
         } else {
-            // dense: every entry of the species rows in output order, from the
+            // dense: every entry in output order; the species rows from the
             // accumulator through the (row, column) -> CSR slot maps (0 off
-            // the pattern); the T and V/P rows were written above
+            // the pattern), the T and V/P rows from their staging
             const long NN = (long)N * N;
             if (LAYOUT == PJ_LAYOUT_F) {
-                if (valid)
+                if (valid) {
+                    for (int j = g; j < N; j += G) {
+                        jac[st + n * ((long)N * j)] = AT(Gg, j);
+                        jac[st + n * (1 + (long)N * j)] = AT(H, j);
+                    }
                     for (long f = g; f < NN; f += G) {
                         const uint16_t e = dm.dmap_cm[f];
                         if (e == DMAP_SKIP) continue;
                         jac[st + n * f] = e == NOSLOT ? 0.0 : AT(J, e);
                     }
+                }
             } else {
                 const int s2 = tid / G, g2 = tid % G;
                 const long st2 = qg * S + s2;
                 if (st2 < n)
-                    for (long f = 2 * (long)N + g2; f < NN; f += G) {
-                        const uint16_t e = dm.dmap_rm[f];
-                        jac[st2 * NN + f] = e == NOSLOT ? 0.0 : J[(size_t)e * S + s2];
+                    for (long f = g2; f < NN; f += G) {
+                        double v;
+                        if (f < N) v = Gg[(size_t)f * S + s2];
+                        else if (f < 2 * N) v = H[(size_t)(f - N) * S + s2];
+                        else {
+                            const uint16_t e = dm.dmap_rm[f];
+                            v = e == NOSLOT ? 0.0 : J[(size_t)e * S + s2];
+                        }
+                        jac[st2 * NN + f] = v;
                     }
             }
         }
