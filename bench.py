@@ -53,7 +53,7 @@ def measured_traffic(workload, form, layout, n, shape):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
     this workload, or None if there is none, it was taken with another launch
     shape, or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"pj_kernel_{workload}_{form}_{layout}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"pj_kernel_{workload}_{form}_{layout}_{shape[0]}x{shape[1]}_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
