@@ -28,6 +28,17 @@
 // derivatives by the chain rule through the rate of progress (for falloff
 // reactions the parameters are those of the high-pressure limit).
 //
+// Reaction types (Sec. 2.2 names them as supported; the formulas are the
+// standard ones): elementary, third-body, falloff with the Lindemann, Troe or
+// SRI broadening factor, chemically activated (the same broadening on a rate
+// with the low-pressure limit, c = F / (1 + Pr)), pressure-dependent
+// Arrhenius (P-Log: ln k linear in ln P between tabulated pressures, the end
+// values outside) and Chebyshev (log10 k a double Chebyshev series in reduced
+// 1/T and log P).  For the last two the main Arrhenius expression is a factor
+// on the tabulated rate, which is what the adjoint's parameters then mean; a
+// rate tabulated in pressure depends on the state variable P of the
+// constant-volume form.
+//
 // The "approximate" Jacobian (Sec. 3.4) neglects the dependence of the bath
 // gas's concentration on the other species' moles: d[C]_Ns/dn_j = 0 for
 // j < Ns, while its dependence on T and V (or P) is kept; this removes the
@@ -55,7 +66,7 @@ const double PREF = 101325.0;
 const double LN10 = 2.302585092994045684;
 
 enum { FORM_CONP = 0, FORM_CONV = 1 };
-enum { T_ELEM = 0, T_THREEBODY = 1, T_LINDEMANN = 2, T_TROE = 3 };
+enum { T_ELEM = 0, T_THREEBODY = 1, T_LINDEMANN = 2, T_TROE = 3, T_SRI = 4, T_PLOG = 5, T_CHEB = 6 };
 
 struct Species {
     double W;
@@ -71,7 +82,17 @@ struct Reaction {
     double lnA, b, theta;
     double lnA0 = 0, b0 = 0, theta0 = 0;            // low-pressure limit
     double alpha = 0, T3 = 0, T1 = 0, T2 = 0;       // Troe
+    double sri[5] = {0, 0, 0, 0, 0};                // SRI a, b, c, d, e
+    bool chemact = false;                           // chemically activated
     std::vector<std::pair<int, double>> eff;        // (species, efficiency)
+    // P-Log: (P [Pa], ln A, b, Ea/R) in ascending pressure
+    std::vector<std::vector<double>> plog;
+    // Chebyshev: NT x NP coefficients of log10 k (t-major) over [Tmin, Tmax] x [Pmin, Pmax]
+    int cheb_nt = 0, cheb_np = 0;
+    double cheb_Tmin = 0, cheb_Tmax = 0, cheb_Pmin = 0, cheb_Pmax = 0;
+    std::vector<double> cheb;
+    bool falloff() const { return type == T_LINDEMANN || type == T_TROE || type == T_SRI; }
+    bool pressure_table() const { return type == T_PLOG || type == T_CHEB; }
 };
 
 struct Mech {
@@ -143,6 +164,9 @@ int type_code(const std::string& t) {
     if (t == "THREEBODY") return T_THREEBODY;
     if (t == "LINDEMANN") return T_LINDEMANN;
     if (t == "TROE") return T_TROE;
+    if (t == "SRI") return T_SRI;
+    if (t == "PLOG") return T_PLOG;
+    if (t == "CHEB") return T_CHEB;
     return -1;
 }
 
@@ -186,12 +210,32 @@ bool parse(const char* path, Mech& m) {
         while (f >> tok) {
             if (tok == "LOW") f >> r.lnA0 >> r.b0 >> r.theta0;
             else if (tok == "TROE") f >> r.alpha >> r.T3 >> r.T1 >> r.T2;
-            else if (tok == "EFF") {
+            else if (tok == "SRI") { for (double& v : r.sri) f >> v; }
+            else if (tok == "CHEMACT") r.chemact = true;
+            else if (tok == "PLOG") {
+                f >> n;
+                for (int a = 0; a < n; ++a) {
+                    std::vector<double> pt(4);
+                    for (double& v : pt) f >> v;
+                    r.plog.push_back(pt);
+                }
+            } else if (tok == "CHEB") {
+                f >> r.cheb_nt >> r.cheb_np >> r.cheb_Tmin >> r.cheb_Tmax >> r.cheb_Pmin >> r.cheb_Pmax;
+                if (!f || r.cheb_nt < 1 || r.cheb_np < 1) return false;
+                r.cheb.resize((size_t)r.cheb_nt * r.cheb_np);
+                for (double& v : r.cheb) f >> v;
+            } else if (tok == "EFF") {
                 f >> n;
                 for (int a = 0; a < n; ++a) { int s; double al; f >> s >> al; r.eff.push_back({s, al}); }
             } else break;
         }
         if (!f) return false;
+        if ((r.type == T_PLOG) != !r.plog.empty() || (r.type == T_CHEB) != !r.cheb.empty()) return false;
+        for (size_t a = 0; a < r.plog.size(); ++a)
+            if (!(r.plog[a][0] > 0) || (a && !(r.plog[a][0] > r.plog[a - 1][0]))) return false;
+        if (r.type == T_CHEB && !(r.cheb_Tmin > 0 && r.cheb_Tmax > r.cheb_Tmin && r.cheb_Pmin > 0
+                                  && r.cheb_Pmax > r.cheb_Pmin)) return false;
+        if (r.chemact && !r.falloff()) return false;
     }
     return tok == "END";
 }
@@ -282,8 +326,9 @@ struct RxnEval {
     S dRf_dT, dRr_dT;
     std::vector<S> dq_dC;       // dq/d[C]_m at fixed T and C_tot
     S dq_dCtot;                 // dq/dC_tot at fixed T and concentrations
-    S dq_dT;                    // dq/dT at fixed concentrations
-    S dq_dlnk;                  // dq/d ln k_f at fixed T and concentrations
+    S dq_dT;                    // dq/dT at fixed concentrations (and fixed P)
+    S dq_dP;                    // dq/dP at fixed T and concentrations (P-Log, Chebyshev)
+    S dq_dlnk;                  // dq/d ln(main Arrhenius factor) at fixed T and concentrations
 };
 
 // Optional perturbations of a reaction's Arrhenius parameters (ln A, b,
@@ -327,6 +372,83 @@ S mass_action_d(const std::vector<std::pair<int, int>>& side, const std::vector<
     return d;
 }
 
+// Rate constants tabulated in pressure: ln k and its partial derivatives by T
+// (at fixed P) and by ln P (at fixed T).
+template <class S>
+struct LnK {
+    S v, dT, dlnP;
+};
+
+// P-Log: between the two tabulated pressures that bracket P, ln k is linear in
+// ln P, each pressure carrying its own Arrhenius expression; below the first
+// or above the last pressure that end's expression holds.
+template <class S>
+LnK<S> plog_lnk(const Reaction& r, S T, S P) {
+    auto lnk_at = [&](const std::vector<double>& pt, S& dT) {
+        dT = S(pt[2]) / T + S(pt[3]) / (T * T);
+        return S(pt[1]) + S(pt[2]) * log(T) - S(pt[3]) / T;
+    };
+    LnK<S> o;
+    const size_t m = r.plog.size();
+    const double p = re(P);
+    o.dlnP = S(0.0);
+    if (m == 1 || p <= r.plog[0][0]) { o.v = lnk_at(r.plog[0], o.dT); return o; }
+    if (p >= r.plog[m - 1][0]) { o.v = lnk_at(r.plog[m - 1], o.dT); return o; }
+    size_t i = 0;
+    while (!(p < r.plog[i + 1][0])) ++i;     // P_i <= P < P_{i+1}
+    S d1, d2;
+    S l1 = lnk_at(r.plog[i], d1), l2 = lnk_at(r.plog[i + 1], d2);
+    S lp1 = S(std::log(r.plog[i][0])), lp2 = S(std::log(r.plog[i + 1][0]));
+    S slope = (l2 - l1) / (lp2 - lp1);
+    S w = (log(P) - lp1) / (lp2 - lp1);
+    o.v = l1 + slope * (log(P) - lp1);
+    o.dT = d1 + w * (d2 - d1);
+    o.dlnP = slope;
+    return o;
+}
+
+// Chebyshev polynomials of the first kind T_0..T_{n-1} at x and their
+// derivatives, from T_0 = 1, T_1 = x, T_{j+1} = 2 x T_j - T_{j-1}.
+template <class S>
+void cheb_poly(int n, S x, std::vector<S>& t, std::vector<S>& dt) {
+    t.assign(n, S(0.0));
+    dt.assign(n, S(0.0));
+    t[0] = S(1.0);
+    if (n > 1) { t[1] = x; dt[1] = S(1.0); }
+    for (int j = 1; j + 1 < n; ++j) {
+        t[j + 1] = S(2.0) * x * t[j] - t[j - 1];
+        dt[j + 1] = S(2.0) * t[j] + S(2.0) * x * dt[j] - dt[j - 1];
+    }
+}
+
+// Chebyshev: log10 k = sum_t sum_p a_tp T_t(Tr) T_p(Pr) with the reduced
+// variables Tr = (2/T - 1/Tmin - 1/Tmax) / (1/Tmax - 1/Tmin) and
+// Pr = (2 log10 P - log10 Pmin - log10 Pmax) / (log10 Pmax - log10 Pmin).
+template <class S>
+LnK<S> cheb_lnk(const Reaction& r, S T, S P) {
+    const double iTmin = 1.0 / r.cheb_Tmin, iTmax = 1.0 / r.cheb_Tmax;
+    const double lmin = std::log10(r.cheb_Pmin), lmax = std::log10(r.cheb_Pmax);
+    S Tr = (S(2.0) / T - S(iTmin) - S(iTmax)) / S(iTmax - iTmin);
+    S Prd = (S(2.0) * log10(P) - S(lmin) - S(lmax)) / S(lmax - lmin);
+    std::vector<S> ft, dft, fp, dfp;
+    cheb_poly(r.cheb_nt, Tr, ft, dft);
+    cheb_poly(r.cheb_np, Prd, fp, dfp);
+    S v(0.0), dv_dTr(0.0), dv_dPr(0.0);
+    for (int t = 0; t < r.cheb_nt; ++t)
+        for (int q = 0; q < r.cheb_np; ++q) {
+            S a(r.cheb[(size_t)t * r.cheb_np + q]);
+            v = v + a * ft[t] * fp[q];
+            dv_dTr = dv_dTr + a * dft[t] * fp[q];
+            dv_dPr = dv_dPr + a * ft[t] * dfp[q];
+        }
+    LnK<S> o;
+    o.v = S(LN10) * v;
+    // dTr/dT = -2 / (T^2 (1/Tmax - 1/Tmin)); dPr/d ln P = 2 / (ln 10 (log10 Pmax - log10 Pmin))
+    o.dT = S(LN10) * dv_dTr * S(-2.0) / (T * T * S(iTmax - iTmin));
+    o.dlnP = dv_dPr * S(2.0) / S(lmax - lmin);
+    return o;
+}
+
 template <class S>
 RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
                          const std::vector<Thermo<S>>& th, bool with_derivs,
@@ -334,13 +456,38 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
     int ns = m.ns;
     RxnEval<S> e;
     S T = st.T;
+    // the main Arrhenius expression ka: k_f itself, the high-pressure limit of
+    // a falloff or chemically activated reaction, or a factor on a rate
+    // constant tabulated in pressure
+    S ka, dka_dT;
     if (shift) {
         S bb = S(r.b) + shift->b, tt = S(r.theta) + shift->theta;
-        e.kf = exp(S(r.lnA) + shift->lnA + bb * log(T) - tt / T);
-        e.dkf_dT = e.kf * (bb / T + tt / (T * T));
+        ka = exp(S(r.lnA) + shift->lnA + bb * log(T) - tt / T);
+        dka_dT = ka * (bb / T + tt / (T * T));
     } else {
-        e.kf = arrhenius(r.lnA, r.b, r.theta, T);
-        e.dkf_dT = e.kf * (S(r.b) / T + S(r.theta) / (T * T));
+        ka = arrhenius(r.lnA, r.b, r.theta, T);
+        dka_dT = ka * (S(r.b) / T + S(r.theta) / (T * T));
+    }
+    S dlnk_dlnP(0.0);   // pressure dependence of k_f at fixed T (P-Log, Chebyshev)
+    e.kf = ka;
+    e.dkf_dT = dka_dT;
+    if (r.pressure_table()) {
+        LnK<S> t = r.type == T_PLOG ? plog_lnk(r, T, st.P) : cheb_lnk(r, T, st.P);
+        S kt = exp(t.v);
+        e.kf = ka * kt;
+        e.dkf_dT = dka_dT * kt + e.kf * t.dT;
+        dlnk_dlnP = t.dlnP;
+    }
+    // falloff forms: the low-pressure limit; a chemically activated reaction's
+    // rate multiplies it instead of the high-pressure limit
+    S k0(0.0), dk0_dT(0.0);
+    if (r.falloff()) {
+        k0 = arrhenius(r.lnA0, r.b0, r.theta0, T);
+        dk0_dT = k0 * (S(r.b0) / T + S(r.theta0) / (T * T));
+    }
+    if (r.chemact) {
+        e.kf = k0;
+        e.dkf_dT = dk0_dT;
     }
 
     // reverse rate constant from the equilibrium constant:
@@ -368,7 +515,6 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
         e.dkr_dT = S(0.0);
     }
 
-    // falloff reactions use the high-pressure limit as k_f
     e.Rf = e.kf * mass_action(r.reac, st.C);
     e.Rr = r.rev ? e.kr * mass_action(r.prod, st.C) : S(0.0);
 
@@ -380,7 +526,7 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
     // to sum_k alpha_k [C]_k; written this way, a species of default efficiency
     // does not enter [M] through the concentrations)
     S M(0.0);
-    if (r.type != T_ELEM) {
+    if (r.type == T_THREEBODY || r.falloff()) {
         M = st.P / (S(RU) * T);
         for (int k = 0; k < ns; ++k)
             if (alpha[k] != 1.0) M = M + S(alpha[k] - 1.0) * st.C[k];
@@ -389,18 +535,16 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
     e.dc_dC.assign(ns, S(0.0));
     e.dc_dCtot = S(0.0);
     e.dc_dT = S(0.0);
-    S Pr_dc_dPr(0.0);   // Pr dc/dPr of a falloff reaction (Pr = k0 [M] / k_f)
-    if (r.type == T_ELEM) {
+    S Pr_dc_dPr(0.0);   // Pr dc/dPr of a falloff reaction (Pr = k0 [M] / k_inf)
+    if (r.type == T_ELEM || r.pressure_table()) {
         e.c = S(1.0);
     } else if (r.type == T_THREEBODY) {
         e.c = M;
         for (int k = 0; k < ns; ++k) e.dc_dC[k] = S(alpha[k] - 1.0);
         e.dc_dCtot = S(1.0);
     } else {
-        S k0 = arrhenius(r.lnA0, r.b0, r.theta0, T);
-        S dk0_dT = k0 * (S(r.b0) / T + S(r.theta0) / (T * T));
-        S Pr = k0 * M / e.kf;
-        S dPr_dT = M * (dk0_dT * e.kf - k0 * e.dkf_dT) / (e.kf * e.kf);
+        S Pr = k0 * M / ka;
+        S dPr_dT = M * (dk0_dT * ka - k0 * dka_dT) / (ka * ka);
         S F(1.0), dF_dPr(0.0), dF_dT(0.0);
         if (r.type == T_TROE) {
             S Fcent = S(1.0 - r.alpha) * exp(-T / S(r.T3)) + S(r.alpha) * exp(-T / S(r.T1))
@@ -427,20 +571,43 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
             dF_dPr = F * dexpo_df * df_dlP / Pr;
             // dF/dT at fixed Pr, through Fcent: dL/dT = dFcent/dT / (Fcent ln10)
             dF_dT = F * S(LN10) * dexpo_dL * dFcent_dT / (Fcent * S(LN10));
+        } else if (r.type == T_SRI) {
+            // SRI: F = d (a exp(-b/T) + exp(-T/c))^X T^e, X = 1 / (1 + (log10 Pr)^2)
+            S a(r.sri[0]), b(r.sri[1]), cc(r.sri[2]), d(r.sri[3]), ee(r.sri[4]);
+            S lP = log10(Pr);
+            S X = S(1.0) / (S(1.0) + lP * lP);
+            S base = a * exp(-b / T) + exp(-T / cc);
+            S dbase_dT = a * b / (T * T) * exp(-b / T) - exp(-T / cc) / cc;
+            F = d * exp(X * log(base)) * exp(ee * log(T));
+            // dX/dPr = -2 log10(Pr) X^2 / (Pr ln 10)
+            dF_dPr = F * log(base) * (S(-2.0) * lP * X * X) / (Pr * S(LN10));
+            dF_dT = F * (X * dbase_dT / base + ee / T);
         }
-        // c = F Pr / (1 + Pr), written as F / (1 + 1/Pr): the same value, but its
-        // complex-step derivative carries no cancellation when Pr >> 1
-        e.c = F / (S(1.0) + S(1.0) / Pr);
-        S dc_dPr = F / ((S(1.0) + Pr) * (S(1.0) + Pr)) + Pr / (S(1.0) + Pr) * dF_dPr;
-        e.dc_dT = dc_dPr * dPr_dT + Pr / (S(1.0) + Pr) * dF_dT;
-        for (int k = 0; k < ns; ++k) e.dc_dC[k] = dc_dPr * k0 * S(alpha[k] - 1.0) / e.kf;
-        e.dc_dCtot = dc_dPr * k0 / e.kf;
+        S dc_dPr;
+        if (r.chemact) {
+            // chemically activated: c = F / (1 + Pr) on the rate with k_0
+            e.c = F / (S(1.0) + Pr);
+            dc_dPr = dF_dPr / (S(1.0) + Pr) - F / ((S(1.0) + Pr) * (S(1.0) + Pr));
+            e.dc_dT = dc_dPr * dPr_dT + dF_dT / (S(1.0) + Pr);
+        } else {
+            // c = F Pr / (1 + Pr), written as F / (1 + 1/Pr): the same value, but its
+            // complex-step derivative carries no cancellation when Pr >> 1
+            e.c = F / (S(1.0) + S(1.0) / Pr);
+            dc_dPr = F / ((S(1.0) + Pr) * (S(1.0) + Pr)) + Pr / (S(1.0) + Pr) * dF_dPr;
+            e.dc_dT = dc_dPr * dPr_dT + Pr / (S(1.0) + Pr) * dF_dT;
+        }
+        for (int k = 0; k < ns; ++k) e.dc_dC[k] = dc_dPr * k0 * S(alpha[k] - 1.0) / ka;
+        e.dc_dCtot = dc_dPr * k0 / ka;
         Pr_dc_dPr = Pr * dc_dPr;
     }
     e.q = e.c * (e.Rf - e.Rr);
-    // R = Rf - Rr is proportional to k_f (k_r = k_f / Kc); for falloff
-    // reactions c also depends on k_f through Pr, with dPr/d ln k_f = -Pr
-    e.dq_dlnk = (r.type == T_LINDEMANN || r.type == T_TROE) ? e.q - (e.Rf - e.Rr) * Pr_dc_dPr : e.q;
+    // R = Rf - Rr is proportional to k_f (k_r = k_f / Kc), and k_f to the main
+    // Arrhenius factor except for a chemically activated reaction (k_f = k_0);
+    // for falloff forms c also depends on that factor through Pr, with
+    // dPr/d ln k_inf = -Pr
+    e.dq_dlnk = (r.chemact ? S(0.0) : e.q) - (r.falloff() ? (e.Rf - e.Rr) * Pr_dc_dPr : S(0.0));
+    // explicit pressure dependence of k_f (k_r = k_f / Kc follows it)
+    e.dq_dP = e.c * (e.Rf - e.Rr) * dlnk_dlnP / st.P;
     if (!with_derivs) return e;
 
     e.dRf_dC.assign(ns, S(0.0));
@@ -583,6 +750,8 @@ void jacobian(const Mech& m, int form, const S* x, S param, S* J, bool approx = 
             S acc = (j == 0) ? ev.rx[i].dq_dT : S(0.0);
             for (int k : colnz[j]) acc = acc + ev.rx[i].dq_dC[k] * dc(k, j);
             if (j < 2) acc = acc + ev.rx[i].dq_dCtot * dCtot[j];
+            // a rate constant tabulated in pressure: P is a state variable of CONV
+            if (j == 1 && form == FORM_CONV) acc = acc + ev.rx[i].dq_dP;
             dq[(size_t)i * N + j] = acc;
         }
 

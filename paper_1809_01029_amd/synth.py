@@ -26,6 +26,14 @@ What it builds (all from ``numpy.random.Generator(PCG64(seed))``):
   1..6 species), Lindemann and Troe falloff (alpha U[0,1], T***, T*, T** in
   U[100, 5000] K).  Arrhenius: log10 A ~ U[8,16], b ~ U[-2,3], Ea/R ~
   U[0, 30000] K; falloff low-pressure limits drawn from the same ranges.
+  Optional further types (absent from the default mixes): SRI falloff
+  (a U[0.1, 2], b and c U[100, 2000] K, d U[0.5, 2], e U[-0.5, 0.5]);
+  chemically activated reactions (Lindemann, Troe or SRI form); pressure-
+  dependent Arrhenius (P-Log: 2..5 pressures with log10 P/atm in [-1, 2.5],
+  each with the reaction's Arrhenius perturbed by U[-2, 2] in ln A,
+  U[-0.5, 0.5] in b and U[-2000, 2000] K in Ea/R); Chebyshev (3..6 x 2..4
+  coefficients over 290..3000 K and 0.01..100 atm, alpha_00 U[8, 13],
+  alpha_10 U[-3, 0], the others N(0, 0.3^2)/(1 + t + p)).
 * States: T ~ U[Tlo, Thi], P ~ U[Plo, Phi] atm, mass fractions
   Y ~ Dirichlet(0.5), V = 1 m^3, moles from the ideal-gas law.  The same draw
   gives the constant-pressure state (T, V, n_1..n_{Ns-1}) with parameter P and
@@ -39,11 +47,18 @@ written with 17 significant digits so it round-trips exactly)::
     SP <k> <name> <W> <nC> <nH> <nO> <nN> <Tlow> <Tmid> <Thigh> <a_lo x7> <a_hi x7>
     REACTIONS <Nr>
     RX <i> <TYPE> <rev> <n_reac> (<sp> <nu>)* <n_prod> (<sp> <nu>)* <lnA> <b> <Ea/R>
-       [LOW <lnA0> <b0> <Ea0/R>] [TROE <alpha> <T***> <T*> <T**>] [EFF <m> (<sp> <alpha>)*]
+       [LOW <lnA0> <b0> <Ea0/R>] [TROE <alpha> <T***> <T*> <T**>] [SRI <a> <b> <c> <d> <e>]
+       [CHEMACT] [PLOG <m> (<P> <lnA> <b> <Ea/R>)*]
+       [CHEB <NT> <NP> <Tmin> <Tmax> <Pmin> <Pmax> <alpha_tp, t-major>] [EFF <m> (<sp> <alpha>)*]
     END
 
-TYPE is ELEM, THREEBODY, LINDEMANN or TROE; rev is 1 (reversible) or 0.
-Species indices are 0-based; the last species is the bath gas.
+TYPE is ELEM, THREEBODY, LINDEMANN, TROE, SRI, PLOG or CHEB; rev is 1
+(reversible) or 0.  Species indices are 0-based; the last species is the bath
+gas.  For LINDEMANN, TROE and SRI the main Arrhenius is the high-pressure
+limit and LOW the low-pressure one; CHEMACT marks a chemically activated
+reaction (the rate multiplies the low-pressure limit).  For PLOG and CHEB the
+main Arrhenius is a factor on the tabulated rate constant (0 0 0 = none);
+pressures are in Pa, in ascending order for PLOG.
 """
 from __future__ import annotations
 
@@ -60,7 +75,8 @@ R_GAS = 8314.462618  # J/(kmol K); used here only to turn mole fractions into mo
 
 T_LOW, T_MID, T_HIGH = 300.0, 1000.0, 5000.0
 
-TYPES = ("ELEM", "THREEBODY", "LINDEMANN", "TROE")
+TYPES = ("ELEM", "THREEBODY", "LINDEMANN", "TROE", "SRI", "PLOG", "CHEB")
+FALLOFF_TYPES = ("LINDEMANN", "TROE", "SRI")
 
 
 @dataclasses.dataclass
@@ -75,6 +91,11 @@ class Reaction:
     low: Optional[Tuple[float, float, float]] = None      # (lnA0, b0, theta0)
     troe: Optional[Tuple[float, float, float, float]] = None  # (alpha, T***, T*, T**)
     eff: List[Tuple[int, float]] = dataclasses.field(default_factory=list)
+    sri: Optional[Tuple[float, float, float, float, float]] = None  # (a, b, c, d, e)
+    chemact: bool = False          # chemically activated (falloff forms)
+    plog: Optional[List[Tuple[float, float, float, float]]] = None  # (P [Pa], lnA, b, Ea/R)
+    # Chebyshev: ((Tmin, Tmax, Pmin [Pa], Pmax [Pa]), coefficients [NT][NP])
+    cheb: Optional[Tuple[Tuple[float, float, float, float], List[List[float]]]] = None
 
 
 @dataclasses.dataclass
@@ -108,6 +129,10 @@ class MixSpec:
     third_body: float = 0.10
     falloff: float = 0.15          # half Lindemann, half Troe
     irreversible: float = 0.05
+    sri: float = 0.0               # SRI falloff
+    chem_act: float = 0.0          # chemically activated (Lindemann, Troe, SRI in turn)
+    plog: float = 0.0
+    cheb: float = 0.0
 
 
 @dataclasses.dataclass(frozen=True)
@@ -135,6 +160,10 @@ WORKLOADS: Dict[str, Workload] = {
     "ns360": Workload("ns360", 360, 2170, 16_384, 360, 1360, T_range=(700.0, 1800.0),
                       P_range_atm=(10.0, 60.0), mix=MixSpec(0.10, 0.20, 0.05),
                       zipf=1.2, bath_reactions=2, n_inert=2),
+    # the 111-species size with every reaction type the library supports
+    "ns111x": Workload("ns111x", 111, 784, 262_144, 111, 1111, zipf=2.5, bath_reactions=1,
+                       n_inert=2, mix=MixSpec(third_body=0.10, falloff=0.10, irreversible=0.05,
+                                              sri=0.03, chem_act=0.04, plog=0.05, cheb=0.03)),
 }
 
 
@@ -371,11 +400,17 @@ def make_mechanism(ns: int, nr: int, seed: int, mix: MixSpec = MixSpec(), zipf: 
     n_troe = n_fall // 2
     n_lind = n_fall - n_troe
     n_irr = int(round(mix.irreversible * nr))
-    n_elem = nr - n_tb - n_fall - n_irr
+    n_sri = int(round(mix.sri * nr))
+    n_ca = int(round(mix.chem_act * nr))
+    n_plog = int(round(mix.plog * nr))
+    n_cheb = int(round(mix.cheb * nr))
+    n_elem = nr - n_tb - n_fall - n_irr - n_sri - n_ca - n_plog - n_cheb
     if n_elem < 0:
         raise ValueError("type mix exceeds 100%")
     kinds = (["ELEM_REV"] * n_elem + ["ELEM_IRR"] * n_irr + ["THREEBODY"] * n_tb
-             + ["LINDEMANN"] * n_lind + ["TROE"] * n_troe)
+             + ["LINDEMANN"] * n_lind + ["TROE"] * n_troe + ["SRI"] * n_sri
+             + ["CA_" + FALLOFF_TYPES[t % 3] for t in range(n_ca)]
+             + ["PLOG"] * n_plog + ["CHEB"] * n_cheb)
     kinds = [kinds[t] for t in rng.permutation(nr)]
     bath_slots = set(rng.choice(nr, size=min(bath_reactions, nr), replace=False).tolist()) \
         if bath_reactions else set()
@@ -393,7 +428,7 @@ def make_mechanism(ns: int, nr: int, seed: int, mix: MixSpec = MixSpec(), zipf: 
     for i, kind in enumerate(kinds):
         with_bath = i in bath_slots
         for _attempt in range(3000):
-            pressure_dep = kind in ("THREEBODY", "LINDEMANN", "TROE")
+            pressure_dep = kind == "THREEBODY" or kind.replace("CA_", "") in FALLOFF_TYPES
             size = int(rng.choice([1, 2, 3], p=[0.15, 0.70, 0.15] if not pressure_dep
                                   else [0.3, 0.7, 0.0]))
             if with_bath:
@@ -425,18 +460,41 @@ def make_mechanism(ns: int, nr: int, seed: int, mix: MixSpec = MixSpec(), zipf: 
         lnA, b, th = _draw_arrhenius(rng)
         rx = Reaction(type="ELEM", rev=(kind != "ELEM_IRR"), reac=reac, prod=prod,
                       lnA=lnA, b=b, theta=th)
-        if kind in ("THREEBODY", "LINDEMANN", "TROE"):
+        if kind.startswith("CA_"):
+            kind = kind[3:]
+            rx.chemact = True
+        if kind in ("THREEBODY",) + FALLOFF_TYPES:
             rx.type = kind
             m = int(rng.integers(1, max_eff + 1))
             chosen = rng.choice(colliders, size=min(m, len(colliders)), replace=False)
             rx.eff = [(int(s), float(rng.uniform(0.5, 5.0))) for s in sorted(chosen)]
             if bath_efficiency:
                 rx.eff.append((bath, float(rng.uniform(0.5, 5.0))))
-        if kind in ("LINDEMANN", "TROE"):
+        if kind in FALLOFF_TYPES:
             rx.low = _draw_arrhenius(rng)
         if kind == "TROE":
             rx.troe = (float(rng.uniform(0.0, 1.0)), float(rng.uniform(100.0, 5000.0)),
                        float(rng.uniform(100.0, 5000.0)), float(rng.uniform(100.0, 5000.0)))
+        if kind == "SRI":
+            rx.sri = (float(rng.uniform(0.1, 2.0)), float(rng.uniform(100.0, 2000.0)),
+                      float(rng.uniform(100.0, 2000.0)), float(rng.uniform(0.5, 2.0)),
+                      float(rng.uniform(-0.5, 0.5)))
+        if kind == "PLOG":
+            rx.type = "PLOG"
+            m_p = int(rng.integers(2, 6))
+            lp = np.sort(rng.choice(np.linspace(-1.0, 2.5, 36), size=m_p, replace=False))
+            rx.plog = [(float(ATM * 10.0 ** v), float(lnA + rng.uniform(-2.0, 2.0)),
+                        float(b + rng.uniform(-0.5, 0.5)),
+                        float(max(0.0, th + rng.uniform(-2000.0, 2000.0)))) for v in lp]
+            rx.lnA, rx.b, rx.theta = 0.0, 0.0, 0.0
+        if kind == "CHEB":
+            rx.type = "CHEB"
+            nt, npr = int(rng.integers(3, 7)), int(rng.integers(2, 5))
+            coef = [[float(rng.normal(0.0, 0.3)) / (1 + t + q) for q in range(npr)] for t in range(nt)]
+            coef[0][0] = float(rng.uniform(8.0, 13.0))
+            coef[1][0] = float(rng.uniform(-3.0, 0.0))
+            rx.cheb = ((290.0, 3000.0, 0.01 * ATM, 100.0 * ATM), coef)
+            rx.lnA, rx.b, rx.theta = 0.0, 0.0, 0.0
         reactions.append(rx)
     return Mechanism(names=names, W=W, comp=comp, tmid=tmid, a_lo=a_lo, a_hi=a_hi,
                      reactions=reactions)
@@ -478,6 +536,18 @@ def dumps(m: Mechanism) -> str:
             tok += ["LOW"] + [_g(v) for v in r.low]
         if r.troe is not None:
             tok += ["TROE"] + [_g(v) for v in r.troe]
+        if r.sri is not None:
+            tok += ["SRI"] + [_g(v) for v in r.sri]
+        if r.chemact:
+            tok.append("CHEMACT")
+        if r.plog is not None:
+            tok += ["PLOG", str(len(r.plog))]
+            for pt in r.plog:
+                tok += [_g(v) for v in pt]
+        if r.cheb is not None:
+            rng_, coef = r.cheb
+            tok += ["CHEB", str(len(coef)), str(len(coef[0]))] + [_g(v) for v in rng_]
+            tok += [_g(v) for row in coef for v in row]
         if r.eff:
             tok += ["EFF", str(len(r.eff))]
             for s, a in r.eff:
@@ -531,12 +601,22 @@ def loads(text: str) -> Mechanism:
         prod = [(int(nxt()), int(nxt())) for _ in range(int(nxt()))]
         lnA, b, th = float(nxt()), float(nxt()), float(nxt())
         r = Reaction(typ, rev, reac, prod, lnA, b, th)
-        while tok[p] in ("LOW", "TROE", "EFF"):
+        while tok[p] in ("LOW", "TROE", "SRI", "CHEMACT", "PLOG", "CHEB", "EFF"):
             kw = nxt()
             if kw == "LOW":
                 r.low = (float(nxt()), float(nxt()), float(nxt()))
             elif kw == "TROE":
                 r.troe = (float(nxt()), float(nxt()), float(nxt()), float(nxt()))
+            elif kw == "SRI":
+                r.sri = tuple(float(nxt()) for _ in range(5))
+            elif kw == "CHEMACT":
+                r.chemact = True
+            elif kw == "PLOG":
+                r.plog = [tuple(float(nxt()) for _ in range(4)) for _ in range(int(nxt()))]
+            elif kw == "CHEB":
+                nt, npr = int(nxt()), int(nxt())
+                rng_ = tuple(float(nxt()) for _ in range(4))
+                r.cheb = (rng_, [[float(nxt()) for _ in range(npr)] for _ in range(nt)])
             else:
                 r.eff = [(int(nxt()), float(nxt())) for _ in range(int(nxt()))]
         rxs.append(r)

@@ -49,3 +49,23 @@ def tiny_file(seed, directory, ns=7, nr=10, **kw):
 # mechanism with and without bath-gas participation.
 TINY_MIX = synth.MixSpec(third_body=0.1, falloff=0.2, irreversible=0.2)
 TINY_SEEDS = (3, 6, 8, 11, 13)
+
+
+# Tiny random mechanisms with every reaction type the library supports (SRI
+# falloff, chemically activated, P-Log and Chebyshev besides the default mix);
+# these seeds give a drawable 12-species/24-reaction mechanism with and
+# without bath-gas participation.
+TYPES_MIX = synth.MixSpec(third_body=0.1, falloff=0.1, irreversible=0.1, sri=0.1, chem_act=0.15,
+                          plog=0.15, cheb=0.1)
+TYPES_SEEDS = (3, 5, 6, 13, 14)
+
+
+def types_file(seed, directory, bath=False):
+    key = ("types", seed, bath, str(directory))
+    if key not in _CACHE:
+        kw = dict(bath_reactions=1, bath_efficiency=True) if bath else {}
+        m = synth.make_mechanism(12, 24, seed, mix=TYPES_MIX, zipf=0.5, **kw)
+        path = os.path.join(str(directory), f"types_{seed}_{int(bath)}.pjm")
+        synth.write_mechanism(m, path)
+        _CACHE[key] = (m, path)
+    return _CACHE[key]

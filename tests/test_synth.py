@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
+ATM = 101325.0
 from paper_1809_01029_amd import synth
 from conftest import TINY_SEEDS, tiny_file, workload_file
 
@@ -26,7 +27,8 @@ def test_workload_mechanism_valid(name, mech_dir):
     assert m.n_species == w.ns and m.n_reactions == w.nr
     bath = m.n_species - 1
     seen = set()
-    counts = {"ELEM_REV": 0, "ELEM_IRR": 0, "THREEBODY": 0, "LINDEMANN": 0, "TROE": 0}
+    counts = {"ELEM_REV": 0, "ELEM_IRR": 0, "THREEBODY": 0, "LINDEMANN": 0, "TROE": 0, "SRI": 0,
+              "PLOG": 0, "CHEB": 0, "CHEMACT": 0}
     for r in m.reactions:
         lhs = sum(nu * m.comp[s] for s, nu in r.reac)
         rhs = sum(nu * m.comp[s] for s, nu in r.prod)
@@ -38,9 +40,21 @@ def test_workload_mechanism_valid(name, mech_dir):
         assert key not in seen and (key[1], key[0]) not in seen
         seen.add(key)
         kind = r.type if r.type != "ELEM" else ("ELEM_REV" if r.rev else "ELEM_IRR")
-        counts[kind] += 1
-        assert 8 * np.log(10) <= r.lnA <= 16 * np.log(10) and -2 <= r.b <= 3 and 0 <= r.theta <= 3e4
-        if r.type in ("THREEBODY", "LINDEMANN", "TROE"):
+        counts["CHEMACT" if r.chemact else kind] += 1
+        if r.type in ("PLOG", "CHEB"):
+            # the main Arrhenius expression is a unit factor on the tabulated rate
+            assert (r.lnA, r.b, r.theta) == (0.0, 0.0, 0.0) and not r.eff
+        else:
+            assert 8 * np.log(10) <= r.lnA <= 16 * np.log(10) and -2 <= r.b <= 3 and 0 <= r.theta <= 3e4
+        if r.type == "PLOG":
+            ps = [pt[0] for pt in r.plog]
+            assert 2 <= len(ps) <= 5 and all(a < b for a, b in zip(ps, ps[1:]))
+            assert 0.1 * ATM * 0.999 <= ps[0] and ps[-1] <= 10 ** 2.5 * ATM * 1.001
+        if r.type == "CHEB":
+            (tmin, tmax, pmin, pmax), coef = r.cheb
+            assert tmin < 600 and tmax > 2200 and pmin < ATM and pmax > 60 * ATM
+            assert 3 <= len(coef) <= 6 and 2 <= len(coef[0]) <= 4
+        if r.type in ("THREEBODY",) + synth.FALLOFF_TYPES:
             assert 1 <= len(r.eff) <= 6 and all(0.5 <= a <= 5 for _, a in r.eff)
             assert all(s != bath for s, _ in r.eff)
         if r.type == "TROE":
@@ -51,6 +65,8 @@ def test_workload_mechanism_valid(name, mech_dir):
     assert counts["LINDEMANN"] + counts["TROE"] == round(w.mix.falloff * nr)
     assert abs(counts["LINDEMANN"] - counts["TROE"]) <= 1
     assert counts["ELEM_IRR"] == round(w.mix.irreversible * nr)
+    assert counts["SRI"] == round(w.mix.sri * nr) and counts["CHEMACT"] == round(w.mix.chem_act * nr)
+    assert counts["PLOG"] == round(w.mix.plog * nr) and counts["CHEB"] == round(w.mix.cheb * nr)
     # the bath gas takes part in exactly the requested number of reactions
     nb = sum(1 for r in m.reactions if bath in [s for s, _ in r.reac + r.prod])
     assert nb == w.bath_reactions
