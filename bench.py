@@ -37,7 +37,8 @@ def log(*a):
 
 # Sources that decide the kernel's memory traffic; a traffic figure measured
 # with other versions of them is not reported.
-KERNEL_SOURCES = ["paper_1809_01029_amd/csrc/kernels.hip", "paper_1809_01029_amd/csrc/internal.h",
+KERNEL_SOURCES = ["paper_1809_01029_amd/csrc/kernel_body.h", "paper_1809_01029_amd/csrc/kernels.hip",
+                  "paper_1809_01029_amd/csrc/kernels_ext.hip", "paper_1809_01029_amd/csrc/internal.h",
                   "paper_1809_01029_amd/csrc/mech.cpp", "paper_1809_01029_amd/csrc/api.cpp"]
 
 
@@ -334,6 +335,31 @@ def main():
             mv.close()
         if args.workload == "ns111" and not args.n_states:
             variants["ragged_13_53_111"] = ragged_batch(api, synth, torch, tmp, args, stream, timeit)
+            # the same size with every reaction type (SRI, chemically activated,
+            # P-Log, Chebyshev besides the default mix), on its own states
+            wx = synth.WORKLOADS["ns111x"]
+            mx = synth.workload_mechanism("ns111x")
+            px = os.path.join(tmp, "ns111x.pjm")
+            synth.write_mechanism(mx, px)
+            stx = synth.make_states(mx, wx.n_states, wx.state_seed, T_range=wx.T_range, P_range_atm=wx.P_range_atm)
+            x5, p5 = synth.pack_state(stx, args.form, args.layout)
+            del stx
+            mechx = api.load_mechanism(px)
+            xs5, ps5 = torch.from_numpy(x5).cuda(), torch.from_numpy(p5).cuda()
+            jac5 = torch.empty((mechx.nnz, wx.n_states) if args.layout == "F" else (wx.n_states, mechx.nnz),
+                               dtype=torch.float64, device="cuda")
+            d5 = torch.empty_like(xs5)
+            if not args.no_autotune:
+                api.autotune(mechx, xs5, ps5, args.form, args.layout, mode="sparse", reps=1, stream=stream)
+            t = timeit(lambda: api.eval_jacobian_sparse(mechx, xs5, ps5, args.form, args.layout, out=jac5,
+                                                        dstate=d5, stream=stream), k=3)
+            ts = timeit(lambda: api.eval_source(mechx, xs5, ps5, args.form, args.layout, out=d5, stream=stream))
+            variants["all_reaction_types_ns111x"] = {
+                "ms": round(t, 4), "states_per_s": wx.n_states / (t * 1e-3), "nnz": mechx.nnz,
+                "launch_shape": list(mechx.launch_shape(1)), "source_only_ms": round(ts, 4),
+                "vs_ns111": round(t / ms, 3)}
+            del xs5, ps5, jac5, d5
+            mechx.close()
         log(f"variants: {json.dumps(variants)}")
 
     cpu = None

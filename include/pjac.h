@@ -73,14 +73,18 @@ typedef enum {
 /*
  * Load a mechanism description (the text format written by the package's
  * synthetic generator: species with NASA 7-coefficient thermodynamics,
- * reactions of type elementary, third-body, Lindemann or Troe falloff;
- * Sec. 2.2 "all modern reaction types", restricted to these four), check that
+ * reactions of type elementary, third-body, falloff with the Lindemann, Troe
+ * or SRI form, chemically activated with the same forms, pressure-dependent
+ * Arrhenius (P-Log) and Chebyshev; the reaction types Sec. 2.2 names as
+ * supported), check that
  * every reaction conserves elements, derive the device tables and the CSR
  * pattern of the Jacobian (Sec. 3.4), and upload them to the current HIP
  * device.  Synchronous.  On success *out receives a handle; on failure *out is
  * NULL and the status says why.
  * Limits (PJ_E_UNSUPPORTED beyond them): at most 3 distinct species per
- * reaction side, coefficients 1..2, at most 65534 Jacobian non-zeros, and the
+ * reaction side, coefficients 1..2, at most 8 third bodies with an efficiency
+ * other than one per reaction, at most 64 pressures per P-Log reaction and
+ * 16 x 16 Chebyshev coefficients, at most 65534 Jacobian non-zeros, and the
  * per-state working set must fit the device's LDS per workgroup.
  */
 pj_status pj_mech_load(const char* desc_path, pj_mech** out);
@@ -174,8 +178,9 @@ pj_status pj_eval_jacobian_dense(const pj_mech* mech, pj_form form, pj_layout la
  * product of the transposed Jacobian with a vector, J^T v, and, summed over
  * the batch, the derivatives of v . dPhi/dt with respect to every reaction's
  * Arrhenius parameters ln A, b and Ea/R (Sec. 2.2's rate constants; for
- * falloff reactions those of the high-pressure limit, the low-pressure limit
- * held fixed).  The Jacobian is formed on chip as for
+ * falloff and chemically activated reactions those of the high-pressure
+ * limit, the low-pressure limit held fixed; for P-Log and Chebyshev reactions
+ * those of the Arrhenius factor that multiplies the tabulated rate).  The Jacobian is formed on chip as for
  * pj_eval_jacobian_sparse and never written out.
  * d_v: N*n doubles, same layout as d_state; d_jtv: N*n doubles, same layout;
  * d_grad_or_null: NULL, or 3*Nr doubles [ln A (Nr), b (Nr), Ea/R (Nr)] in the
@@ -190,7 +195,8 @@ pj_status pj_eval_adjoint(const pj_mech* mech, pj_form form, pj_layout layout, i
 
 /*
  * Replace / read the Arrhenius parameters (ln A, b, Ea/R of k_f; of k_inf
- * for falloff reactions) of all Nr reactions, host arrays in description
+ * for falloff and chemically activated reactions; of the factor on the
+ * tabulated rate for P-Log and Chebyshev) of all Nr reactions, host arrays in description
  * order; a NULL array is left unchanged / not written.  Setting updates the
  * uploaded tables synchronously (the caller orders it against work in
  * flight that uses the mechanism).

@@ -1,6 +1,7 @@
 """Build the HIP library (libpjac.so, gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -32,14 +33,16 @@ def _run(cmd):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in ("mech.cpp", "api.cpp", "batch.cpp"):
+    jobs = []
+    for src in ("mech.cpp", "api.cpp", "batch.cpp", "kernels.hip", "kernels_ext.hip"):
         o = os.path.join(BUILD, src + ".o")
-        _run([HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", o])
-        objs.append(o)
-    o = os.path.join(BUILD, "kernels.hip.o")
-    _run([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", o])
-    objs.append(o)
+        dev = DEVICE if src.endswith(".hip") else []
+        jobs.append(([HIPCC] + COMMON + dev + ["-c", os.path.join(CSRC, src), "-o", o], o))
+    # the translation units compile in parallel (the two kernel sets dominate)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        for f in [ex.submit(_run, cmd) for cmd, _ in jobs]:
+            f.result()
+    objs = [o for _, o in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC] + DEVICE + ["-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)

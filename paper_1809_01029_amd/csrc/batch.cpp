@@ -179,8 +179,10 @@ pj_status enqueue(pj_batch* b, int mode, pj_form form, pj_layout layout, int S, 
     if (b->table_total == 0) return PJ_OK;
     int64_t gr_off = -1;
     const int64_t lds = batch_lds(b, mode, S, W, &gr_off);
+    int ext = 0;   // the further reaction types' kernels if any segment needs them
+    for (auto& sg : b->segs) ext |= sg.mech->m.dm.ext;
     hipError_t e = pj::launch_batch(mode, form, layout, S, W, lds, b->d_segs, b->table_nseg, b->table_total,
-                                    gr_off, st);
+                                    gr_off, ext, st);
     if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
     return PJ_OK;
 }

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -14,47 +15,71 @@ namespace pj {
 
 constexpr double RU = 8314.462618;       // J/(kmol K)
 constexpr double PREF = 101325.0;        // Pa
+constexpr double LN10 = 2.302585092994045684;
 constexpr int MAXSIDE = 3;               // species per reaction side
 constexpr int NSLOT = 2 * MAXSIDE;       // reactant slots 0..2, product slots 3..5
 constexpr uint16_t NOSLOT = 0xFFFF;
 constexpr uint16_t DMAP_SKIP = 0xFFFE;   // dense map: entry written elsewhere
 
-enum RxnKind : int { K_ELEM = 0, K_THREEBODY = 1, K_LINDEMANN = 2, K_TROE = 3 };
+enum RxnKind : int { K_ELEM = 0, K_THREEBODY = 1, K_LINDEMANN = 2, K_TROE = 3, K_SRI = 4,
+                     K_PLOG = 5, K_CHEB = 6 };
+__host__ __device__ inline bool kind_falloff(int k) { return k >= K_LINDEMANN && k <= K_SRI; }
+__host__ __device__ inline bool kind_table(int k) { return k == K_PLOG || k == K_CHEB; }
+constexpr int MAX_PLOG = 64;          // pressures of one P-Log reaction
+constexpr int MAX_CHEB = 16;          // Chebyshev coefficients per direction
 
 // Bits of the per-reaction info word.
 //   bits 0..23 : coefficient of slot a (a < 6) in bits 4a..4a+3 (0 = empty slot)
-//   bits 24..25: kind (RxnKind)
-//   bit  26    : reversible
-//   bit  27    : the rate depends on the bath-gas concentration
-//   bit  28    : the bath gas has a non-zero coefficient
-constexpr uint32_t INFO_REV = 1u << 26;
-constexpr uint32_t INFO_BATH = 1u << 27;
-constexpr uint32_t INFO_BATHROW = 1u << 28;
+//   bits 24..26: kind (RxnKind)
+//   bit  27    : reversible
+//   bit  28    : the rate depends on the bath-gas concentration
+//   bit  29    : the bath gas has a non-zero coefficient
+//   bit  30    : chemically activated (falloff kinds)
+constexpr uint32_t INFO_REV = 1u << 27;
+constexpr uint32_t INFO_BATH = 1u << 28;
+constexpr uint32_t INFO_BATHROW = 1u << 29;
+constexpr uint32_t INFO_CHEMACT = 1u << 30;
+constexpr uint32_t CHUNK_TAB = 1u << 12, CHUNK_SRI = 1u << 13, CHUNK_CHEMACT = 1u << 14;
 __host__ __device__ inline int info_nu(uint32_t w, int a) { return (w >> (4 * a)) & 0xF; }
-__host__ __device__ inline int info_kind(uint32_t w) { return (w >> 24) & 0x3; }
+__host__ __device__ inline int info_kind(uint32_t w) { return (w >> 24) & 0x7; }
 
 // Per-reaction device records, in the kernel order (sorted by kind) and
 // padded to a multiple of 64 reactions.  Each record is 16-byte aligned and
 // read with 16-byte vector loads.
 struct alignas(16) RxnRec {          // 80 B
     uint32_t info;                   // see INFO_* above
-    uint32_t eff;                    // index of this reaction's EffRec (third bodies)
+    uint32_t eff;                    // index of this reaction's EffRec (third bodies; 0 = none)
     uint32_t neff;                   // number of third bodies with efficiency != 1
     uint32_t chunk;                  // slot positions used in this reaction's 64-reaction
                                      // chunk (bits 0..5), any reversible (bit 6), the
-                                     // largest neff in the chunk (bits 8..11)
+                                     // largest neff in the chunk (bits 8..11), any rate
+                                     // tabulated in pressure (bit 12), any SRI (bit 13),
+                                     // any chemically activated (bit 14)
     uint16_t sp[6];                  // species of slot a (Ns = empty slot)
-    uint16_t pad1[2];
-    double lnA, b, theta;            // Arrhenius (k_inf for falloff)
+    uint16_t tab;                    // P-Log / Chebyshev: index of the TabRec
+    uint16_t pad1;
+    double lnA, b, theta;            // Arrhenius (k_inf for falloff; a factor on a
+                                     // rate tabulated in pressure)
     double dnu;                      // sum of net coefficients
     double domega;                   // sum_{k<Ns} nu_ki (1 - W_k/W_Ns)
     double bam1;                     // efficiency - 1 of the bath gas (0 if none)
 };
 struct alignas(16) FallRec {         // 64 B, falloff reactions
     double lnA0, b0, theta0;         // low-pressure limit
-    double alpha, inv_t3, inv_t1, t2;// Troe: alpha, 1/T***, 1/T*, T**
-    double pad;
+    double p[5];                     // Troe: alpha, 1/T***, 1/T*, T**
+                                     // SRI:  a, b, 1/c, log10 d, e
 };
+struct alignas(16) TabRec {          // 48 B, rate constants tabulated in pressure
+    int32_t off;                     // first double of the reaction's table
+    int32_t n;                       // P-Log: pressures; Chebyshev: coefficients in T
+    int32_t np;                      // Chebyshev: coefficients in P
+    int32_t pad;
+    double ta, tb;                   // Chebyshev: reduced temperature ta / T + tb
+    double pa, pb;                   // Chebyshev: reduced pressure pa ln P + pb
+};
+// Table entries: P-Log, per pressure (ascending) {P, ln P, ln A, b, Ea/R, 0};
+// Chebyshev, ln 10 * alpha_tp at t * np + p.
+constexpr int PLOG_STRIDE = 6;
 struct alignas(16) JacRec {          // 96 B, Jacobian scatter slots (NOSLOT = none)
     uint16_t rowbase[6];             // CSR start of the row of slot a's species
     uint16_t pad0[2];
@@ -70,7 +95,7 @@ struct alignas(16) EffRec {          // 176 B, third-body reactions; record 0 is
                                      // entry e) at [a][e]
 };
 static_assert(sizeof(RxnRec) == 80 && sizeof(FallRec) == 64 && sizeof(JacRec) == 96 &&
-              sizeof(EffRec) == 176, "record sizes");
+              sizeof(EffRec) == 176 && sizeof(TabRec) == 48, "record sizes");
 
 // Thermodynamic coefficients of one species and one temperature range.
 constexpr int TH_N = 18;
@@ -94,6 +119,8 @@ struct DevMech {
     const FallRec* fall;      // [nr_pad]
     const JacRec* jrec;       // [nr_pad]
     const EffRec* effrec;     // [1 + reactions with third bodies]
+    const TabRec* tab;        // [reactions tabulated in pressure, at least 1]
+    const double* tabd;       // their tables
 
     // pattern
     const int32_t* row_ptr;   // [N + 1]
@@ -102,6 +129,7 @@ struct DevMech {
     const uint16_t* dmap_rm;  // [N*N] CSR slot of (i, j) at i*N + j, NOSLOT if none
     const uint16_t* dmap_cm;  // [N*N] the same at i + N*j; DMAP_SKIP for rows 0 and 1
     int approx;               // approximate Jacobian (bath gas held against n_j)
+    int ext;                  // holds SRI, chemically activated, P-Log or Chebyshev reactions
     int lsearch;              // find CSR slots by a run-time row search
     const int32_t* orig;      // [nr] description index of each kernel-order reaction
     const uint16_t* col_idx;  // [nnz]
@@ -121,7 +149,13 @@ struct Mechanism {
         double lnA, b, theta;
         double lnA0 = 0, b0 = 0, theta0 = 0;
         double alpha = 0, T3 = 1, T1 = 1, T2 = 0;
+        double sri[5] = {0, 0, 0, 0, 0};   // a, b, c, d, e
+        bool chemact = false;
         std::vector<std::pair<int, double>> eff;
+        std::vector<std::array<double, 4>> plog;   // (P, ln A, b, Ea/R), ascending P
+        int cheb_nt = 0, cheb_np = 0;
+        double cheb_T[2] = {0, 0}, cheb_P[2] = {0, 0};
+        std::vector<double> cheb;                  // [nt][np]
     };
     std::vector<Rxn> rx;
 
@@ -181,9 +215,18 @@ hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int6
 hipError_t zero_async(double* p, int64_t n, hipStream_t stream);
 // batch kernel (modes source, sparse, adjoint; S = 1, 2, 4)
 // gr_off: LDS offset (doubles) of the adjoint's per-segment parameter sums, or -1
+// ext: some segment's mechanism holds the further reaction types
 hipError_t launch_batch(int mode, int form, int layout, int S, int waves, int64_t lds,
                         const BatchSeg* d_segs, int nseg, int64_t total_groups, int64_t gr_off,
-                        hipStream_t stream);
+                        int ext, hipStream_t stream);
+// kernels_ext.hip: the same launches for mechanisms with the further reaction types
+hipError_t launch_ext(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
+                      const double* state, const double* param, double* dstate, double* jac,
+                      const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,
+                      hipStream_t stream);
+hipError_t launch_batch_ext(int mode, int form, int layout, int S, int waves, int64_t lds,
+                            const BatchSeg* d_segs, int nseg, int64_t total_groups, int64_t gr_off,
+                            hipStream_t stream);
 // api.cpp
 void choose_launch(Mechanism& m);
 

@@ -93,6 +93,9 @@ pj_status parse_description(const char* path, Mechanism& m, std::string& err) {
         else if (kind == "THREEBODY") r.kind = K_THREEBODY;
         else if (kind == "LINDEMANN") r.kind = K_LINDEMANN;
         else if (kind == "TROE") r.kind = K_TROE;
+        else if (kind == "SRI") r.kind = K_SRI;
+        else if (kind == "PLOG") r.kind = K_PLOG;
+        else if (kind == "CHEB") r.kind = K_CHEB;
         else { err = "unknown reaction type " + kind; return PJ_E_PARSE; }
         r.rev = rev != 0;
         for (int side = 0; side < 2; ++side) {
@@ -110,8 +113,11 @@ pj_status parse_description(const char* path, Mechanism& m, std::string& err) {
             }
         }
         if (!tk.real(r.lnA) || !tk.real(r.b) || !tk.real(r.theta)) { err = "bad Arrhenius in reaction " + std::to_string(i); return PJ_E_PARSE; }
-        bool has_low = false, has_troe = false;
-        while (tk.more() && (tk.peek() == "LOW" || tk.peek() == "TROE" || tk.peek() == "EFF")) {
+        bool has_low = false, has_troe = false, has_sri = false;
+        auto keyword = [&](const std::string& k) {
+            return k == "LOW" || k == "TROE" || k == "SRI" || k == "CHEMACT" || k == "PLOG" || k == "CHEB" || k == "EFF";
+        };
+        while (tk.more() && keyword(tk.peek())) {
             std::string kw;
             tk.word(kw);
             if (kw == "LOW") {
@@ -120,6 +126,33 @@ pj_status parse_description(const char* path, Mechanism& m, std::string& err) {
             } else if (kw == "TROE") {
                 if (!tk.real(r.alpha) || !tk.real(r.T3) || !tk.real(r.T1) || !tk.real(r.T2)) { err = "bad TROE"; return PJ_E_PARSE; }
                 has_troe = true;
+            } else if (kw == "SRI") {
+                for (double& x : r.sri) if (!tk.real(x)) { err = "bad SRI"; return PJ_E_PARSE; }
+                has_sri = true;
+            } else if (kw == "CHEMACT") {
+                r.chemact = true;
+            } else if (kw == "PLOG") {
+                if (!tk.integer(n) || n < 1) { err = "bad PLOG count"; return PJ_E_PARSE; }
+                if (n > MAX_PLOG) { err = "more than " + std::to_string(MAX_PLOG) + " PLOG pressures"; return PJ_E_UNSUPPORTED; }
+                for (long a = 0; a < n; ++a) {
+                    std::array<double, 4> pt;
+                    for (double& x : pt) if (!tk.real(x)) { err = "bad PLOG entry"; return PJ_E_PARSE; }
+                    if (!(pt[0] > 0) || (a && !(pt[0] > r.plog.back()[0]))) { err = "PLOG pressures must be positive and ascending"; return PJ_E_PARSE; }
+                    r.plog.push_back(pt);
+                }
+            } else if (kw == "CHEB") {
+                long nt, np;
+                if (!tk.integer(nt) || !tk.integer(np) || nt < 1 || np < 1) { err = "bad CHEB size"; return PJ_E_PARSE; }
+                if (nt > MAX_CHEB || np > MAX_CHEB) {
+                    err = "more than " + std::to_string(MAX_CHEB) + " CHEB coefficients in one direction";
+                    return PJ_E_UNSUPPORTED;
+                }
+                r.cheb_nt = (int)nt;
+                r.cheb_np = (int)np;
+                if (!tk.real(r.cheb_T[0]) || !tk.real(r.cheb_T[1]) || !tk.real(r.cheb_P[0]) || !tk.real(r.cheb_P[1])) { err = "bad CHEB range"; return PJ_E_PARSE; }
+                if (!(r.cheb_T[0] > 0 && r.cheb_T[1] > r.cheb_T[0] && r.cheb_P[0] > 0 && r.cheb_P[1] > r.cheb_P[0])) { err = "CHEB ranges must be positive and ascending"; return PJ_E_PARSE; }
+                r.cheb.resize((size_t)nt * np);
+                for (double& x : r.cheb) if (!tk.real(x)) { err = "bad CHEB coefficient"; return PJ_E_PARSE; }
             } else {
                 if (!tk.integer(n) || n < 0) { err = "bad EFF"; return PJ_E_PARSE; }
                 for (long a = 0; a < n; ++a) {
@@ -130,10 +163,15 @@ pj_status parse_description(const char* path, Mechanism& m, std::string& err) {
                 }
             }
         }
-        if ((r.kind == K_LINDEMANN || r.kind == K_TROE) != has_low) { err = "falloff reaction without LOW (or LOW on another type)"; return PJ_E_PARSE; }
+        if (kind_falloff(r.kind) != has_low) { err = "falloff reaction without LOW (or LOW on another type)"; return PJ_E_PARSE; }
         if ((r.kind == K_TROE) != has_troe) { err = "TROE parameters do not match the reaction type"; return PJ_E_PARSE; }
+        if ((r.kind == K_SRI) != has_sri) { err = "SRI parameters do not match the reaction type"; return PJ_E_PARSE; }
         if (r.kind == K_TROE && (!(r.T3 > 0) || !(r.T1 > 0))) { err = "Troe T*** and T* must be positive"; return PJ_E_PARSE; }
-        if (r.kind == K_ELEM && !r.eff.empty()) { err = "efficiencies on an elementary reaction"; return PJ_E_PARSE; }
+        if (r.kind == K_SRI && (!(r.sri[0] >= 0) || !(r.sri[2] > 0) || !(r.sri[3] > 0))) { err = "SRI needs a >= 0, c > 0 and d > 0"; return PJ_E_PARSE; }
+        if (r.chemact && !kind_falloff(r.kind)) { err = "CHEMACT on a reaction without a falloff form"; return PJ_E_PARSE; }
+        if ((r.kind == K_PLOG) != !r.plog.empty()) { err = "PLOG table does not match the reaction type"; return PJ_E_PARSE; }
+        if ((r.kind == K_CHEB) != !r.cheb.empty()) { err = "CHEB table does not match the reaction type"; return PJ_E_PARSE; }
+        if ((r.kind == K_ELEM || kind_table(r.kind)) && !r.eff.empty()) { err = "efficiencies on a reaction without a third body"; return PJ_E_PARSE; }
     }
     if (!tk.expect("END") || tk.more()) { err = "missing END"; return PJ_E_PARSE; }
     return PJ_OK;
@@ -248,7 +286,12 @@ pj_status build_mechanism(const char* path, Mechanism& m, std::string& err) {
     for (int i = 0; i < m.nr; ++i) m.order[i] = i;
     auto key = [&](int i) {
         const auto& r = m.rx[i];
-        int cls = r.kind == K_ELEM ? (r.rev ? 0 : 1) : r.kind + 1;
+        // elementary (reversible, irreversible), third-body, falloff
+        // (Lindemann, Troe, SRI), chemically activated (same forms), P-Log,
+        // Chebyshev
+        int cls = r.kind == K_ELEM ? (r.rev ? 0 : 1)
+                  : kind_falloff(r.kind) ? r.kind + 1 + (r.chemact ? 3 : 0)
+                  : r.kind == K_THREEBODY ? 2 : r.kind + 4;
         return cls * 100 + (int)r.reac.size() * 10 + (int)r.prod.size();
     };
     std::stable_sort(m.order.begin(), m.order.end(), [&](int a, int b) { return key(a) < key(b); });
@@ -299,6 +342,8 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     };
     empty_eff(effrec[0]);
     std::vector<char> dense_row(ns, 0);
+    std::vector<TabRec> tabs;
+    std::vector<double> tabd;
     // Slot positions.  The lanes of a wave handle 64 consecutive reactions
     // and scatter slot a of every reaction in the same instruction, so a
     // species that sits in the same slot of many of those reactions (a hub
@@ -386,16 +431,50 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
         R.lnA = r.lnA;
         R.b = r.b;
         R.theta = r.theta;
-        if (r.kind == K_LINDEMANN || r.kind == K_TROE) {
+        if (r.chemact) R.info |= INFO_CHEMACT;
+        if (kind_falloff(r.kind)) {
             fall[p].lnA0 = r.lnA0;
             fall[p].b0 = r.b0;
             fall[p].theta0 = r.theta0;
         }
         if (r.kind == K_TROE) {
-            fall[p].alpha = r.alpha;
-            fall[p].inv_t3 = 1.0 / r.T3;
-            fall[p].inv_t1 = 1.0 / r.T1;
-            fall[p].t2 = r.T2;
+            fall[p].p[0] = r.alpha;
+            fall[p].p[1] = 1.0 / r.T3;
+            fall[p].p[2] = 1.0 / r.T1;
+            fall[p].p[3] = r.T2;
+        }
+        if (r.kind == K_SRI) {
+            fall[p].p[0] = r.sri[0];
+            fall[p].p[1] = r.sri[1];
+            fall[p].p[2] = 1.0 / r.sri[2];
+            fall[p].p[3] = std::log10(r.sri[3]);
+            fall[p].p[4] = r.sri[4];
+        }
+        if (kind_table(r.kind)) {
+            if (tabs.size() >= 65535) { err = "more than 65535 reactions tabulated in pressure"; return PJ_E_UNSUPPORTED; }
+            TabRec tr{};
+            tr.off = (int32_t)tabd.size();
+            if (r.kind == K_PLOG) {
+                tr.n = (int32_t)r.plog.size();
+                for (const auto& pt : r.plog) {
+                    const double row[PLOG_STRIDE] = {pt[0], std::log(pt[0]), pt[1], pt[2], pt[3], 0.0};
+                    tabd.insert(tabd.end(), row, row + PLOG_STRIDE);
+                }
+            } else {
+                // Tr = (2/T - 1/Tmin - 1/Tmax) / (1/Tmax - 1/Tmin) = ta / T + tb,
+                // Pr = (2 ln P - ln Pmin - ln Pmax) / (ln Pmax - ln Pmin) = pa ln P + pb
+                const double iT0 = 1.0 / r.cheb_T[0], iT1 = 1.0 / r.cheb_T[1];
+                const double l0 = std::log(r.cheb_P[0]), l1 = std::log(r.cheb_P[1]);
+                tr.n = r.cheb_nt;
+                tr.np = r.cheb_np;
+                tr.ta = 2.0 / (iT1 - iT0);
+                tr.tb = -(iT0 + iT1) / (iT1 - iT0);
+                tr.pa = 2.0 / (l1 - l0);
+                tr.pb = -(l0 + l1) / (l1 - l0);
+                for (double a : r.cheb) tabd.push_back(LN10 * a);
+            }
+            R.tab = (uint16_t)tabs.size();
+            tabs.push_back(tr);
         }
         // rows: species of the reaction other than the bath gas
         JacRec& Jr = jrec[p];
@@ -411,7 +490,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
                 Jr.slot[a * NSLOT + b] = (uint16_t)sl;
             }
         }
-        if (r.kind != K_ELEM) {
+        if (r.kind == K_THREEBODY || kind_falloff(r.kind)) {
             EffRec E;
             empty_eff(E);
             int ne = 0;
@@ -434,13 +513,18 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
         }
     }
     // per 64-reaction chunk: which slot positions any of its reactions uses
-    // (bits 0..5), whether any is reversible (bit 6), and the largest number of
-    // third bodies of its reactions (bits 8..11); copied into every record
+    // (bits 0..5), whether any is reversible (bit 6), the largest number of
+    // third bodies of its reactions (bits 8..11), and which of the further
+    // reaction types occur in it (bits 12..14); copied into every record
     std::vector<uint32_t> chunk((size_t)nr_pad / 64, 0);
     for (int p = 0; p < nr; ++p) {
         uint32_t& cm = chunk[p / 64];
         for (int a = 0; a < NSLOT; ++a) if (NUA[p][a]) cm |= 1u << a;
         if (rec[p].info & INFO_REV) cm |= 1u << 6;
+        const int kd = info_kind(rec[p].info);
+        if (kind_table(kd)) cm |= CHUNK_TAB;
+        if (kd == K_SRI) cm |= CHUNK_SRI;
+        if (rec[p].info & INFO_CHEMACT) cm |= CHUNK_CHEMACT;
         const uint32_t ne = std::max((cm >> 8) & 0xFu, rec[p].neff);
         cm = (cm & ~(0xFu << 8)) | (ne << 8);
     }
@@ -461,6 +545,8 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     }
     const int n_dense = (int)dense_rows.size();
     if (dense_rows.empty()) dense_rows.push_back(-1);
+    if (tabs.empty()) tabs.push_back(TabRec{});
+    if (tabd.empty()) tabd.push_back(0.0);
 
     // ---- one device buffer
     size_t total = 0;
@@ -470,6 +556,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     size_t o_rec = place(rec.size() * sizeof(RxnRec)), o_fall = place(fall.size() * sizeof(FallRec)),
            o_jrec = place(jrec.size() * sizeof(JacRec));
     size_t o_eff = place(effrec.size() * sizeof(EffRec));
+    size_t o_tab = place(tabs.size() * sizeof(TabRec)), o_tabd = place(tabd.size() * 8);
     size_t o_rowp = place(m.row_ptr.size() * 4), o_col = place(col16.size() * 2),
            o_dr = place(dense_rows.size() * 4);
     // dense maps: CSR slot of every (row, column), row-major and column-major
@@ -491,6 +578,8 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     put(o_fall, fall.data(), fall.size() * sizeof(FallRec));
     put(o_jrec, jrec.data(), jrec.size() * sizeof(JacRec));
     put(o_eff, effrec.data(), effrec.size() * sizeof(EffRec));
+    put(o_tab, tabs.data(), tabs.size() * sizeof(TabRec));
+    put(o_tabd, tabd.data(), tabd.size() * 8);
     put(o_rowp, m.row_ptr.data(), m.row_ptr.size() * 4);
     put(o_col, col16.data(), col16.size() * 2);
     put(o_dr, dense_rows.data(), dense_rows.size() * 4);
@@ -527,6 +616,8 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.fall = (const FallRec*)P(o_fall);
     dm.jrec = (const JacRec*)P(o_jrec);
     dm.effrec = (const EffRec*)P(o_eff);
+    dm.tab = (const TabRec*)P(o_tab);
+    dm.tabd = (const double*)P(o_tabd);
     dm.row_ptr = (const int32_t*)P(o_rowp);
     dm.col_idx = (const uint16_t*)P(o_col);
     dm.dense_rows = (const int32_t*)P(o_dr);
@@ -537,6 +628,9 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.dmap_cm = (const uint16_t*)P(o_dmcm);
     dm.approx = (m.opts & PJ_OPT_APPROX_JACOBIAN) ? 1 : 0;
     dm.lsearch = (m.opts & PJ_OPT_LINEAR_SEARCH) ? 1 : 0;
+    dm.ext = 0;
+    for (const auto& r : m.rx)
+        if (r.kind == K_SRI || r.chemact || kind_table(r.kind)) dm.ext = 1;
     m.h_rec = rec;
     m.off_rec = o_rec;
 

@@ -243,3 +243,63 @@ def test_column_order_arrays_and_options(api, mech_dir, tmp_path):
     assert lib.pj_mech_parse_ex(os.fsencode(path), 8, ctypes.byref(h)) == 1
     assert b"option" in lib.pj_last_error()
     assert lib.pj_mech_options(None) == -1
+
+
+@pytest.mark.parametrize("bath", [False, True])
+def test_pattern_matches_oracle_all_types(api, bath, mech_dir):
+    from conftest import TYPES_SEEDS, types_file
+    for seed in TYPES_SEEDS:
+        m, path = types_file(seed, mech_dir, bath=bath)
+        mech = api.Mechanism(path, upload=False)
+        np.testing.assert_array_equal(mech.pattern_dense(), oracle.Oracle(path).pattern())
+
+
+def test_error_paths_of_further_reaction_types(api, tmp_path):
+    from conftest import TYPES_SEEDS, types_file
+    m, _ = types_file(TYPES_SEEDS[0], tmp_path)
+    good = synth.dumps(m)
+    assert _status(api, _write(tmp_path, good)) == 0
+
+    def edited(fn):
+        mm = synth.loads(good)
+        fn(mm)
+        return _status(api, _write(tmp_path, synth.dumps(mm)))
+
+    def first(mm, t):
+        return next(r for r in mm.reactions if r.type == t)
+
+    def pl_descending(mm):
+        r = first(mm, "PLOG")
+        r.plog = r.plog[::-1]
+
+    def pl_too_long(mm):
+        r = first(mm, "PLOG")
+        r.plog = [(synth.ATM * (1 + k), 30.0, 0.0, 0.0) for k in range(65)]
+
+    def cheb_bad_range(mm):
+        r = first(mm, "CHEB")
+        (t0, t1, p0, p1), c = r.cheb
+        r.cheb = ((t1, t0, p0, p1), c)
+
+    def cheb_too_big(mm):
+        r = first(mm, "CHEB")
+        r.cheb = (r.cheb[0], [[1.0] * 2 for _ in range(17)])
+
+    def chemact_on_elem(mm):
+        first(mm, "ELEM").chemact = True
+
+    def sri_bad(mm):
+        r = first(mm, "SRI")
+        r.sri = (0.5, 100.0, -3.0, 1.0, 0.0)
+
+    def eff_on_plog(mm):
+        first(mm, "PLOG").eff = [(0, 2.0)]
+
+    assert edited(pl_descending) == 2          # PJ_E_PARSE
+    assert edited(pl_too_long) == 6            # PJ_E_UNSUPPORTED
+    assert edited(cheb_bad_range) == 2
+    assert edited(cheb_too_big) == 6
+    assert edited(chemact_on_elem) == 2
+    assert edited(sri_bad) == 2
+    assert edited(eff_on_plog) == 2
+    assert _status(api, _write(tmp_path, good.replace(" SRI ", " SRI2 ", 1))) == 2
