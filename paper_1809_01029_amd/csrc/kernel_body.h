@@ -941,29 +941,28 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_batch_kernel(const BatchSeg* _
                                                                 const int nseg, const long total,
                                                                 const long gr_off) {
     extern __shared__ double lds[];
-    long q0, q1, qstep;
-    group_range(total, q0, q1, qstep);
-    // adjoint: the parameter sums of the segment in hand live in LDS at gr_off
-    // (gr_off < 0: added to the output per group); the groups of a workgroup
-    // run through the segments in order, so it flushes at most once per
-    // segment
+    // Every segment is spread over the whole grid, each XCD taking a
+    // contiguous share of it as for a single mechanism, so that segments of
+    // very different cost per group keep all XCDs equally busy.  Adjoint: the
+    // parameter sums of the segment in hand live in LDS at gr_off (gr_off < 0:
+    // added to the output per group) and are flushed once per segment.
     const bool use_gr = MODE == MODE_ADJ && gr_off >= 0;
     double* GR = use_gr ? lds + gr_off : nullptr;
-    int cur = -1;
-    for (long gq = q0; gq < q1; gq += qstep) {
-        int k = 0;
-        while (k + 1 < nseg && segs[k + 1].g0 <= gq) ++k;
+    for (int k = 0; k < nseg; ++k) {
         const BatchSeg& b = segs[k];
-        if (use_gr && k != cur) {
-            if (cur >= 0) flush_gr(segs[cur], GR);
+        const long ng = (k + 1 < nseg ? segs[k + 1].g0 : total) - b.g0;
+        long q0, q1, qstep;
+        group_range(ng, q0, q1, qstep);
+        if (q0 >= q1) continue;   // uniform over the workgroup
+        if (use_gr) {
             for (int i = threadIdx.x; i < 3 * b.dm.nr_pad; i += blockDim.x) GR[i] = 0.0;
             __syncthreads();
-            cur = k;
         }
-        eval_group<FORM, LAYOUT, MODE, S, EXT>(b.dm, b.n, b.state, b.param, b.dstate, b.out, b.vin, b.grad,
-                                          use_gr && b.grad, GR, gq - b.g0);
+        for (long q = q0; q < q1; q += qstep)
+            eval_group<FORM, LAYOUT, MODE, S, EXT>(b.dm, b.n, b.state, b.param, b.dstate, b.out, b.vin,
+                                                   b.grad, use_gr && b.grad, GR, q);
+        if (use_gr) flush_gr(b, GR);
     }
-    if (use_gr && cur >= 0) flush_gr(segs[cur], GR);
 }
 
 template <int FORM, int LAYOUT, int MODE, int S, bool EXT>
@@ -1008,7 +1007,10 @@ static hipError_t launch_batch_t(int waves, int64_t lds, const BatchSeg* segs, i
         if (e != hipSuccess) return e;
     }
     // a persistent grid over the segments' groups (a multiple of 8, the XCD count)
-    int64_t grid = total < 8192 ? total : 8192;
+    // (the adjoint's workgroups each flush their parameter sums once per
+    // segment: a smaller grid keeps those atomics few)
+    const int64_t cap = MODE == MODE_ADJ ? 2048 : 8192;
+    int64_t grid = total < cap ? total : cap;
     if (grid >= 8) grid &= ~(int64_t)7;
     hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * waves), (size_t)lds, stream, segs, nseg, (long)total,
                        (long)gr_off);
