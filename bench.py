@@ -333,6 +333,41 @@ def main():
                                "vs_static_csr": round(t / ms, 3)}
             del jv
             mv.close()
+        # saturation: states/s of the same launch against the batch size (the
+        # first k states of this batch)
+        sat = {}
+        for k in (100, 1000, 10000, 30000, 100000, n):
+            if k > n:
+                continue
+            xk = xs[:k] if args.layout == "C" else xs[:, :k].contiguous()
+            pk = ps[:k]
+            jk = torch.empty((nnz, k) if args.layout == "F" else (k, nnz), dtype=torch.float64, device="cuda")
+            dk = torch.empty_like(xk)
+            t = timeit(lambda: api.eval_jacobian_sparse(mech, xk, pk, args.form, args.layout, out=jk, dstate=dk,
+                                                        stream=stream), k=10 if k < n else 3)
+            sat[str(k)] = {"ms": round(t, 4), "states_per_s": k / (t * 1e-3)}
+            del xk, jk, dk
+        variants["saturation_sparse"] = sat
+        # with the inputs copied in from pinned host memory and the outputs
+        # (source terms and CSR values) copied back, per step (not `value`)
+        hx = torch.empty(xs.shape, dtype=torch.float64, pin_memory=True)
+        hp = torch.empty(ps.shape, dtype=torch.float64, pin_memory=True)
+        hj = torch.empty(jac.shape, dtype=torch.float64, pin_memory=True)
+        hd = torch.empty(dstate.shape, dtype=torch.float64, pin_memory=True)
+        hx.copy_(xs)
+        hp.copy_(ps)
+
+        def pcie_step():
+            xs.copy_(hx, non_blocking=True)
+            ps.copy_(hp, non_blocking=True)
+            api.eval_jacobian_sparse(mech, xs, ps, args.form, args.layout, out=jac, dstate=dstate, stream=stream)
+            hj.copy_(jac, non_blocking=True)
+            hd.copy_(dstate, non_blocking=True)
+        t = timeit(pcie_step, k=2)
+        variants["pcie_inclusive_sparse"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3),
+                                             "bytes_over_pcie": int((xs.numel() + ps.numel() + jac.numel()
+                                                                     + dstate.numel()) * 8)}
+        del hx, hp, hj, hd
         if args.workload == "ns111" and not args.n_states:
             variants["ragged_13_53_111"] = ragged_batch(api, synth, torch, tmp, args, stream, timeit)
             # the same size with every reaction type (SRI, chemically activated,
