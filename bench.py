@@ -116,12 +116,21 @@ def ragged_batch(api, synth, torch, tmp, args, stream, timeit):
                 b.add(sg["mech"], sg["xs"], sg["ps"], args.layout, dstate=sg["d"])
             else:
                 b.add(sg["mech"], sg["xs"], sg["ps"], args.layout, out=sg["jtv"], v=sg["v"], grad=sg["g"])
+        # the batch autotuner chooses between one persistent launch (at its
+        # best shape) and one launch per segment (at each mechanism's shape)
         b.autotune(mode, args.form, args.layout, reps=1, stream=stream)
+        chosen = b.strategy(mode)
         t_plain = timeit(plain)
         t_batch = timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream))
         t_graph = timeit(lambda: b.eval(mode, args.form, args.layout, graph=True, stream=stream))
+        b.set_strategy(mode, not chosen)
+        t_other = timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream))
+        t_persist, t_perseg = (t_other, t_batch) if chosen else (t_batch, t_other)
         out[mode] = {"per_mechanism_ms": round(t_plain, 4), "batch_ms": round(t_batch, 4),
-                     "graph_ms": round(t_graph, 4), "batch_shape": list(b.launch_shape(mode))}
+                     "graph_ms": round(t_graph, 4),
+                     "batch_strategy": "per_segment" if chosen else "persistent",
+                     "persistent_launch_ms": round(t_persist, 4), "per_segment_launches_ms": round(t_perseg, 4),
+                     "persistent_shape": list(b.launch_shape(mode))}
         b.close()
     for sg in segs:
         sg["mech"].close()

@@ -266,7 +266,10 @@ int64_t pj_mech_lds_bytes(const pj_mech* mech, int for_jacobian);
  * Buffers are caller-owned device memory in the layout given at evaluation,
  * and must stay valid while the batch (or its graph) may run.  States per
  * workgroup are at most 4 and shared by all segments; the LDS a workgroup
- * gets is that of the largest segment.
+ * gets is that of the largest segment.  Per mode, the batch can instead run
+ * one launch per segment, each at its mechanism's own launch shape for that
+ * mode (pj_batch_set_strategy(batch, mode, 1); 0 = the persistent launch,
+ * the default); the graph then holds those launches.
  *
  * pj_batch_add records a segment (n_states may be 0); adding or clearing
  * segments, or changing the launch shape, discards a captured graph.
@@ -274,9 +277,14 @@ int64_t pj_mech_lds_bytes(const pj_mech* mech, int for_jacobian);
  * shape uploads a small segment table synchronously).  pj_batch_eval_graph
  * captures the same work once per (mode, form, layout, shape) on a private
  * stream and launches the graph on `stream`; later calls replay it.
- * pj_batch_autotune times every fitting shape (as pj_mech_autotune) and keeps
- * the fastest for that mode.  Errors as for the per-mechanism calls, with the
- * segment index in the message (pj_batch_last_error).
+ * pj_batch_autotune times every fitting shape (as pj_mech_autotune) and one
+ * launch per segment (at the mechanisms' current shapes), and keeps the
+ * fastest for that mode: *states_per_group and *waves_per_group receive 0
+ * when the per-segment launches win (the best persistent shape is kept as
+ * the mode's launch shape either way).  pj_batch_strategy returns the mode's
+ * strategy (0 or 1; -1 for a NULL batch or a bad mode).  Errors as for the
+ * per-mechanism calls, with the segment index in the message
+ * (pj_batch_last_error).
  */
 typedef struct pj_batch pj_batch; /* opaque, library-owned */
 pj_status pj_batch_create(pj_batch** out);
@@ -288,6 +296,8 @@ pj_status pj_batch_clear(pj_batch* batch);
 int pj_batch_size(const pj_batch* batch); /* segments, -1 for NULL */
 pj_status pj_batch_set_launch(pj_batch* batch, int mode, int states_per_group, int waves_per_group);
 int pj_batch_launch_shape(const pj_batch* batch, int mode, int* states_per_group, int* waves_per_group);
+pj_status pj_batch_set_strategy(pj_batch* batch, int mode, int per_segment);
+int pj_batch_strategy(const pj_batch* batch, int mode);
 pj_status pj_batch_eval(pj_batch* batch, int mode, pj_form form, pj_layout layout, pj_stream stream);
 pj_status pj_batch_eval_graph(pj_batch* batch, int mode, pj_form form, pj_layout layout, pj_stream stream);
 pj_status pj_batch_autotune(pj_batch* batch, int mode, pj_form form, pj_layout layout, int reps,

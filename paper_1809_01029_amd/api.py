@@ -95,6 +95,10 @@ _lib.pj_batch_autotune.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                    ctypes.POINTER(ctypes.c_float)]
 _lib.pj_batch_autotune.restype = ctypes.c_int
+_lib.pj_batch_set_strategy.argtypes = [_P, ctypes.c_int, ctypes.c_int]
+_lib.pj_batch_set_strategy.restype = ctypes.c_int
+_lib.pj_batch_strategy.argtypes = [_P, ctypes.c_int]
+_lib.pj_batch_strategy.restype = ctypes.c_int
 _lib.pj_batch_last_error.argtypes = []
 _lib.pj_batch_last_error.restype = ctypes.c_char_p
 _lib.pj_mech_set_waves_per_state.argtypes = [_P, ctypes.c_int]
@@ -472,12 +476,23 @@ class Batch:
             raise PjError(1, "pj_batch_launch_shape")
         return a.value, b.value
 
+    def set_strategy(self, mode: str, per_segment: bool):
+        """One persistent launch (False) or one launch per segment at each
+        mechanism's own launch shape (True) for ``mode``."""
+        self._bcheck(_lib.pj_batch_set_strategy(self._h, MODES[mode], int(bool(per_segment))),
+                     "pj_batch_set_strategy")
+
+    def strategy(self, mode: str) -> bool:
+        return _lib.pj_batch_strategy(self._h, MODES[mode]) == 1
+
     def eval(self, mode: str, form: str = "conp", layout: str = "F", graph: bool = False, stream=None):
         f = _lib.pj_batch_eval_graph if graph else _lib.pj_batch_eval
         self._bcheck(f(self._h, MODES[mode], FORMS[form], LAYOUTS[layout], _stream(stream)),
                      "pj_batch_eval_graph" if graph else "pj_batch_eval")
 
     def autotune(self, mode: str, form: str = "conp", layout: str = "F", reps: int = 2, stream=None):
+        """Keep the fastest of every persistent launch shape and one launch per
+        segment; returns (S, W, ms), (0, 0, ms) for the per-segment launches."""
         S, W, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
         self._bcheck(_lib.pj_batch_autotune(self._h, MODES[mode], FORMS[form], LAYOUTS[layout], reps,
                                             _stream(stream), ctypes.byref(S), ctypes.byref(W), ctypes.byref(ms)),

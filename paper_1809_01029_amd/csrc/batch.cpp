@@ -1,6 +1,7 @@
 // C-ABI of ragged multi-mechanism batches (declared in include/pjac.h):
 // segments of states of different mechanisms evaluated by one persistent
-// launch, optionally captured once into a HIP graph and replayed.
+// launch (or, per mode, by one launch per segment at each mechanism's own
+// launch shape), optionally captured once into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,6 +38,7 @@ struct pj_batch {
     std::vector<Seg> segs;
     int device = -1;
     int user_S[pj::N_MODES] = {0, 0, 0, 0}, user_W[pj::N_MODES] = {0, 0, 0, 0};
+    int per_seg[pj::N_MODES] = {0, 0, 0, 0};   // 1: one launch per segment
     // device copy of the segment table, for the shape it was built with
     pj::BatchSeg* d_segs = nullptr;
     size_t d_cap = 0;
@@ -46,7 +48,7 @@ struct pj_batch {
     // captured graph and what it was captured for
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int g_mode = -1, g_form = -1, g_layout = -1, g_S = 0, g_W = 0;
+    int g_mode = -1, g_form = -1, g_layout = -1, g_S = 0, g_W = 0, g_per_seg = 0;
     hipStream_t capture_stream = nullptr;
 
     void drop_graph() {
@@ -187,6 +189,29 @@ pj_status enqueue(pj_batch* b, int mode, pj_form form, pj_layout layout, int S, 
     return PJ_OK;
 }
 
+// one launch per segment, each at its mechanism's launch shape for the mode
+// (the single-mechanism entry points, which also clear the adjoint's sums)
+pj_status enqueue_segments(pj_batch* b, int mode, pj_form form, pj_layout layout, hipStream_t st) {
+    for (size_t i = 0; i < b->segs.size(); ++i) {
+        const auto& sg = b->segs[i];
+        pj_status r;
+        if (mode == pj::MODE_SRC)
+            r = pj_eval_source(sg.mech, form, layout, sg.n, sg.state, sg.param, sg.dstate, st);
+        else if (mode == pj::MODE_SPARSE)
+            r = pj_eval_jacobian_sparse(sg.mech, form, layout, sg.n, sg.state, sg.param, sg.out, sg.dstate, st);
+        else
+            r = pj_eval_adjoint(sg.mech, form, layout, sg.n, sg.state, sg.param, sg.v, sg.out, sg.grad, sg.dstate, st);
+        if (r != PJ_OK) return fail(r, "segment " + std::to_string(i) + ": " + pj_last_error());
+    }
+    return PJ_OK;
+}
+
+// the batch as configured for the mode: one persistent launch of shape S x W,
+// or one launch per segment
+pj_status enqueue_mode(pj_batch* b, int mode, pj_form form, pj_layout layout, int S, int W, hipStream_t st) {
+    return b->per_seg[mode] ? enqueue_segments(b, mode, form, layout, st) : enqueue(b, mode, form, layout, S, W, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -256,6 +281,21 @@ int pj_batch_launch_shape(const pj_batch* b, int mode, int* states_per_group, in
     return 0;
 }
 
+pj_status pj_batch_set_strategy(pj_batch* b, int mode, int per_segment) {
+    if (!b) return fail(PJ_E_INVALID, "NULL batch");
+    if (!batch_mode(mode)) return fail(PJ_E_INVALID, "bad mode");
+    if (per_segment != 0 && per_segment != 1) return fail(PJ_E_INVALID, "per_segment must be 0 or 1");
+    b->per_seg[mode] = per_segment;
+    b->drop_graph();
+    g_err.clear();
+    return PJ_OK;
+}
+
+int pj_batch_strategy(const pj_batch* b, int mode) {
+    if (!b || !batch_mode(mode)) return -1;
+    return b->per_seg[mode];
+}
+
 pj_status pj_batch_eval(pj_batch* b, int mode, pj_form form, pj_layout layout, pj_stream stream) {
     if (!b) return fail(PJ_E_INVALID, "NULL batch");
     pj_status r = check_segments(b, mode, form, layout);
@@ -263,9 +303,9 @@ pj_status pj_batch_eval(pj_batch* b, int mode, pj_form form, pj_layout layout, p
     if (b->segs.empty()) { g_err.clear(); return PJ_OK; }
     int S, W;
     batch_shape(b, mode, S, W);
-    if (batch_lds(b, mode, S, W) > lds_max_of(b))
+    if (!b->per_seg[mode] && batch_lds(b, mode, S, W) > lds_max_of(b))
         return fail(PJ_E_UNSUPPORTED, "a segment's working set exceeds the LDS of one workgroup");
-    r = enqueue(b, mode, form, layout, S, W, (hipStream_t)stream);
+    r = enqueue_mode(b, mode, form, layout, S, W, (hipStream_t)stream);
     if (r == PJ_OK) g_err.clear();
     return r;
 }
@@ -277,17 +317,21 @@ pj_status pj_batch_eval_graph(pj_batch* b, int mode, pj_form form, pj_layout lay
     if (b->segs.empty()) { g_err.clear(); return PJ_OK; }
     int S, W;
     batch_shape(b, mode, S, W);
-    if (batch_lds(b, mode, S, W) > lds_max_of(b))
+    const int ps = b->per_seg[mode];
+    if (!ps && batch_lds(b, mode, S, W) > lds_max_of(b))
         return fail(PJ_E_UNSUPPORTED, "a segment's working set exceeds the LDS of one workgroup");
-    if (!b->exec || b->g_mode != mode || b->g_form != form || b->g_layout != layout || b->g_S != S || b->g_W != W) {
+    if (!b->exec || b->g_mode != mode || b->g_form != form || b->g_layout != layout || b->g_S != S || b->g_W != W ||
+        b->g_per_seg != ps) {
         b->drop_graph();
-        r = upload_table(b, S);   // synchronous, outside the capture
-        if (r != PJ_OK) return r;
+        if (!ps) {
+            r = upload_table(b, S);   // synchronous, outside the capture
+            if (r != PJ_OK) return r;
+        }
         if (!b->capture_stream && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
             return fail(PJ_E_DEVICE, "hipStreamCreate failed");
         hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
-        r = enqueue(b, mode, form, layout, S, W, b->capture_stream);
+        r = enqueue_mode(b, mode, form, layout, S, W, b->capture_stream);
         hipGraph_t gr = nullptr;
         e = hipStreamEndCapture(b->capture_stream, &gr);
         if (r != PJ_OK) {
@@ -306,6 +350,7 @@ pj_status pj_batch_eval_graph(pj_batch* b, int mode, pj_form form, pj_layout lay
         b->g_layout = layout;
         b->g_S = S;
         b->g_W = W;
+        b->g_per_seg = ps;
     }
     hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
     if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
@@ -327,15 +372,23 @@ pj_status pj_batch_autotune(pj_batch* b, int mode, pj_form form, pj_layout layou
         return fail(PJ_E_DEVICE, "hipEventCreate failed");
     }
     const int mx = lds_max_of(b);
-    int bS = 0, bW = 0;
-    float best = -1.0f;
+    int bS = 0, bW = 0, pS = 0, pW = 0;
+    float best = -1.0f, bestp = -1.0f;
     pj_status err = PJ_OK;
-    for (int S = 1; S <= 4 && err == PJ_OK; S *= 2)
+    // every persistent launch shape that fits (S > 0), then one launch per
+    // segment at each mechanism's current shape (S = 0); the best persistent
+    // shape is kept for the mode either way
+    for (int S = 1; S <= 8 && err == PJ_OK; S *= 2)
         for (int W = 1; W <= 8 && err == PJ_OK; W *= 2) {
-            if (batch_lds(b, mode, S, W) > mx) continue;
-            err = enqueue(b, mode, form, layout, S, W, st);   // warm-up
+            const bool segs_each = S == 8;
+            if (segs_each && W > 1) break;
+            if (!segs_each && batch_lds(b, mode, S, W) > mx) continue;
+            auto run = [&]() {
+                return segs_each ? enqueue_segments(b, mode, form, layout, st) : enqueue(b, mode, form, layout, S, W, st);
+            };
+            err = run();   // warm-up
             hipError_t e = err == PJ_OK ? hipEventRecord(e0, st) : hipSuccess;
-            for (int k = 0; k < reps && err == PJ_OK && e == hipSuccess; ++k) err = enqueue(b, mode, form, layout, S, W, st);
+            for (int k = 0; k < reps && err == PJ_OK && e == hipSuccess; ++k) err = run();
             if (err != PJ_OK) break;
             if (e == hipSuccess) e = hipEventRecord(e1, st);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -343,13 +396,25 @@ pj_status pj_batch_autotune(pj_batch* b, int mode, pj_form form, pj_layout layou
             if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
             if (e != hipSuccess) { err = fail(PJ_E_DEVICE, std::string("autotuning: ") + hipGetErrorString(e)); break; }
             t /= (float)reps;
-            if (best < 0.0f || t < best) { best = t; bS = S; bW = W; }
+            if (!segs_each && (bestp < 0.0f || t < bestp)) {
+                bestp = t;
+                pS = S;
+                pW = W;
+            }
+            if (best < 0.0f || t < best) {
+                best = t;
+                bS = segs_each ? 0 : S;
+                bW = segs_each ? 0 : W;
+            }
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != PJ_OK) return err;
-    b->user_S[mode] = bS;
-    b->user_W[mode] = bW;
+    b->per_seg[mode] = bS == 0 ? 1 : 0;
+    if (pS) {
+        b->user_S[mode] = pS;
+        b->user_W[mode] = pW;
+    }
     b->drop_graph();
     if (states_per_group) *states_per_group = bS;
     if (waves_per_group) *waves_per_group = bW;

@@ -200,6 +200,14 @@ def test_batch_argument_checks(api, tmp_path):
     for mode, S, W in ((2, 1, 1), (1, 8, 1), (1, 3, 1), (1, 1, 3)):
         assert lib.pj_batch_set_launch(b, mode, S, W) == 1
     assert lib.pj_batch_set_launch(b, 1, 2, 4) == 0
+    # strategy: one persistent launch (0, the default) or one per segment (1)
+    assert lib.pj_batch_strategy(b, 1) == 0
+    assert lib.pj_batch_set_strategy(b, 1, 2) == 1
+    assert lib.pj_batch_set_strategy(b, 2, 1) == 1
+    assert lib.pj_batch_set_strategy(None, 1, 1) == 1
+    assert lib.pj_batch_set_strategy(b, 1, 1) == 0 and lib.pj_batch_strategy(b, 1) == 1
+    assert lib.pj_batch_set_strategy(b, 1, 0) == 0 and lib.pj_batch_strategy(b, 1) == 0
+    assert lib.pj_batch_strategy(None, 1) == -1 and lib.pj_batch_strategy(b, 2) == -1
     # modes: 0, 1, 3 only; a mechanism that is not uploaded is reported by segment
     assert lib.pj_batch_eval(b, 2, 0, 0, None) == 1
     assert lib.pj_batch_eval(b, 1, 0, 0, None) == 1

@@ -124,11 +124,18 @@ def test_batch_equals_per_mechanism_launch(torch_cuda, api, mode, mech_dir):
                 assert torch.equal(ref, sg["out"]) and torch.equal(dref, sg["d"]), sg["name"]
 
 
+@pytest.mark.parametrize("per_segment", [False, True])
 @pytest.mark.parametrize("mode", ["sparse", "adjoint"])
-def test_batch_graph_replays(torch_cuda, api, mode, mech_dir):
+def test_batch_graph_replays(torch_cuda, api, mode, per_segment, mech_dir):
     torch = torch_cuda
     b, segs = build(torch, api, mech_dir, "conp", "F", mode)
     b.set_launch(mode, 2, 1)
+    b.set_strategy(mode, per_segment)
+    if per_segment:
+        # one wave per workgroup for every mechanism too: replays then give
+        # the eager run's bits
+        for sg in segs:
+            sg["mech"].set_launch(2, 1)
     b.eval(mode, "conp", "F")
     torch.cuda.synchronize()
     ref = [(sg["d"].clone(), None if sg["out"] is None else sg["out"].clone(),
@@ -161,10 +168,48 @@ def test_batch_autotune(torch_cuda, api, mech_dir):
     b, segs = build(torch, api, mech_dir, "conp", "C", "sparse")
     S, W, ms = b.autotune("sparse", "conp", "C", reps=1)
     note(f"batch autotune: S={S} W={W} {ms:.4f} ms")
-    assert b.launch_shape("sparse") == (S, W) and S in (1, 2, 4) and W in (1, 2, 4, 8)
+    if S == 0:
+        # one launch per segment won; the best persistent shape is kept
+        assert W == 0 and b.strategy("sparse")
+        Sp, Wp = b.launch_shape("sparse")
+        assert Sp in (1, 2, 4) and Wp in (1, 2, 4, 8)
+    else:
+        assert not b.strategy("sparse")
+        assert b.launch_shape("sparse") == (S, W) and S in (1, 2, 4) and W in (1, 2, 4, 8)
     for sg in segs:
         if sg["out"] is not None:
             sg["out"].zero_()
     b.eval("sparse", "conp", "C")
     torch.cuda.synchronize()
     check_against_oracle(api, segs, "conp", "C", "sparse")
+
+
+@pytest.mark.parametrize("layout", ["F", "C"])
+@pytest.mark.parametrize("form,mode", [("conp", "source"), ("conv", "sparse"), ("conp", "adjoint")])
+def test_batch_per_segment_launches(torch_cuda, api, form, mode, layout, mech_dir):
+    """One launch per segment at each mechanism's own shape: the oracle's
+    values, and (one wave per workgroup) the single-mechanism calls' bits."""
+    torch = torch_cuda
+    b, segs = build(torch, api, mech_dir, form, layout, mode)
+    for k, sg in enumerate(segs):
+        sg["mech"].set_launch((1, 2, 4)[k % 3], 1)
+    b.set_strategy(mode, True)
+    assert b.strategy(mode)
+    note(f"batch per segment {form} {mode} {layout}")
+    b.eval(mode, form, layout)
+    torch.cuda.synchronize()
+    check_against_oracle(api, segs, form, layout, mode)
+    if mode == "adjoint":
+        return
+    for sg in segs:
+        if sg["x"].shape[0] == 0:
+            continue
+        if mode == "source":
+            ref = api.eval_source(sg["mech"], sg["xs"], sg["ps"], form, layout)
+            torch.cuda.synchronize()
+            assert torch.equal(ref, sg["d"]), sg["name"]
+        else:
+            dref = torch.empty_like(sg["xs"])
+            ref = api.eval_jacobian_sparse(sg["mech"], sg["xs"], sg["ps"], form, layout, dstate=dref)
+            torch.cuda.synchronize()
+            assert torch.equal(ref, sg["out"]) and torch.equal(dref, sg["d"]), sg["name"]
