@@ -790,9 +790,21 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
         __syncthreads();
 
         if (ADJ) {
-            // species rows: J_kj v_k into column j
-            for (int e = 2 * N + g; e < nnz; e += G)
-                atomicAdd(&AT(JTV, dm.col_idx[e]), AT(J, e) * AT(VV, dm.row_of[e]));
+            // species rows: J_kj v_k into column j, with several entries'
+            // (column, row) table reads in flight per lane
+            constexpr int TU = 8;
+            int e = 2 * N + g;
+            for (; e + (TU - 1) * G < nnz; e += TU * G) {
+                uint16_t c[TU], r[TU];
+#pragma unroll
+                for (int u = 0; u < TU; ++u) {
+                    c[u] = dm.col_idx[e + u * G];
+                    r[u] = dm.row_of[e + u * G];
+                }
+#pragma unroll
+                for (int u = 0; u < TU; ++u) atomicAdd(&AT(JTV, c[u]), AT(J, e + u * G) * AT(VV, r[u]));
+            }
+            for (; e < nnz; e += G) atomicAdd(&AT(JTV, dm.col_idx[e]), AT(J, e) * AT(VV, dm.row_of[e]));
             __syncthreads();
             if (valid)
                 for (int i = g; i < N; i += G) {
@@ -829,6 +841,9 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             // dense: every entry in output order; the species rows from the
             // accumulator through the (row, column) -> CSR slot maps (0 off
             // the pattern), the T and V/P rows from their staging
+            // Each lane keeps DU map entries in flight: the map reads come from
+            // L2, and one at a time they would leave the loop latency-bound.
+            constexpr int DU = 8;
             const long NN = (long)N * N;
             if (LAYOUT == PJ_LAYOUT_F) {
                 if (valid) {
@@ -836,7 +851,16 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                         jac[st + n * ((long)N * j)] = AT(Gg, j);
                         jac[st + n * (1 + (long)N * j)] = AT(H, j);
                     }
-                    for (long f = g; f < NN; f += G) {
+                    long f = g;
+                    for (; f + (DU - 1) * G < NN; f += DU * G) {
+                        uint16_t e[DU];
+#pragma unroll
+                        for (int u = 0; u < DU; ++u) e[u] = dm.dmap_cm[f + u * G];
+#pragma unroll
+                        for (int u = 0; u < DU; ++u)
+                            if (e[u] != DMAP_SKIP) jac[st + n * (f + u * G)] = e[u] == NOSLOT ? 0.0 : AT(J, e[u]);
+                    }
+                    for (; f < NN; f += G) {
                         const uint16_t e = dm.dmap_cm[f];
                         if (e == DMAP_SKIP) continue;
                         jac[st + n * f] = e == NOSLOT ? 0.0 : AT(J, e);
@@ -845,17 +869,24 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             } else {
                 const int s2 = tid / G, g2 = tid % G;
                 const long st2 = qg * S + s2;
-                if (st2 < n)
-                    for (long f = g2; f < NN; f += G) {
-                        double v;
-                        if (f < N) v = Gg[(size_t)f * S + s2];
-                        else if (f < 2 * N) v = H[(size_t)(f - N) * S + s2];
-                        else {
-                            const uint16_t e = dm.dmap_rm[f];
-                            v = e == NOSLOT ? 0.0 : J[(size_t)e * S + s2];
-                        }
-                        jac[st2 * NN + f] = v;
+                if (st2 < n) {
+                    double* out = jac + st2 * NN;
+                    for (int f = g2; f < 2 * N; f += G)
+                        out[f] = f < N ? Gg[(size_t)f * S + s2] : H[(size_t)(f - N) * S + s2];
+                    long f = 2 * N + g2;
+                    for (; f + (DU - 1) * G < NN; f += DU * G) {
+                        uint16_t e[DU];
+#pragma unroll
+                        for (int u = 0; u < DU; ++u) e[u] = dm.dmap_rm[f + u * G];
+#pragma unroll
+                        for (int u = 0; u < DU; ++u)
+                            out[f + u * G] = e[u] == NOSLOT ? 0.0 : J[(size_t)e[u] * S + s2];
                     }
+                    for (; f < NN; f += G) {
+                        const uint16_t e = dm.dmap_rm[f];
+                        out[f] = e == NOSLOT ? 0.0 : J[(size_t)e * S + s2];
+                    }
+                }
             }
         }
         __syncthreads();
