@@ -820,9 +820,18 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             if (LAYOUT == PJ_LAYOUT_F) {
                 // S consecutive states of one slot are contiguous
                 if (valid) {
-                    if (dm.ccs_pos)
-                        for (int e = g; e < nnz; e += G) jac[(long)dm.ccs_pos[e] * n + st] = val(e, s);
-                    else
+                    if (dm.ccs_pos) {
+                        // several column-order positions in flight per lane
+                        int e = g;
+                        for (; e + 7 * G < nnz; e += 8 * G) {
+                            uint16_t q[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) q[u] = dm.ccs_pos[e + u * G];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) jac[(long)q[u] * n + st] = val(e + u * G, s);
+                        }
+                        for (; e < nnz; e += G) jac[(long)dm.ccs_pos[e] * n + st] = val(e, s);
+                    } else
                         for (int e = g; e < nnz; e += G) jac[(long)e * n + st] = val(e, s);
                 }
             } else {
@@ -831,9 +840,17 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 const int s2 = tid / G, g2 = tid % G;
                 const long st2 = qg * S + s2;
                 if (st2 < n) {
-                    if (dm.ccs_pos)
-                        for (int e = g2; e < nnz; e += G) jac[st2 * (long)nnz + dm.ccs_pos[e]] = val(e, s2);
-                    else
+                    if (dm.ccs_pos) {
+                        int e = g2;
+                        for (; e + 7 * G < nnz; e += 8 * G) {
+                            uint16_t q[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) q[u] = dm.ccs_pos[e + u * G];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) jac[st2 * (long)nnz + q[u]] = val(e + u * G, s2);
+                        }
+                        for (; e < nnz; e += G) jac[st2 * (long)nnz + dm.ccs_pos[e]] = val(e, s2);
+                    } else
                         for (int e = g2; e < nnz; e += G) jac[st2 * (long)nnz + e] = val(e, s2);
                 }
             }
