@@ -135,6 +135,51 @@ def ragged_batch(api, synth, torch, tmp, args, stream, timeit):
         b.close()
     for sg in segs:
         sg["mech"].close()
+    out["many_small"] = many_small_batch(api, synth, torch, tmp, args, stream, timeit)
+    return out
+
+
+def many_small_batch(api, synth, torch, tmp, args, stream, timeit, nseg=16, count=1024):
+    """The launch-latency-bound regime: 16 segments of 1,024 states of the
+    13-species mechanism (separate state draws), source terms and sparse
+    Jacobian: one launch per segment against the batch (autotuned strategy)
+    and its graph."""
+    w = synth.WORKLOADS["ns13"]
+    mm = synth.workload_mechanism("ns13")
+    pth = os.path.join(tmp, "small_ns13.pjm")
+    synth.write_mechanism(mm, pth)
+    me = api.load_mechanism(pth)
+    segs = []
+    for k in range(nseg):
+        st = synth.make_states(mm, count, 3000 + k, T_range=w.T_range, P_range_atm=w.P_range_atm)
+        x, p = synth.pack_state(st, args.form, args.layout)
+        xs = torch.from_numpy(x).cuda()
+        segs.append(dict(xs=xs, ps=torch.from_numpy(p).cuda(), d=torch.empty_like(xs),
+                         j=torch.empty((me.nnz, count) if args.layout == "F" else (count, me.nnz),
+                                       dtype=torch.float64, device="cuda")))
+    out = {"segments": nseg, "states_per_segment": count}
+    for mode in ("source", "sparse"):
+        api.autotune(me, segs[0]["xs"], segs[0]["ps"], args.form, args.layout, mode=mode, reps=2, stream=stream)
+
+        def plain():
+            for sg in segs:
+                if mode == "source":
+                    api.eval_source(me, sg["xs"], sg["ps"], args.form, args.layout, out=sg["d"], stream=stream)
+                else:
+                    api.eval_jacobian_sparse(me, sg["xs"], sg["ps"], args.form, args.layout, out=sg["j"],
+                                             dstate=sg["d"], stream=stream)
+        b = api.Batch()
+        for sg in segs:
+            b.add(me, sg["xs"], sg["ps"], args.layout, out=sg["j"] if mode == "sparse" else None, dstate=sg["d"])
+        b.autotune(mode, args.form, args.layout, reps=3, stream=stream)
+        out[mode] = {"per_segment_launches_ms": round(timeit(plain, k=20), 4),
+                     "batch_ms": round(timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream), k=20), 4),
+                     "graph_ms": round(timeit(lambda: b.eval(mode, args.form, args.layout, graph=True,
+                                                             stream=stream), k=20), 4),
+                     "batch_strategy": "per_segment" if b.strategy(mode) else "persistent",
+                     "persistent_shape": list(b.launch_shape(mode))}
+        b.close()
+    me.close()
     return out
 
 
