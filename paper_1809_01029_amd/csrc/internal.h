@@ -1,5 +1,6 @@
 // Internal structures shared by the host mechanism compiler (mech.cpp), the
-// kernels (kernels.hip) and the C-ABI (api.cpp).
+// kernels (kernel_body.h, kernels.hip, kernels_ext.hip) and the C-ABI (api.cpp,
+// batch.cpp).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -201,7 +202,7 @@ struct BatchSeg {
 pj_status build_mechanism(const char* path, Mechanism& m, std::string& err);
 pj_status upload_mechanism(Mechanism& m, std::string& err);
 
-// kernels.hip
+// kernels.hip (kernel_body.h)
 enum Mode : int { MODE_SRC = 0, MODE_SPARSE = 1, MODE_DENSE = 2, MODE_ADJ = 3,
                   MODE_SPARSE_LS = 4 /* sparse with run-time slot search; launch shape of MODE_SPARSE */ };
 constexpr int N_MODES = 4;        // modes with a launch shape of their own

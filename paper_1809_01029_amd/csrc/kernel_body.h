@@ -21,15 +21,17 @@
 //     J                [nnz]  CSR accumulator of the species rows
 //     B                [Ns]   per-row sum of the bath-gas partials
 //     TQ, SQ           [Ns+1] energy- and mole-weighted concentration
-//                      partials, kept in the space of CSR rows 0 and 1,
-//                      which are written to the output from registers
+//                      partials, kept in the space of CSR rows 0 and 1 (the
+//                      finished T and V/P rows are staged in the G and H
+//                      arrays and written out with the species rows)
 //     VV, JTV          [N]    (adjoint) the vector v and J^T v
 //     GR               [3 Nr] (adjoint, per workgroup, not per state) the
 //                      workgroup's sums of the Arrhenius-parameter derivatives
 // Reactions scatter into these with LDS FP64 atomics (ds_add_f64).  Because
 // the S states of one reaction sit in adjacent words, one atomic instruction
-// touches 64/S reactions in S-word blocks, which keeps LDS bank conflicts and
-// same-address collisions (hub species) low.  With one wave per workgroup the
+// touches 64/S reactions in S-word blocks; the order of the species within a
+// reaction side is chosen per 64-reaction chunk so that hub species do not
+// repeat one address within an instruction.  With one wave per workgroup the
 // order of those additions is fixed by program order, so results are bitwise
 // reproducible.
 //
@@ -322,9 +324,9 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
     double* B = J + (size_t)nnz * S;
     double* VV = B + (size_t)ns * S;      // adjoint: v, then J^T v
     double* JTV = VV + (size_t)N * S;
-    // The T and V/P rows (the first 2N CSR slots) go to the output straight
-    // from registers; their LDS space holds the energy- and mole-weighted
-    // partial sums meanwhile.
+    // The LDS of the T and V/P rows (the first 2N CSR slots) holds the
+    // energy- and mole-weighted partial sums; the finished rows are staged
+    // in the G and H arrays.
     double* TQ = J;
     double* SQ = J + (size_t)N * S;
 #define AT(arr, i) (arr)[(size_t)(i) * S + s]
