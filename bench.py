@@ -18,6 +18,7 @@ import argparse
 import concurrent.futures
 import hashlib
 import json
+import platform
 import os
 import sys
 import tempfile
@@ -473,8 +474,14 @@ def main():
         with concurrent.futures.ThreadPoolExecutor(threads) as ex:
             list(ex.map(run_oracle, np.array_split(np.arange(k), threads)))
         dt = time.perf_counter() - t0
+        host = platform.processor() or platform.machine()
+        try:
+            with open("/proc/cpuinfo") as fh:
+                host = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), host)
+        except OSError:
+            pass
         cpu = {"value": k / dt, "unit": "states/s", "cores": threads, "kind": "oracle",
-               "serial_value": k / dt1,
+               "serial_value": k / dt1, "host_cpu": host, "host_cpus_visible": os.cpu_count(),
                "sample": f"first {k} of the {n} {args.workload} states: source terms + analytical "
                          f"Jacobian (dense, holding the CSR values), FP64 oracle on {threads} host threads "
                          f"{dt:.1f} s; on one thread {dt1:.1f} s (serial_value)"}

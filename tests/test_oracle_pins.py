@@ -419,7 +419,7 @@ def test_jacobian_matches_complex_step_tiny(form, seed, bath, mech_dir):
 
 
 @pytest.mark.parametrize("form", ["conp", "conv"])
-@pytest.mark.parametrize("name,n", [("ns13", 16), ("ns53", 2)])
+@pytest.mark.parametrize("name,n", [("ns13", 16), ("ns53", 2), ("ns111", 2), ("ns360", 1)])
 def test_jacobian_matches_complex_step_workloads(form, name, n, mech_dir):
     m, path = workload_file(name, mech_dir)
     o = oracle.Oracle(path)
