@@ -389,6 +389,30 @@ def main():
                                "vs_static_csr": round(t / ms, 3)}
             del jv
             mv.close()
+        if args.workload == "ns111" and not args.n_states:
+            # the 13-species configuration at its size (1,024 states): launch
+            # latency bound, reported per call
+            w13 = synth.WORKLOADS["ns13"]
+            m13 = synth.workload_mechanism("ns13")
+            p13 = os.path.join(tmp, "ns13.pjm")
+            synth.write_mechanism(m13, p13)
+            st13 = synth.make_states(m13, w13.n_states, w13.state_seed, T_range=w13.T_range,
+                                     P_range_atm=w13.P_range_atm)
+            x6, p6 = synth.pack_state(st13, args.form, args.layout)
+            mech13 = api.load_mechanism(p13)
+            xs6, ps6 = torch.from_numpy(x6).cuda(), torch.from_numpy(p6).cuda()
+            j6 = torch.empty((mech13.nnz, w13.n_states) if args.layout == "F" else (w13.n_states, mech13.nnz),
+                             dtype=torch.float64, device="cuda")
+            d6 = torch.empty_like(xs6)
+            if not args.no_autotune:
+                api.autotune(mech13, xs6, ps6, args.form, args.layout, mode="sparse", reps=3, stream=stream)
+            t = timeit(lambda: api.eval_jacobian_sparse(mech13, xs6, ps6, args.form, args.layout, out=j6, dstate=d6,
+                                                        stream=stream), k=50)
+            variants["ns13_1024_sparse"] = {"us_per_call": round(t * 1e3, 2),
+                                            "states_per_s": w13.n_states / (t * 1e-3),
+                                            "launch_shape": list(mech13.launch_shape(1))}
+            del xs6, ps6, j6, d6
+            mech13.close()
         # saturation: states/s of the same launch against the batch size (the
         # first k states of this batch)
         sat = {}
