@@ -66,11 +66,14 @@ def check_jac(g, o, s, what):
                           f"worst ratio {float(np.max(err / (JAC_TOL * s + JAC_ABS))):.3e}"
 
 
-def run_case(torch, api, path, x_c, p, form, layout, dense=True, sample=None):
+def run_case(torch, api, path, x_c, p, form, layout, dense=True, sample=None, launch=None):
     """Evaluate on the GPU and compare with the oracle on all states (or the
-    ``sample`` indices)."""
+    ``sample`` indices); ``launch``: (states, waves) per workgroup, else the
+    library's default shape."""
     o = oracle.Oracle(path)
     mech = api.load_mechanism(path)
+    if launch:
+        mech.set_launch(*launch)
     n = x_c.shape[0]
     note(f"case {path} n={n} form={form} layout={layout}")
     xs, ps = to_dev(torch, x_c, p, layout)

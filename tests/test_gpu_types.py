@@ -167,3 +167,30 @@ def test_types_in_ragged_batch(torch_cuda, api, mode, mech_dir):
             assert np.all(np.abs(_host(out, layout) - j_o) <= 1e-8 * j_s + 1e-20), f"batch {path} J^T v"
             assert np.all(np.abs(grad.cpu().numpy() - g_o) <= 1e-8 * g_s + 1e-20), f"batch {path} grad"
     b.close()
+
+
+# random mechanisms holding every type: (seed, species, reactions); odd seeds
+# let the bath gas react and give it an efficiency
+RANDOM_TYPES = [(100, 11, 23), (101, 12, 30), (103, 14, 44), (104, 15, 51), (105, 16, 58),
+                (106, 17, 24), (107, 18, 31), (108, 19, 38), (109, 20, 45), (112, 12, 25)]
+
+
+@pytest.mark.parametrize("seed,ns,nr", RANDOM_TYPES)
+def test_types_random_mechanisms(torch_cuda, api, seed, ns, nr, mech_dir):
+    """Both forms and layouts at a launch shape drawn per mechanism, states
+    from 500 to 2,500 K and 0.02 to 500 atm, a ragged last group."""
+    from conftest import TYPES_MIX
+    import os
+    m = synth.make_mechanism(ns, nr, seed, mix=TYPES_MIX, zipf=0.5, bath_reactions=seed % 2,
+                             bath_efficiency=bool(seed % 2))
+    path = os.path.join(str(mech_dir), f"rtypes_{seed}.pjm")
+    synth.write_mechanism(m, path)
+    rng = np.random.default_rng(seed)
+    S, W = [(1, 1), (1, 2), (2, 2), (2, 4), (4, 1), (4, 4), (8, 1), (16, 1)][seed % 8]
+    st = synth.make_states(m, 77, seed, T_range=(500.0, 2500.0), P_range_atm=(0.02, 500.0))
+    for form in ("conp", "conv"):
+        x, p = synth.pack_state(st, form, "C")
+        layout = "CF"[int(rng.integers(2))]
+        run_case(torch_cuda, api, path, x, p, form, layout, dense=True)
+        note(f"random types {seed} {form} at {S}x{W}")
+        run_case(torch_cuda, api, path, x, p, form, "F" if layout == "C" else "C", dense=False, launch=(S, W))
