@@ -66,6 +66,9 @@ def _load():
         lib.ora_adjoint.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, D, D, D, D]
         lib.ora_param_grad_cs.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, ctypes.c_double, D]
         lib.ora_jvp_cs.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, ctypes.c_double, D]
+        lib.ora_source_ld.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D]
+        lib.ora_jacobian_ld.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, ctypes.c_int]
+        lib.ora_source_ops.argtypes = [P, ctypes.c_int, D, ctypes.c_double, D]
         _lib = lib
     return _lib
 
@@ -118,27 +121,55 @@ class Oracle:
                 "C": out[6 * nr + ns: 6 * nr + 2 * ns], "Tdot": t[0], "Sdot": t[1],
                 "N": t[2], "D": t[3], "Omega": t[4]}
 
-    def source(self, x, p, form="conp", scale: bool = False):
+    def source(self, x, p, form="conp", bound: bool = False):
+        """Source terms [n, N]; with ``bound``, also the running error bound
+        of every value (a first-order bound on |computed - exact|, in the
+        value's units)."""
         x = _f64(x).reshape(-1, self.N)
         p = _f64(p).reshape(-1)
         n = x.shape[0]
         f = np.zeros_like(x)
-        s = np.zeros_like(x) if scale else None
+        b = np.zeros_like(x) if bound else None
         self._lib.ora_source(self._h, _FORMS[form], n, _d(x), _d(p), _d(f),
-                             _d(s) if scale else None)
-        return (f, s) if scale else f
+                             _d(b) if bound else None)
+        return (f, b) if bound else f
 
-    def jacobian(self, x, p, form="conp", scale: bool = False, approx: bool = False):
-        """Analytical Jacobian [n, N, N]; ``approx``: the approximate form
-        (the bath gas's moles held fixed against the other species')."""
+    def jacobian(self, x, p, form="conp", bound: bool = False, approx: bool = False):
+        """Analytical Jacobian [n, N, N] (with ``bound``, also the running
+        error bound of every entry); ``approx``: the approximate form (the
+        bath gas's moles held fixed against the other species')."""
         x = _f64(x).reshape(-1, self.N)
         p = _f64(p).reshape(-1)
         n = x.shape[0]
         J = np.zeros((n, self.N, self.N))
-        s = np.zeros_like(J) if scale else None
+        b = np.zeros_like(J) if bound else None
         self._lib.ora_jacobian_ex(self._h, _FORMS[form], n, _d(x), _d(p), _d(J),
-                                  _d(s) if scale else None, int(approx))
-        return (J, s) if scale else J
+                                  _d(b) if bound else None, int(approx))
+        return (J, b) if bound else J
+
+    def source_ld(self, x, p, form="conp"):
+        """Source terms evaluated in long double, rounded to double."""
+        x = _f64(x).reshape(-1, self.N)
+        p = _f64(p).reshape(-1)
+        f = np.zeros_like(x)
+        self._lib.ora_source_ld(self._h, _FORMS[form], x.shape[0], _d(x), _d(p), _d(f))
+        return f
+
+    def jacobian_ld(self, x, p, form="conp", approx: bool = False):
+        """Analytical Jacobian evaluated in long double, rounded to double."""
+        x = _f64(x).reshape(-1, self.N)
+        p = _f64(p).reshape(-1)
+        J = np.zeros((x.shape[0], self.N, self.N))
+        self._lib.ora_jacobian_ld(self._h, _FORMS[form], x.shape[0], _d(x), _d(p), _d(J), int(approx))
+        return J
+
+    def source_ops(self, x, p: float, form="conp"):
+        """Arithmetic operations of one state's source terms as the oracle
+        writes them: dict(flops = + - * / count, exp, log)."""
+        x = _f64(x).reshape(-1)
+        out = np.zeros(3)
+        self._lib.ora_source_ops(self._h, _FORMS[form], _d(x), float(p), _d(out))
+        return {"flops": int(out[0]), "exp": int(out[1]), "log": int(out[2])}
 
     def jacobian_cs(self, x, p, form="conp", hrel: float = 1e-30, approx: bool = False):
         x = _f64(x).reshape(-1, self.N)
@@ -154,21 +185,21 @@ class Oracle:
         self._lib.ora_jacobian_fd(self._h, _FORMS[form], x.shape[0], _d(x), _d(p), rel, _d(J))
         return J
 
-    def adjoint(self, x, p, v, form="conp", scale: bool = False):
+    def adjoint(self, x, p, v, form="conp", bound: bool = False):
         """(J^T v per state [n, N], batch-summed d(v . dPhi/dt)/d(ln A, b, Ea/R)
-        per reaction [3, nr] in description order), with absolute-term scales
-        of both if ``scale``."""
+        per reaction [3, nr] in description order), with the running error
+        bounds of both if ``bound``."""
         x = _f64(x).reshape(-1, self.N)
         p = _f64(p).reshape(-1)
         v = _f64(v).reshape(-1, self.N)
         n = x.shape[0]
         jtv = np.zeros_like(x)
         g = np.zeros((3, self.nr))
-        js = np.zeros_like(x) if scale else None
-        gs = np.zeros_like(g) if scale else None
+        js = np.zeros_like(x) if bound else None
+        gs = np.zeros_like(g) if bound else None
         self._lib.ora_adjoint(self._h, _FORMS[form], n, _d(x), _d(p), _d(v), _d(jtv), _d(g),
-                              _d(js) if scale else None, _d(gs) if scale else None)
-        return (jtv, g, js, gs) if scale else (jtv, g)
+                              _d(js) if bound else None, _d(gs) if bound else None)
+        return (jtv, g, js, gs) if bound else (jtv, g)
 
     def param_grad_cs(self, x, p, v, form="conp", hrel: float = 1e-30):
         """Complex-step d(v . dPhi/dt)/d(ln A, b, Ea/R), summed over states."""

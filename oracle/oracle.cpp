@@ -12,14 +12,22 @@
 //   * double                 - the values;
 //   * std::complex<double>   - complex-step derivatives (a check of the
 //                              hand-derived Jacobian, exact to rounding);
-//   * Scaled                 - value plus an "absolute-term" scale: every
-//                              addition or subtraction adds the magnitudes
-//                              of its operands, products and quotients
-//                              multiply them, functions take the magnitude of
-//                              their value.  The scale equals |value| when
-//                              nothing cancels and grows by the amount of
-//                              cancellation otherwise; parity tolerances are
-//                              relative to it.
+//   * Err                    - value plus a first-order bound on its rounding
+//                              error (running error analysis: Wilkinson;
+//                              Higham, Accuracy and Stability of Numerical
+//                              Algorithms, Sec. 3.3).  Each operation adds the
+//                              propagated bounds of its operands, weighted by
+//                              the magnitude of its partial derivatives, and
+//                              one rounding of its own result; library exp
+//                              and log add one ulp.  Parity tolerances widen
+//                              by this bound only where it is not small
+//                              against the value (cancellation);
+//   * long double            - the same definitions in 64-bit-significand
+//                              arithmetic, an independent reference against
+//                              which the bound is checked;
+//   * Cnt                    - values that count the arithmetic operations
+//                              of the source terms as written here (the
+//                              algorithmic operation count of the roofline).
 //
 // The adjoint (the product of the transposed Jacobian with a vector v and
 // the batch-summed derivatives of v . dPhi/dt with respect to every
@@ -104,32 +112,69 @@ struct Mech {
 // ---------------------------------------------------------------------------
 // scalar types
 
-struct Scaled {
-    double v, s;
-    Scaled() : v(0), s(0) {}
-    Scaled(double x) : v(x), s(std::fabs(x)) {}
-    Scaled(double x, double sc) : v(x), s(sc) {}
+// Running error bound: v is the computed value, m a bound on |v - exact| in
+// units of the unit roundoff u = 2^-53 (to first order in u).  Inputs and the
+// constants of the description are exact (m = 0).
+const double U_ROUND = 1.1102230246251565e-16;   // 2^-53
+const double FN_ULPS = 2.0;   // library exp / log / log10: within one ulp (2u)
+
+struct Err {
+    double v, m;
+    Err() : v(0), m(0) {}
+    Err(double x) : v(x), m(0) {}
+    Err(double x, double mm) : v(x), m(mm) {}
 };
-inline Scaled operator+(Scaled a, Scaled b) { return Scaled(a.v + b.v, a.s + b.s); }
-inline Scaled operator-(Scaled a, Scaled b) { return Scaled(a.v - b.v, a.s + b.s); }
-inline Scaled operator-(Scaled a) { return Scaled(-a.v, a.s); }
-inline Scaled operator*(Scaled a, Scaled b) { return Scaled(a.v * b.v, a.s * b.s); }
-// A quotient multiplies the amplifications of numerator and denominator,
-// s(a/b) = (s_a/|b|) (s_b/|b|), as a product does: s(ab) = s_a s_b.  With
-// operands that carry no cancellation both give |value|.
-inline Scaled operator/(Scaled a, Scaled b) {
-    double ab = std::fabs(b.v);
-    return Scaled(a.v / b.v, (a.s / ab) * (b.s / ab));
+inline Err operator+(Err a, Err b) { double r = a.v + b.v; return Err(r, a.m + b.m + std::fabs(r)); }
+inline Err operator-(Err a, Err b) { double r = a.v - b.v; return Err(r, a.m + b.m + std::fabs(r)); }
+inline Err operator-(Err a) { return Err(-a.v, a.m); }
+inline Err operator*(Err a, Err b) {
+    double r = a.v * b.v;
+    return Err(r, std::fabs(b.v) * a.m + std::fabs(a.v) * b.m + std::fabs(r));
 }
-inline Scaled& operator+=(Scaled& a, Scaled b) { a = a + b; return a; }
-inline Scaled& operator-=(Scaled& a, Scaled b) { a = a - b; return a; }
-inline Scaled exp(Scaled a) { double e = std::exp(a.v); return Scaled(e, e); }
-inline Scaled log(Scaled a) { double l = std::log(a.v); return Scaled(l, std::fabs(l) + a.s / std::fabs(a.v)); }
-inline Scaled log10(Scaled a) { double l = std::log10(a.v); return Scaled(l, std::fabs(l) + a.s / (LN10 * std::fabs(a.v))); }
+// d(a/b) = da / b - (a/b) db / b
+inline Err operator/(Err a, Err b) {
+    double r = a.v / b.v;
+    return Err(r, (a.m + std::fabs(r) * b.m) / std::fabs(b.v) + std::fabs(r));
+}
+inline Err& operator+=(Err& a, Err b) { a = a + b; return a; }
+inline Err& operator-=(Err& a, Err b) { a = a - b; return a; }
+inline Err exp(Err a) { double e = std::exp(a.v); return Err(e, e * a.m + FN_ULPS * e); }
+inline Err log(Err a) {
+    double l = std::log(a.v);
+    return Err(l, a.m / std::fabs(a.v) + FN_ULPS * std::fabs(l));
+}
+inline Err log10(Err a) {
+    double l = std::log10(a.v);
+    return Err(l, a.m / (LN10 * std::fabs(a.v)) + FN_ULPS * std::fabs(l));
+}
+
+// Operation counting: every + - * / of two values (or a value and a
+// constant) counts one, exp, log and log10 count separately.
+struct OpCount {
+    double flops = 0, exps = 0, logs = 0;
+};
+thread_local OpCount g_ops;
+struct Cnt {
+    double v;
+    Cnt() : v(0) {}
+    Cnt(double x) : v(x) {}
+};
+inline Cnt operator+(Cnt a, Cnt b) { g_ops.flops += 1; return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { g_ops.flops += 1; return Cnt(a.v - b.v); }
+inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
+inline Cnt operator*(Cnt a, Cnt b) { g_ops.flops += 1; return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { g_ops.flops += 1; return Cnt(a.v / b.v); }
+inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
+inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
+inline Cnt exp(Cnt a) { g_ops.exps += 1; return Cnt(std::exp(a.v)); }
+inline Cnt log(Cnt a) { g_ops.logs += 1; return Cnt(std::log(a.v)); }
+inline Cnt log10(Cnt a) { g_ops.logs += 1; return Cnt(std::log10(a.v)); }
 
 inline double re(double x) { return x; }
 inline double re(const std::complex<double>& x) { return x.real(); }
-inline double re(const Scaled& x) { return x.v; }
+inline double re(const Err& x) { return x.v; }
+inline double re(const Cnt& x) { return x.v; }
+inline double re(long double x) { return (double)x; }
 
 using std::exp;
 using std::log;
@@ -144,10 +189,11 @@ inline double rn_sum(const double* v, int n) {
     return (double)acc;
 }
 inline double exact_sum(const double* v, int n) { return rn_sum(v, n); }
-inline Scaled exact_sum(const Scaled* v, int n) {
+template <class S>
+S exact_sum(const S* v, int n) {
     std::vector<double> x(n);
-    for (int k = 0; k < n; ++k) x[k] = v[k].v;
-    return Scaled(rn_sum(x.data(), n));
+    for (int k = 0; k < n; ++k) x[k] = re(v[k]);
+    return S(rn_sum(x.data(), n));
 }
 inline std::complex<double> exact_sum(const std::complex<double>* v, int n) {
     std::vector<double> x(n);
@@ -294,6 +340,17 @@ inline std::complex<double> frozen_sum(const std::complex<double>* v, int n) {
 template <class S>
 S frozen_sum(const S* v, int n) { return exact_sum(v, n); }
 
+// The bath gas's moles are defined on the double inputs: n_Ns = PV/(RT) -
+// RN(sum_k n_k), formed as (P V) / (R T) minus that sum, in double, so that
+// any two codes that follow the definition hold the same bits.  The types
+// that measure rounding (Err) or carry more precision (long double) take
+// that double as their exact starting point; the complex step and the
+// operation count follow the arithmetic as written.
+template <class S>
+S closure_moles(S ntot, S sum, double) { return ntot - sum; }
+inline Err closure_moles(Err, Err, double shared) { return Err(shared, 0.0); }
+inline long double closure_moles(long double, long double, double shared) { return (long double)shared; }
+
 template <class S>
 State<S> make_state(const Mech& m, int form, const S* x, S param, bool frozen = false) {
     State<S> st;
@@ -303,10 +360,13 @@ State<S> make_state(const Mech& m, int form, const S* x, S param, bool frozen = 
     else { st.P = x[1]; st.V = param; }
     S ntot = (st.P * st.V) / (S(RU) * st.T);
     S sum = frozen ? frozen_sum(x + 2, ns - 1) : exact_sum(x + 2, ns - 1);
+    std::vector<double> xd(ns - 1);
+    for (int k = 0; k < ns - 1; ++k) xd[k] = re(x[2 + k]);
+    const double shared = (re(st.P) * re(st.V)) / (RU * re(st.T)) - rn_sum(xd.data(), ns - 1);
     st.n.resize(ns);
     st.C.resize(ns);
     for (int k = 0; k < ns - 1; ++k) st.n[k] = x[2 + k];
-    st.n[ns - 1] = ntot - sum;
+    st.n[ns - 1] = closure_moles(ntot, sum, shared);
     for (int k = 0; k < ns; ++k) st.C[k] = st.n[k] / st.V;
     return st;
 }
@@ -944,18 +1004,20 @@ void ora_components(void* h, int form, const double* x, double param, double* ou
     t[0] = ev.Tdot; t[1] = ev.Sdot; t[2] = ev.N; t[3] = ev.D; t[4] = ev.Omega;
 }
 
-// Source terms for n states, state rows of length N (row-major), optional scales.
+// Source terms for n states, state rows of length N (row-major); bound (if
+// not NULL) receives the running error bound of each value, u * m, in the
+// value's units.
 void ora_source(void* h, int form, long n, const double* x, const double* param,
-                double* f, double* scale) {
+                double* f, double* bound) {
     const Mech& m = *static_cast<Mech*>(h);
     int N = m.ns + 1;
     for (long s = 0; s < n; ++s) {
         const double* xs = x + s * N;
-        if (scale) {
-            std::vector<Scaled> xx(N);
-            for (int i = 0; i < N; ++i) xx[i] = Scaled(xs[i]);
-            Eval<Scaled> ev = evaluate(m, form, xx.data(), Scaled(param[s]), false);
-            for (int i = 0; i < N; ++i) { f[s * N + i] = ev.f[i].v; scale[s * N + i] = ev.f[i].s; }
+        if (bound) {
+            std::vector<Err> xx(N);
+            for (int i = 0; i < N; ++i) xx[i] = Err(xs[i]);
+            Eval<Err> ev = evaluate(m, form, xx.data(), Err(param[s]), false);
+            for (int i = 0; i < N; ++i) { f[s * N + i] = ev.f[i].v; bound[s * N + i] = U_ROUND * ev.f[i].m; }
         } else {
             Eval<double> ev = evaluate(m, form, xs, param[s], false);
             for (int i = 0; i < N; ++i) f[s * N + i] = ev.f[i];
@@ -963,28 +1025,69 @@ void ora_source(void* h, int form, long n, const double* x, const double* param,
     }
 }
 
-// Analytical Jacobian, dense row-major N*N per state, optional scales;
-// approx != 0: the approximate form.
+// Analytical Jacobian, dense row-major N*N per state, optional running error
+// bounds; approx != 0: the approximate form.
 void ora_jacobian_ex(void* h, int form, long n, const double* x, const double* param,
-                     double* J, double* scale, int approx) {
+                     double* J, double* bound, int approx) {
     const Mech& m = *static_cast<Mech*>(h);
     int N = m.ns + 1;
     size_t NN = (size_t)N * N;
     for (long s = 0; s < n; ++s) {
         const double* xs = x + s * N;
-        if (scale) {
-            std::vector<Scaled> xx(N), JJ(NN);
-            for (int i = 0; i < N; ++i) xx[i] = Scaled(xs[i]);
-            jacobian(m, form, xx.data(), Scaled(param[s]), JJ.data(), approx != 0);
-            for (size_t e = 0; e < NN; ++e) { J[s * NN + e] = JJ[e].v; scale[s * NN + e] = JJ[e].s; }
+        if (bound) {
+            std::vector<Err> xx(N), JJ(NN);
+            for (int i = 0; i < N; ++i) xx[i] = Err(xs[i]);
+            jacobian(m, form, xx.data(), Err(param[s]), JJ.data(), approx != 0);
+            for (size_t e = 0; e < NN; ++e) { J[s * NN + e] = JJ[e].v; bound[s * NN + e] = U_ROUND * JJ[e].m; }
         } else {
             jacobian(m, form, xs, param[s], J + s * NN, approx != 0);
         }
     }
 }
 
-void ora_jacobian(void* h, int form, long n, const double* x, const double* param, double* J, double* scale) {
-    ora_jacobian_ex(h, form, n, x, param, J, scale, 0);
+void ora_jacobian(void* h, int form, long n, const double* x, const double* param, double* J, double* bound) {
+    ora_jacobian_ex(h, form, n, x, param, J, bound, 0);
+}
+
+// The same definitions in long double (64-bit significand), rounded to
+// double at the end: a reference about 2^11 times more precise than the
+// double evaluation, used to check the running error bounds.
+void ora_source_ld(void* h, int form, long n, const double* x, const double* param, double* f) {
+    const Mech& m = *static_cast<Mech*>(h);
+    int N = m.ns + 1;
+    for (long s = 0; s < n; ++s) {
+        std::vector<long double> xx(N);
+        for (int i = 0; i < N; ++i) xx[i] = x[s * N + i];
+        Eval<long double> ev = evaluate(m, form, xx.data(), (long double)param[s], false);
+        for (int i = 0; i < N; ++i) f[s * N + i] = (double)ev.f[i];
+    }
+}
+
+void ora_jacobian_ld(void* h, int form, long n, const double* x, const double* param, double* J, int approx) {
+    const Mech& m = *static_cast<Mech*>(h);
+    int N = m.ns + 1;
+    size_t NN = (size_t)N * N;
+    for (long s = 0; s < n; ++s) {
+        std::vector<long double> xx(N), JJ(NN);
+        for (int i = 0; i < N; ++i) xx[i] = x[s * N + i];
+        jacobian(m, form, xx.data(), (long double)param[s], JJ.data(), approx != 0);
+        for (size_t e = 0; e < NN; ++e) J[s * NN + e] = (double)JJ[e];
+    }
+}
+
+// Arithmetic operations of the source terms of one state as the definitions
+// above write them: out = {+ - * / count, exp count, log and log10 count}.
+void ora_source_ops(void* h, int form, const double* x, double param, double* out) {
+    const Mech& m = *static_cast<Mech*>(h);
+    int N = m.ns + 1;
+    std::vector<Cnt> xx(N);
+    for (int i = 0; i < N; ++i) xx[i] = Cnt(x[i]);
+    g_ops = OpCount();
+    Eval<Cnt> ev = evaluate(m, form, xx.data(), Cnt(param), false);
+    (void)ev;
+    out[0] = g_ops.flops;
+    out[1] = g_ops.exps;
+    out[2] = g_ops.logs;
 }
 
 // Complex-step Jacobian: column j = Im f(Phi + i h_j e_j) / h_j with
@@ -1036,25 +1139,25 @@ void ora_pattern_ex(void* h, unsigned char* P, int approx) { pattern(*static_cas
 
 // Adjoint over n states (rows of length N, v likewise): jtv[s] = J(s)^T v[s];
 // grad[3][nr] = sum over states of d(v . dPhi/dt)/d(ln A, b, Ea/R) per reaction
-// in description order.  Optional absolute-term scales of both.
+// in description order.  Optional running error bounds of both.
 void ora_adjoint(void* h, int form, long n, const double* x, const double* param, const double* v,
                  double* jtv_out, double* grad, double* jtv_scale, double* grad_scale) {
     const Mech& m = *static_cast<Mech*>(h);
     int N = m.ns + 1, nr = (int)m.rx.size();
-    std::vector<Scaled> gsum(3 * nr, Scaled(0.0));
+    std::vector<Err> gsum(3 * nr, Err(0.0));
     std::vector<double> gd(3 * nr, 0.0);
     for (long s = 0; s < n; ++s) {
         const double* xs = x + s * N;
         const double* vs = v + s * N;
         if (jtv_scale || grad_scale) {
-            std::vector<Scaled> xx(N), o(N), g(3 * nr);
-            for (int i = 0; i < N; ++i) xx[i] = Scaled(xs[i]);
-            jtv(m, form, xx.data(), Scaled(param[s]), vs, o.data());
+            std::vector<Err> xx(N), o(N), g(3 * nr);
+            for (int i = 0; i < N; ++i) xx[i] = Err(xs[i]);
+            jtv(m, form, xx.data(), Err(param[s]), vs, o.data());
             for (int j = 0; j < N; ++j) {
                 jtv_out[s * N + j] = o[j].v;
-                if (jtv_scale) jtv_scale[s * N + j] = o[j].s;
+                if (jtv_scale) jtv_scale[s * N + j] = U_ROUND * o[j].m;
             }
-            param_grad(m, form, xx.data(), Scaled(param[s]), vs, g.data());
+            param_grad(m, form, xx.data(), Err(param[s]), vs, g.data());
             for (int q = 0; q < 3 * nr; ++q) gsum[q] = gsum[q] + g[q];
         } else {
             std::vector<double> g(3 * nr);
@@ -1065,7 +1168,7 @@ void ora_adjoint(void* h, int form, long n, const double* x, const double* param
     }
     for (int q = 0; q < 3 * nr; ++q) {
         grad[q] = (jtv_scale || grad_scale) ? gsum[q].v : gd[q];
-        if (grad_scale) grad_scale[q] = gsum[q].s;
+        if (grad_scale) grad_scale[q] = U_ROUND * gsum[q].m;
     }
 }
 

@@ -8,12 +8,15 @@ and complex-step / central-difference derivatives of the source terms for the
 analytical Jacobian.  A dropped term, a wrong sign, a wrong index or a
 transposed operand anywhere in the oracle fails at least one of them.
 """
+import copy
 import math
 
 import numpy as np
 import pytest
 
 import oracle
+from oracle import gates
+from oracle.gates import U_ROUND, WIDEN
 from paper_1809_01029_amd import synth
 from conftest import TINY_SEEDS, tiny_file, workload_file
 
@@ -388,19 +391,31 @@ def test_detailed_balance_equilibrium(seed, mech_dir, tmp_path):
         x = state_vec(T, V, C[:-1] * V)
         c = o.components(x, P)
         assert np.all(np.abs(c["q"]) <= 1e-10 * np.abs(c["c"]) * np.abs(c["Rf"]) + 1e-300)
-        f, sc = o.source(x[None], np.array([P]), "conp", scale=True)
-        assert np.all(np.abs(f) <= 1e-9 * sc + 1e-300)
+        # at equilibrium the computed source terms are rounding noise: within
+        # the running error bound (the state itself is rounded, whence the margin)
+        f, fb = o.source(x[None], np.array([P]), "conp", bound=True)
+        assert np.all(np.abs(f) <= 4 * fb + 1e-300), float(np.max(np.abs(f) / (fb + 1e-300)))
 
 
 # ---------------------------------------------------------------------------
 # analytical Jacobian
 
 def _check_cs(o, x, p, form, tol=1e-12):
-    J, Js = o.jacobian(x, p, form, scale=True)
+    # the complex step is exact to rounding: it agrees with the analytical
+    # Jacobian to tol relative, or within the rounding the bound allows
+    J, Jb = o.jacobian(x, p, form, bound=True)
     Jc = o.jacobian_cs(x, p, form)
     err = np.abs(J - Jc)
-    assert np.all(err <= tol * Js + 1e-300), float(np.max(err / (Js + 1e-300)))
-    return J, Js, Jc
+    allow = tol * np.abs(J) + WIDEN * Jb + 1e-300
+    assert np.all(err <= allow), float(np.max(err / allow))
+    return J, Jb, Jc
+
+
+def fd_allowance(J, Jb, f, fb, h):
+    """Central differences with step h (per column): truncation (taken as
+    1e-6 relative, plus the rounding the bound allows) and the rounding of
+    the two source evaluations divided by the step."""
+    return 1e-6 * np.abs(J) + WIDEN * Jb + (4e-16 * np.abs(f) + 2 * fb)[:, :, None] / h[:, None, :]
 
 
 @pytest.mark.parametrize("form", ["conp", "conv"])
@@ -436,14 +451,13 @@ def test_jacobian_matches_central_differences(form, mech_dir):
     o = oracle.Oracle(path)
     st, (x, p) = _tiny_states(m, n=4, seed=3, form=form)
     # keep the bath gas well away from zero so that the +-h steps stay physical
-    J, Js = o.jacobian(x, p, form, scale=True)
+    J, Jb = o.jacobian(x, p, form, bound=True)
     for rel in (1e-6,):
         Jf = o.jacobian_fd(x, p, form, rel=rel)
-        f, fs = o.source(x, p, form, scale=True)
+        f, fb = o.source(x, p, form, bound=True)
         h = rel * np.maximum(np.abs(x), 1e-300)
-        # truncation O(h^2) plus rounding eps*|f|/h of the differences
-        tol = 1e-6 * Js + 4e-16 * fs[:, :, None] / h[:, None, :]
-        assert np.all(np.abs(J - Jf) <= tol)
+        tol = fd_allowance(J, Jb, f, fb, h)
+        assert np.all(np.abs(J - Jf) <= tol), float(np.max(np.abs(J - Jf) / tol))
 
 
 def test_pattern_of_hand_mechanism(tmp_path):
@@ -478,16 +492,11 @@ def test_pattern_of_hand_mechanism(tmp_path):
     np.testing.assert_array_equal(o2.pattern(), E2)
 
 
-def test_scale_bounds_value(mech_dir):
-    m, path = workload_file("ns13", mech_dir)
-    o = oracle.Oracle(path)
-    st = synth.make_states(m, 8, 5)
-    x, p = synth.pack_state(st, "conp", "C")
-    f, fs = o.source(x, p, "conp", scale=True)
-    assert np.all(fs >= np.abs(f) * (1 - 1e-15))
-    J, Js = o.jacobian(x, p, "conp", scale=True)
-    assert np.all(Js >= np.abs(J) * (1 - 1e-15))
-    # no cancellation -> scale equals the magnitude: one irreversible reaction
+def test_bound_is_small_without_cancellation(mech_dir):
+    # one irreversible reaction: nothing cancels, so the bound of each molar
+    # rate is a modest multiple of its rounding (the exponential amplifies the
+    # roundings of its argument ln A + b ln T - (Ea/R)/T, here about 25, by
+    # that argument)
     sp = SPECIES_ABC
     rx = [synth.Reaction("ELEM", False, [(0, 1), (1, 1)], [(2, 1)], 25.0, 0.3, 1000.0)]
     import tempfile, os
@@ -496,8 +505,90 @@ def test_scale_bounds_value(mech_dir):
         synth.write_mechanism(micro(sp, rx), pth)
         o2 = oracle.Oracle(pth)
         xx, P = _abc_state()
-        f2, s2 = o2.source(xx[None], np.array([P]), "conp", scale=True)
-        np.testing.assert_allclose(s2[0, 2:], np.abs(f2[0, 2:]), rtol=1e-15)
+        f2, b2 = o2.source(xx[None], np.array([P]), "conp", bound=True)
+        assert np.all(b2[0, 2:] <= 256 * U_ROUND * np.abs(f2[0, 2:]))
+        assert np.all(b2[0, 2:] >= U_ROUND * np.abs(f2[0, 2:]))
+
+
+@pytest.mark.parametrize("form", ["conp", "conv"])
+@pytest.mark.parametrize("name,n", [("ns13", 12), ("ns53", 4), ("ns111", 3)])
+def test_bound_covers_extended_precision_error(form, name, n, mech_dir):
+    # the running error bound holds: the double evaluation is within it of
+    # the same definitions evaluated in long double, on every entry
+    m, path = workload_file(name, mech_dir)
+    o = oracle.Oracle(path)
+    w = synth.WORKLOADS[name]
+    st = synth.make_states(m, n, w.state_seed + 11, T_range=w.T_range, P_range_atm=w.P_range_atm)
+    x, p = synth.pack_state(st, form, "C")
+    f, fb = o.source(x, p, form, bound=True)
+    fl = o.source_ld(x, p, form)
+    assert np.all(np.abs(f - fl) <= fb + 1e-300), float(np.max(np.abs(f - fl) / (fb + 1e-300)))
+    J, Jb = o.jacobian(x, p, form, bound=True)
+    Jl = o.jacobian_ld(x, p, form)
+    assert np.all(np.abs(J - Jl) <= Jb + 1e-300), float(np.max(np.abs(J - Jl) / (Jb + 1e-300)))
+
+
+@pytest.mark.parametrize("form", ["conp", "conv"])
+@pytest.mark.parametrize("seed", TINY_SEEDS)
+def test_bound_covers_extended_precision_error_tiny(form, seed, mech_dir):
+    m, path = tiny_file(seed, mech_dir, bath_reactions=1, bath_efficiency=True)
+    o = oracle.Oracle(path)
+    st, (x, p) = _tiny_states(m, n=6, seed=seed, form=form)
+    J, Jb = o.jacobian(x, p, form, bound=True)
+    Jl = o.jacobian_ld(x, p, form)
+    assert np.all(np.abs(J - Jl) <= Jb + 1e-300)
+    Ja, Jab = o.jacobian(x, p, form, bound=True, approx=True)
+    assert np.all(np.abs(Ja - o.jacobian_ld(x, p, form, approx=True)) <= Jab + 1e-300)
+
+
+@pytest.mark.parametrize("form", ["conp", "conv"])
+def test_gate_rejects_planted_errors(form, mech_dir):
+    # a 1e-6 relative error anywhere in the T and V/P rows, or in the
+    # species block, fails the Jacobian gate on at least 99% of the entries
+    # whose size puts the 1e-20 floor below that error (a gate that widened
+    # by the amount terms cancel, compounded through products, let most of
+    # them through)
+    m, path = workload_file("ns111", mech_dir)
+    o = oracle.Oracle(path)
+    w = synth.WORKLOADS["ns111"]
+    st = synth.make_states(m, 16, w.state_seed, T_range=w.T_range, P_range_atm=w.P_range_atm)
+    x, p = synth.pack_state(st, form, "C")
+    J, Jb = o.jacobian(x, p, form, bound=True)
+    allow = gates.jac_allowance(J, Jb)
+    a = np.abs(J)
+    rows = np.zeros(J.shape, dtype=bool)
+    rows[:, :2, :] = True
+    for rel in (1e-6, 1e-7):
+        planted = J * (1 + rel)
+        caught = np.abs(planted - J) > allow
+        above = rel * a > 1e-20
+        assert caught[rows & above].mean() >= 0.99, caught[rows & above].mean()
+        assert caught[~rows & above].mean() >= 0.99, caught[~rows & above].mean()
+    # and most entries are well conditioned: the literal relative test applies
+    kap = Jb[a > 0] / (U_ROUND * a[a > 0])
+    assert np.median(kap) < 1e4 and np.mean(kap > 1e6) < 0.01
+
+
+@pytest.mark.parametrize("form", ["conp", "conv"])
+@pytest.mark.parametrize("name,n", [("ns13", 12), ("ns53", 4)])
+def test_gate_accepts_reordered_reactions(form, name, n, mech_dir, tmp_path):
+    # the same mechanism with its reactions listed in another order sums
+    # every production rate and Jacobian entry in another order: a correct
+    # evaluation, which the gate must accept entry by entry
+    m, path = workload_file(name, mech_dir)
+    rng = np.random.default_rng(5)
+    m2 = copy.deepcopy(m)
+    m2.reactions = [m.reactions[i] for i in rng.permutation(len(m.reactions))]
+    p2 = str(tmp_path / f"{name}_perm.pjm")
+    synth.write_mechanism(m2, p2)
+    o, o2 = oracle.Oracle(path), oracle.Oracle(p2)
+    w = synth.WORKLOADS[name]
+    st = synth.make_states(m, n, w.state_seed + 5, T_range=w.T_range, P_range_atm=w.P_range_atm)
+    x, p = synth.pack_state(st, form, "C")
+    f, fb = o.source(x, p, form, bound=True)
+    gates.check_source(o2.source(x, p, form), f, fb, "reordered source terms")
+    J, Jb = o.jacobian(x, p, form, bound=True)
+    gates.check_jac(o2.jacobian(x, p, form), J, Jb, "reordered Jacobian")
 
 
 def test_closure_uses_exactly_rounded_sum(tmp_path):
