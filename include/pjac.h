@@ -194,6 +194,26 @@ pj_status pj_eval_adjoint(const pj_mech* mech, pj_form form, pj_layout layout, i
                           pj_stream stream);
 
 /*
+ * pj_eval_source and pj_eval_adjoint with the Arrhenius parameters of this
+ * call given as a device array instead of the mechanism's tables (what a
+ * differentiable calibration needs: the forward and backward passes of one
+ * parameter set run on that set, whatever other calls do meanwhile, and
+ * nothing shared is written or synchronised).  d_arrhenius: 3*Nr doubles on
+ * the device, [ln A (Nr), b (Nr), Ea/R (Nr)] in the description's reaction
+ * order, the same meaning as pj_mech_set_arrhenius; read only, owned by the
+ * caller, and it must stay valid until the call's work on `stream` is done.
+ * NULL gives PJ_E_INVALID.  Everything else as pj_eval_source /
+ * pj_eval_adjoint.
+ */
+pj_status pj_eval_source_arrhenius(const pj_mech* mech, pj_form form, pj_layout layout, int64_t n_states,
+                                   const double* d_state, const double* d_param, const double* d_arrhenius,
+                                   double* d_dstate, pj_stream stream);
+pj_status pj_eval_adjoint_arrhenius(const pj_mech* mech, pj_form form, pj_layout layout, int64_t n_states,
+                                    const double* d_state, const double* d_param, const double* d_arrhenius,
+                                    const double* d_v, double* d_jtv, double* d_grad_or_null,
+                                    double* d_dstate_or_null, pj_stream stream);
+
+/*
  * Replace / read the Arrhenius parameters (ln A, b, Ea/R of k_f; of k_inf
  * for falloff and chemically activated reactions; of the factor on the
  * tabulated rate for P-Log and Chebyshev) of all Nr reactions, host arrays in description
@@ -206,8 +226,8 @@ pj_status pj_mech_get_arrhenius(const pj_mech* mech, double* lnA, double* b, dou
 
 /*
  * Launch shape.  A workgroup evaluates states_per_group consecutive states at
- * once (a power of two up to 64) with waves_per_group waves (1, 2, 4 or 8);
- * 1 state per workgroup is the paper's deep mapping (Sec. 2.1: the lanes of a
+ * once (a power of two up to 64) with waves_per_group waves (1 to 8); 1 state
+ * per workgroup is the paper's deep mapping (Sec. 2.1: the lanes of a
  * workgroup cooperate on one state), 64 states on one wave its shallow
  * mapping (a lane per state).  0 restores the automatic choice (the most
  * states, up to 4, whose working set fits the LDS of one workgroup, and
@@ -229,7 +249,7 @@ int pj_mech_launch_shape(const pj_mech* mech, int mode, int* states_per_group, i
 
 /*
  * Autotuner: time every launch shape that fits (states per workgroup 1, 2,
- * 4, ..., 64; waves per workgroup 1, 2, 4, 8) for mode 0 (source), 1 (sparse
+ * 4, ..., 64; waves per workgroup 1 to 8) for mode 0 (source), 1 (sparse
  * Jacobian) or 2 (dense Jacobian) on the caller's batch, and keep the fastest
  * for that mode until the next pj_mech_set_launch.  The buffers are those of
  * the matching evaluation call (d_out: d_dstate for mode 0, the Jacobian

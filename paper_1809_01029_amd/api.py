@@ -68,6 +68,10 @@ _lib.pj_eval_jacobian_dense.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P
 _lib.pj_eval_jacobian_dense.restype = ctypes.c_int
 _lib.pj_eval_adjoint.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P, _P, _P, _P]
 _lib.pj_eval_adjoint.restype = ctypes.c_int
+_lib.pj_eval_source_arrhenius.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P, _P]
+_lib.pj_eval_source_arrhenius.restype = ctypes.c_int
+_lib.pj_eval_adjoint_arrhenius.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P, _P, _P, _P, _P]
+_lib.pj_eval_adjoint_arrhenius.restype = ctypes.c_int
 _DP = ctypes.POINTER(ctypes.c_double)
 _lib.pj_mech_set_arrhenius.argtypes = [_P, _DP, _DP, _DP]
 _lib.pj_mech_set_arrhenius.restype = ctypes.c_int
@@ -284,14 +288,23 @@ def _state_shape(mech, n, layout):
 
 
 def eval_source(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, form: str = "conp",
-                layout: str = "F", out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """pj_eval_source: dPhi/dt for every state."""
+                layout: str = "F", out: Optional[torch.Tensor] = None, stream=None,
+                arrhenius: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """pj_eval_source: dPhi/dt for every state.  ``arrhenius``: this call's
+    (ln A, b, Ea/R) as a (3, n_reactions) float64 device tensor in
+    description order (pj_eval_source_arrhenius), else the mechanism's."""
     n = _n_states(mech, state, layout)
     _need(state, _state_shape(mech, n, layout), "state", None)
     _need(param, (n,), "param", state.device)
     if out is None:
         out = torch.empty_like(state)
     _need(out, _state_shape(mech, n, layout), "out", state.device)
+    if arrhenius is not None:
+        _need(arrhenius, (3, mech.n_reactions), "arrhenius", state.device)
+        _check(_lib.pj_eval_source_arrhenius(mech.handle, FORMS[form], LAYOUTS[layout], n, _ptr(state),
+                                             _ptr(param), _ptr(arrhenius), _ptr(out), _stream(stream)),
+               "pj_eval_source_arrhenius")
+        return out
     _check(_lib.pj_eval_source(mech.handle, FORMS[form], LAYOUTS[layout], n, _ptr(state), _ptr(param),
                                _ptr(out), _stream(stream)), "pj_eval_source")
     return out
@@ -345,10 +358,12 @@ MODES = {"source": 0, "sparse": 1, "dense": 2, "adjoint": 3}
 def eval_adjoint(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, v: torch.Tensor,
                  form: str = "conp", layout: str = "F", jtv: Optional[torch.Tensor] = None,
                  grad: Optional[torch.Tensor] = None, with_grad: bool = True,
-                 dstate: Optional[torch.Tensor] = None, stream=None):
+                 dstate: Optional[torch.Tensor] = None, stream=None,
+                 arrhenius: Optional[torch.Tensor] = None):
     """pj_eval_adjoint: (J^T v per state in the state layout, batch-summed
     d(v . dPhi/dt)/d(ln A, b, Ea/R) as a (3, n_reactions) tensor in
-    description order, or None when ``with_grad`` is False)."""
+    description order, or None when ``with_grad`` is False).  ``arrhenius``:
+    this call's parameters as in eval_source (pj_eval_adjoint_arrhenius)."""
     n = _n_states(mech, state, layout)
     _need(state, _state_shape(mech, n, layout), "state", None)
     _need(param, (n,), "param", state.device)
@@ -364,6 +379,12 @@ def eval_adjoint(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, v: t
         grad = None
     if dstate is not None:
         _need(dstate, _state_shape(mech, n, layout), "dstate", state.device)
+    if arrhenius is not None:
+        _need(arrhenius, (3, mech.n_reactions), "arrhenius", state.device)
+        _check(_lib.pj_eval_adjoint_arrhenius(mech.handle, FORMS[form], LAYOUTS[layout], n, _ptr(state),
+                                              _ptr(param), _ptr(arrhenius), _ptr(v), _ptr(jtv), _ptr(grad),
+                                              _ptr(dstate), _stream(stream)), "pj_eval_adjoint_arrhenius")
+        return jtv, grad
     _check(_lib.pj_eval_adjoint(mech.handle, FORMS[form], LAYOUTS[layout], n, _ptr(state), _ptr(param),
                                 _ptr(v), _ptr(jtv), _ptr(grad), _ptr(dstate), _stream(stream)),
            "pj_eval_adjoint")
@@ -372,24 +393,26 @@ def eval_adjoint(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, v: t
 
 class SourceTerms(torch.autograd.Function):
     """dPhi/dt as a differentiable function of the states and of the
-    mechanism's Arrhenius parameters: forward runs pj_eval_source with the
-    given (ln A, b, Ea/R) installed in the mechanism, backward runs
-    pj_eval_adjoint.  The parameter P (CONP) or V (CONV) gets no gradient."""
+    Arrhenius parameters (ln A, b, Ea/R): forward runs
+    pj_eval_source_arrhenius with the given parameters, backward runs
+    pj_eval_adjoint_arrhenius with the same (saved) parameters, so each graph
+    differentiates at its own parameters; the mechanism's tables are never
+    written and the host never waits.  The parameter P (CONP) or V (CONV)
+    gets no gradient."""
 
     @staticmethod
     def forward(ctx, state, param, lnA, b, theta, mech, form, layout):
-        mech.set_arrhenius(lnA.detach().cpu().numpy(), b.detach().cpu().numpy(),
-                           theta.detach().cpu().numpy())
+        arr = torch.stack([lnA.detach(), b.detach(), theta.detach()]).to(
+            device=state.device, dtype=torch.float64).contiguous()
         ctx.mech, ctx.form, ctx.layout = mech, form, layout
-        ctx.save_for_backward(state, param)
-        return eval_source(mech, state, param, form, layout)
+        ctx.save_for_backward(state, param, arr)
+        return eval_source(mech, state, param, form, layout, arrhenius=arr)
 
     @staticmethod
     def backward(ctx, v):
-        state, param = ctx.saved_tensors
-        jtv, grad = eval_adjoint(ctx.mech, state, param, v.contiguous(), ctx.form, ctx.layout)
-        g = grad.to(v.device)
-        return jtv, None, g[0], g[1], g[2], None, None, None
+        state, param, arr = ctx.saved_tensors
+        jtv, grad = eval_adjoint(ctx.mech, state, param, v.contiguous(), ctx.form, ctx.layout, arrhenius=arr)
+        return jtv, None, grad[0], grad[1], grad[2], None, None, None
 
 
 def source_terms(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, lnA: torch.Tensor,

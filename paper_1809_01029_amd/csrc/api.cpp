@@ -69,7 +69,8 @@ namespace {
 
 pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, int64_t n,
                const double* state, const double* param, double* dstate, double* jac,
-               pj_stream stream, const double* vin = nullptr, double* grad = nullptr) {
+               pj_stream stream, const double* vin = nullptr, double* grad = nullptr,
+               const double* arr = nullptr) {
     if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
     if (form != PJ_CONP && form != PJ_CONV) return fail(PJ_E_INVALID, "bad form");
     if (layout != PJ_LAYOUT_F && layout != PJ_LAYOUT_C) return fail(PJ_E_INVALID, "bad layout");
@@ -96,7 +97,11 @@ pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, in
         kmode = pj::MODE_SPARSE_LS;
         S = std::min(S, 4);
     }
-    hipError_t e = pj::launch(m.dm, kmode, form, layout, S, n, state, param, dstate, jac, vin, grad,
+    // a call with its own Arrhenius parameters runs on a copy of the device
+    // description that points at them (the mechanism itself is not touched)
+    pj::DevMech dm = m.dm;
+    dm.arr = arr;
+    hipError_t e = pj::launch(dm, kmode, form, layout, S, n, state, param, dstate, jac, vin, grad,
                               m.adj_grad_in_lds ? 1 : 0, m.waves[mode], pj::lds_bytes(m.dm, mode, S, m.waves[mode],
                               m.adj_grad_in_lds), (hipStream_t)stream);
     if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -230,6 +235,27 @@ pj_status pj_eval_adjoint(const pj_mech* mech, pj_form form, pj_layout layout, i
                 stream, d_v, d_grad_or_null);
 }
 
+pj_status pj_eval_source_arrhenius(const pj_mech* mech, pj_form form, pj_layout layout, int64_t n_states,
+                                   const double* d_state, const double* d_param, const double* d_arrhenius,
+                                   double* d_dstate, pj_stream stream) {
+    if (!d_arrhenius) return fail(PJ_E_INVALID, "NULL Arrhenius parameters");
+    return eval(mech, pj::MODE_SRC, form, layout, n_states, d_state, d_param, d_dstate, nullptr, stream,
+                nullptr, nullptr, d_arrhenius);
+}
+
+pj_status pj_eval_adjoint_arrhenius(const pj_mech* mech, pj_form form, pj_layout layout, int64_t n_states,
+                                    const double* d_state, const double* d_param, const double* d_arrhenius,
+                                    const double* d_v, double* d_jtv, double* d_grad_or_null,
+                                    double* d_dstate_or_null, pj_stream stream) {
+    if (!d_arrhenius) return fail(PJ_E_INVALID, "NULL Arrhenius parameters");
+    if (n_states == 0 && mech && d_grad_or_null && mech->m.dbuf) {
+        hipError_t e = pj::zero_async(d_grad_or_null, 3 * (int64_t)mech->m.nr, (hipStream_t)stream);
+        if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("zeroing the gradient failed: ") + hipGetErrorString(e));
+    }
+    return eval(mech, pj::MODE_ADJ, form, layout, n_states, d_state, d_param, d_dstate_or_null, d_jtv,
+                stream, d_v, d_grad_or_null, d_arrhenius);
+}
+
 pj_status pj_mech_set_arrhenius(pj_mech* mech, const double* lnA, const double* b, const double* theta) {
     if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
     pj::Mechanism& m = mech->m;
@@ -273,8 +299,8 @@ pj_status pj_mech_set_launch(pj_mech* mech, int states_per_group, int waves_per_
     if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
     if (states_per_group && !pow2_upto(states_per_group, MAX_S))
         return fail(PJ_E_INVALID, "states_per_group must be 0 or a power of two up to 64");
-    if (waves_per_group && !pow2_upto(waves_per_group, MAX_WAVES))
-        return fail(PJ_E_INVALID, "waves_per_group must be 0, 1, 2, 4 or 8");
+    if (waves_per_group < 0 || waves_per_group > MAX_WAVES)
+        return fail(PJ_E_INVALID, "waves_per_group must be 0 (automatic) or 1 to 8");
     mech->m.user_S = states_per_group;
     mech->m.user_waves = waves_per_group;
     if (mech->m.dbuf) {
@@ -337,7 +363,7 @@ pj_status autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int6
     float best = -1.0f;
     std::string err;
     for (int S = 1; S <= maxS && err.empty(); S *= 2) {
-        for (int w = S > 64 ? S / 64 : 1; w <= MAX_WAVES; w *= 2) {
+        for (int w = 1; w <= MAX_WAVES; ++w) {
             const int64_t l = pj::lds_bytes(m.dm, mode, S, w, gr);
             if (l > m.lds_max) continue;
             auto go = [&]() {

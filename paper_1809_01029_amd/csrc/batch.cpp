@@ -262,9 +262,8 @@ pj_status pj_batch_set_launch(pj_batch* b, int mode, int states_per_group, int w
     if (!batch_mode(mode)) return fail(PJ_E_INVALID, "bad mode");
     if (states_per_group != 0 && states_per_group != 1 && states_per_group != 2 && states_per_group != 4)
         return fail(PJ_E_INVALID, "states_per_group must be 0, 1, 2 or 4");
-    if (waves_per_group != 0 && waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4 &&
-        waves_per_group != 8)
-        return fail(PJ_E_INVALID, "waves_per_group must be 0, 1, 2, 4 or 8");
+    if (waves_per_group < 0 || waves_per_group > 8)
+        return fail(PJ_E_INVALID, "waves_per_group must be 0 (automatic) or 1 to 8");
     b->user_S[mode] = states_per_group;
     b->user_W[mode] = waves_per_group;
     b->drop_graph();
@@ -379,7 +378,7 @@ pj_status pj_batch_autotune(pj_batch* b, int mode, pj_form form, pj_layout layou
     // segment at each mechanism's current shape (S = 0); the best persistent
     // shape is kept for the mode either way
     for (int S = 1; S <= 8 && err == PJ_OK; S *= 2)
-        for (int W = 1; W <= 8 && err == PJ_OK; W *= 2) {
+        for (int W = 1; W <= 8 && err == PJ_OK; ++W) {
             const bool segs_each = S == 8;
             if (segs_each && W > 1) break;
             if (!segs_each && batch_lds(b, mode, S, W) > mx) continue;

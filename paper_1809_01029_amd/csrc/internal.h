@@ -135,6 +135,8 @@ struct DevMech {
     const int32_t* orig;      // [nr] description index of each kernel-order reaction
     const uint16_t* col_idx;  // [nnz]
     const int32_t* dense_rows;// [n_dense_rows] species index k of bath-dense rows
+    const double* arr;        // NULL, or one call's Arrhenius parameters [ln A (nr), b (nr),
+                              // Ea/R (nr)] in description order, in place of the tables
 };
 
 struct Mechanism {

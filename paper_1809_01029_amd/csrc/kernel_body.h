@@ -79,6 +79,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "internal.h"
 
 namespace pj {
@@ -423,7 +425,14 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 spc[a] = rr.sp[a];
                 nu[a] = info_nu(w, a);
             }
-            const double lnA = rr.lnA, bexp = rr.b, th = rr.theta;
+            double lnA = rr.lnA, bexp = rr.b, th = rr.theta;
+            if (dm.arr) {
+                // this call's parameters (description order) instead of the tables
+                const int o = dm.orig[p];
+                lnA = dm.arr[o];
+                bexp = dm.arr[dm.nr + o];
+                th = dm.arr[2 * dm.nr + o];
+            }
             double lnkf = lnA + bexp * lnT - th * invT;
             // a rate constant tabulated in pressure: the main expression is a factor on it
             double dlkt_dT = 0.0, dlkt_dP = 0.0;
@@ -1015,17 +1024,29 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_batch_kernel(const BatchSeg* _
     }
 }
 
+// Allow a kernel the device's whole LDS per workgroup, once per device (the
+// attribute belongs to the function, not to a launch).
+inline hipError_t allow_full_lds(const void* fn, std::atomic<uint64_t>& done) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = dev < 64 ? (1ull << dev) : 0;
+    if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+    int mx = 0;
+    e = hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e == hipSuccess) e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_acq_rel);
+    return e;
+}
+
 template <int FORM, int LAYOUT, int MODE, int S, bool EXT>
 static hipError_t launch_t(const DevMech& dm, int64_t n, const double* state, const double* param,
                            double* dstate, double* jac, const double* vin, double* grad,
                            int grad_in_lds, int waves, int64_t lds, hipStream_t stream) {
     auto k = pj_kernel<FORM, LAYOUT, MODE, S, EXT>;
     if (lds > 65536) {
-        // allow the kernel the device's whole LDS per workgroup
-        int dev = 0, mx = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        static std::atomic<uint64_t> done{0};
+        hipError_t e = allow_full_lds((const void*)k, done);
         if (e != hipSuccess) return e;
     }
     // one workgroup per group of S states, rounded down to a multiple of 8
@@ -1050,10 +1071,8 @@ static hipError_t launch_batch_t(int waves, int64_t lds, const BatchSeg* segs, i
                                  int64_t gr_off, hipStream_t stream) {
     auto k = pj_batch_kernel<FORM, LAYOUT, MODE, S, EXT>;
     if (lds > 65536) {
-        int dev = 0, mx = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+        static std::atomic<uint64_t> done{0};
+        hipError_t e = allow_full_lds((const void*)k, done);
         if (e != hipSuccess) return e;
     }
     // a persistent grid over the segments' groups (a multiple of 8, the XCD count)

@@ -626,6 +626,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.ccs_pos = (m.opts & PJ_OPT_CCS) ? (const uint16_t*)P(o_ccs) : nullptr;
     dm.dmap_rm = (const uint16_t*)P(o_dmrm);
     dm.dmap_cm = (const uint16_t*)P(o_dmcm);
+    dm.arr = nullptr;
     dm.approx = (m.opts & PJ_OPT_APPROX_JACOBIAN) ? 1 : 0;
     dm.lsearch = (m.opts & PJ_OPT_LINEAR_SEARCH) ? 1 : 0;
     dm.ext = 0;

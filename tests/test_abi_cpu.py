@@ -135,11 +135,14 @@ def test_launch_shape_and_autotune_argument_checks(api, tmp_path):
     mech = api.Mechanism(_write(tmp_path, synth.dumps(m)), upload=False)
     h = mech.handle
     dummy = ctypes.c_void_p(16)
-    # states per workgroup: powers of two up to 64; waves: 1, 2, 4, 8
+    # states per workgroup: powers of two up to 64; waves: 1 to 8
     for S in (1, 2, 4, 8, 16, 32, 64):
         assert lib.pj_mech_set_launch(h, S, 1) == 0
         assert mech.launch_shape(1) == (S, 1)
-    for S, W in ((3, 1), (128, 1), (-1, 1), (4, 3), (4, 16)):
+    for W in range(1, 9):
+        assert lib.pj_mech_set_launch(h, 2, W) == 0
+        assert mech.launch_shape(1) == (2, W)
+    for S, W in ((3, 1), (128, 1), (-1, 1), (4, 9), (4, 16), (4, -1)):
         assert lib.pj_mech_set_launch(h, S, W) == 1
     assert lib.pj_mech_set_launch(h, 0, 0) == 0
     # autotune: argument errors are reported before any device work
@@ -197,9 +200,10 @@ def test_batch_argument_checks(api, tmp_path):
     assert lib.pj_batch_add(b, mech.handle, -1, dummy, dummy, dummy, None, None, None) == 1
     assert lib.pj_batch_add(b, mech.handle, 4, dummy, dummy, dummy, None, None, None) == 0
     assert lib.pj_batch_size(b) == 1
-    for mode, S, W in ((2, 1, 1), (1, 8, 1), (1, 3, 1), (1, 1, 3)):
+    for mode, S, W in ((2, 1, 1), (1, 8, 1), (1, 3, 1), (1, 1, 9), (1, 1, -1)):
         assert lib.pj_batch_set_launch(b, mode, S, W) == 1
     assert lib.pj_batch_set_launch(b, 1, 2, 4) == 0
+    assert lib.pj_batch_set_launch(b, 1, 2, 7) == 0
     # strategy: one persistent launch (0, the default) or one per segment (1)
     assert lib.pj_batch_strategy(b, 1) == 0
     assert lib.pj_batch_set_strategy(b, 1, 2) == 1

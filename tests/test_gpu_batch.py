@@ -173,10 +173,10 @@ def test_batch_autotune(torch_cuda, api, mech_dir):
         # one launch per segment won; the best persistent shape is kept
         assert W == 0 and b.strategy("sparse")
         Sp, Wp = b.launch_shape("sparse")
-        assert Sp in (1, 2, 4) and Wp in (1, 2, 4, 8)
+        assert Sp in (1, 2, 4) and 1 <= Wp <= 8
     else:
         assert not b.strategy("sparse")
-        assert b.launch_shape("sparse") == (S, W) and S in (1, 2, 4) and W in (1, 2, 4, 8)
+        assert b.launch_shape("sparse") == (S, W) and S in (1, 2, 4) and 1 <= W <= 8
     for sg in segs:
         if sg["out"] is not None:
             sg["out"].zero_()

@@ -194,7 +194,7 @@ def test_autotune(torch_cuda, api, mode, mech_dir):
     note(f"autotune {mode}: S={S} waves={W} {ms:.4f} ms")
     mi = api.MODES[mode]
     assert mech.launch_shape(mi) == (S, W)
-    assert S in (1, 2, 4, 8, 16, 32, 64) and W in (1, 2, 4, 8) and ms > 0
+    assert S in (1, 2, 4, 8, 16, 32, 64) and 1 <= W <= 8 and ms > 0
     o = oracle.Oracle(path)
     f_o, f_s = o.source(x, p, "conp", bound=True)
     if mode == "source":
