@@ -196,6 +196,44 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
 
 
+def fp64_calibration(n=1 << 22, reps=16):
+    """The four launches of pj_calibrate_fp64 (exp, log, log10, loop alone)
+    whose FP64 counters give the device's weight of each function."""
+    import torch
+    from paper_1809_01029_amd import api
+    x = torch.linspace(0.5, 1.5, n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    res = {}
+    for fn in ("exp", "log", "log10", "none"):
+        api.calibrate_fp64(fn, x, reps, out=y)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        api.calibrate_fp64(fn, x, reps, out=y)
+        b.record()
+        torch.cuda.synchronize()
+        res[fn] = round(a.elapsed_time(b), 4)
+    print(json.dumps({"calibration_calls": n * reps, "ms": res}), flush=True)
+
+
+def fp64_weights():
+    """FP64 operations of one call of the device's exp, log and log10, from
+    the committed counter summary of the calibration launches, or None."""
+    path = os.path.join(ROOT, "profiles", "fp64_transcendental_weights.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        return {f: float(kv[f"w_{f}"]) for f in ("exp", "log", "log10")}
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +252,8 @@ def main():
                     help="S,W: fix the launch shape (states and waves per workgroup) instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (traffic-counter reference)")
+    ap.add_argument("--fp64-calibration", action="store_true",
+                    help="run only the FP64 weight calibration launches of exp, log and log10")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -223,6 +263,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.fp64_calibration:
+        fp64_calibration()
         return
 
     import numpy as np
@@ -307,7 +350,8 @@ def main():
         if not args.no_autotune:
             api.autotune(mech, xs, ps, args.form, args.layout, mode="source", reps=2, stream=stream)
         t = timeit(lambda: api.eval_source(mech, xs, ps, args.form, args.layout, out=out_src, stream=stream))
-        variants["source_only"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3)}
+        variants["source_only"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3),
+                                   "launch_shape": list(mech.launch_shape(0))}
         del out_src
         if N * N * n * 8 < 60e9:
             dshape = (N, N, n) if args.layout == "F" else (n, N, N)
@@ -316,9 +360,28 @@ def main():
                 api.autotune(mech, xs, ps, args.form, args.layout, mode="dense", reps=1, stream=stream)
             t = timeit(lambda: api.eval_jacobian_dense(mech, xs, ps, args.form, args.layout, out=dj,
                                                        dstate=dstate, stream=stream), k=3)
-            variants["dense_jacobian"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3),
-                                          "hbm_GBps": (8 * (2 * N + 1) + 8 * N * N) * n / (t * 1e-3) / 1e9}
+            db = (8 * (2 * N + 1) + 8 * N * N) * n
+            variants["dense_jacobian"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3), "layout": args.layout,
+                                          "hbm_GBps": db / (t * 1e-3) / 1e9,
+                                          "frac": round(db / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             del dj
+            # the other state layout (F: [s + n (i + N j)]; C: [s][i][j])
+            ol = "C" if args.layout == "F" else "F"
+            xo, po = synth.pack_state(st, args.form, ol)
+            xso, pso = torch.from_numpy(xo).cuda(), torch.from_numpy(po).cuda()
+            del xo
+            dj = torch.empty((N, N, n) if ol == "F" else (n, N, N), dtype=torch.float64, device="cuda")
+            do = torch.empty_like(xso)
+            if not args.no_autotune:
+                api.autotune(mech, xso, pso, args.form, ol, mode="dense", reps=1, stream=stream)
+            t = timeit(lambda: api.eval_jacobian_dense(mech, xso, pso, args.form, ol, out=dj, dstate=do,
+                                                       stream=stream), k=3)
+            variants[f"dense_jacobian_layout_{ol}"] = {
+                "ms": round(t, 4), "states_per_s": n / (t * 1e-3), "hbm_GBps": db / (t * 1e-3) / 1e9,
+                "frac": round(db / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "launch_shape": list(mech.launch_shape(2))}
+            del dj, xso, pso, do
+            if not args.no_autotune:
+                api.autotune(mech, xs, ps, args.form, args.layout, mode="dense", reps=1, stream=stream)
         other = "conv" if args.form == "conp" else "conp"
         x2, p2 = synth.pack_state(st, other, args.layout)
         xs2, ps2 = torch.from_numpy(x2).cuda(), torch.from_numpy(p2).cuda()
@@ -362,6 +425,38 @@ def main():
                                           "launch_shape": list(mech53.launch_shape(1))}
             del xs4, ps4, jac4, d4
             mech53.close()
+            # the 360-species configuration at its full size (16,384 states,
+            # T 700..1800 K, P 10..60 atm): source terms + sparse Jacobian
+            w360 = synth.WORKLOADS["ns360"]
+            m360 = synth.workload_mechanism("ns360")
+            p360 = os.path.join(tmp, "ns360.pjm")
+            synth.write_mechanism(m360, p360)
+            st360 = synth.make_states(m360, w360.n_states, w360.state_seed, T_range=w360.T_range,
+                                      P_range_atm=w360.P_range_atm)
+            x7, p7 = synth.pack_state(st360, args.form, args.layout)
+            del st360
+            mech360 = api.load_mechanism(p360)
+            xs7, ps7 = torch.from_numpy(x7).cuda(), torch.from_numpy(p7).cuda()
+            n7 = w360.n_states
+            jac7 = torch.empty((mech360.nnz, n7) if args.layout == "F" else (n7, mech360.nnz), dtype=torch.float64,
+                               device="cuda")
+            d7 = torch.empty_like(xs7)
+            if not args.no_autotune:
+                api.autotune(mech360, xs7, ps7, args.form, args.layout, mode="sparse", reps=1, stream=stream)
+            t = timeit(lambda: api.eval_jacobian_sparse(mech360, xs7, ps7, args.form, args.layout, out=jac7,
+                                                        dstate=d7, stream=stream), k=5)
+            if not args.no_autotune:
+                api.autotune(mech360, xs7, ps7, args.form, args.layout, mode="source", reps=1, stream=stream)
+            ts = timeit(lambda: api.eval_source(mech360, xs7, ps7, args.form, args.layout, out=d7, stream=stream))
+            b7 = 8 * (mech360.N + 1) + 8 * mech360.N + 8 * mech360.nnz
+            variants["ns360_16k_sparse"] = {"ms": round(t, 4), "states_per_s": n7 / (t * 1e-3), "nnz": mech360.nnz,
+                                            "bytes_per_state": b7,
+                                            "hbm_frac": round(b7 * n7 / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                            "launch_shape": list(mech360.launch_shape(1)),
+                                            "source_only_ms": round(ts, 4),
+                                            "source_launch_shape": list(mech360.launch_shape(0))}
+            del xs7, ps7, jac7, d7
+            mech360.close()
         # adjoint (J^T v + Arrhenius-parameter sums) on the same batch
         if not args.no_autotune:
             api.autotune(mech, xs, ps, args.form, args.layout, mode="adjoint", reps=1, stream=stream)
@@ -492,16 +587,22 @@ def main():
         def run_oracle(ix):
             o.source(xc[ix], pc[ix], args.form)
             o.jacobian(xc[ix], pc[ix], args.form)
-        # one host core, then every core of the host's share (the oracle's
-        # C calls release the interpreter lock, so threads run in parallel)
+        # one host core on a tenth of the sample, then every core of the
+        # host's share on the whole sample, 10 times (the paper's mean of 10
+        # runs; the oracle's C calls release the interpreter lock, so threads
+        # run in parallel)
+        k1 = max(1, k // 10)
         t0 = time.perf_counter()
-        run_oracle(np.arange(k))
-        dt1 = time.perf_counter() - t0
+        run_oracle(np.arange(k1))
+        dt1 = (time.perf_counter() - t0) * k / k1
         threads = max(1, min(16, os.cpu_count() or 1))
-        t0 = time.perf_counter()
+        runs = []
         with concurrent.futures.ThreadPoolExecutor(threads) as ex:
-            list(ex.map(run_oracle, np.array_split(np.arange(k), threads)))
-        dt = time.perf_counter() - t0
+            for _ in range(10):
+                t0 = time.perf_counter()
+                list(ex.map(run_oracle, np.array_split(np.arange(k), threads)))
+                runs.append(time.perf_counter() - t0)
+        dt = float(np.mean(runs))
         host = platform.processor() or platform.machine()
         try:
             with open("/proc/cpuinfo") as fh:
@@ -510,9 +611,28 @@ def main():
             pass
         cpu = {"value": k / dt, "unit": "states/s", "cores": threads, "kind": "oracle",
                "serial_value": k / dt1, "host_cpu": host, "host_cpus_visible": os.cpu_count(),
+               "runs": 10, "run_s": [round(r, 3) for r in runs],
                "sample": f"first {k} of the {n} {args.workload} states: source terms + analytical "
-                         f"Jacobian (dense, holding the CSR values), FP64 oracle on {threads} host threads "
-                         f"{dt:.1f} s; on one thread {dt1:.1f} s (serial_value)"}
+                         f"Jacobian (dense, holding the CSR values), FP64 oracle on {threads} host threads, "
+                         f"mean of 10 runs {dt:.2f} s; one thread on the first {k1} states, scaled to {k} "
+                         f"({dt1:.1f} s, serial_value)"}
+        # operation count of the source terms (the oracle's definitions without
+        # the derivatives, ln T once) for the FP64 roofline of the source-only
+        # kernel, weighted by the device's own exp / log / log10
+        ops = [o.source_ops(xc[i], pc[i], args.form) for i in range(min(8, k))]
+        wts = fp64_weights()
+        if "source_only" in variants:
+            so = variants["source_only"]
+            if wts is None:
+                so["roofline"] = None
+            else:
+                fl = float(np.mean([q["flops"] + wts["exp"] * q["exp"] + wts["log"] * q["log"]
+                                    + wts["log10"] * q["log10"] for q in ops]))
+                ach = fl * n / (so["ms"] * 1e-3) / 1e12
+                so["roofline"] = {"bound": "fp64", "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
+                                  "flops_per_state": round(fl, 1), "ops_per_state": ops[0],
+                                  "weights": wts}
         log(f"cpu oracle: {cpu['value']:.2f} states/s on {threads} threads, {k / dt1:.2f} on one, {k} states")
 
     out = {

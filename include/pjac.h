@@ -327,6 +327,19 @@ const char* pj_batch_last_error(void);
 /* Thread-local description of the last error ("" if none). */
 const char* pj_last_error(void);
 
+/*
+ * Calibration of the FP64 operation weights of the device's own exp (fn 0),
+ * log (1) and log10 (2), or of the loop alone (3): d_out[i] = sum over
+ * r < reps of f(d_in[i] + r 1e-3), n values on `stream` (device arrays of n
+ * doubles, caller-owned).  Profiling the four launches with the hardware's
+ * FP64 counters gives the arithmetic one call of each function executes,
+ * which weights the transcendentals in the source terms' operation count
+ * (the FP64 roofline of Sec. 3.5.1's source-term timings).  PJ_E_INVALID
+ * for a bad fn, n < 0, reps < 1 or NULL arrays; PJ_E_DEVICE if the launch
+ * fails.
+ */
+pj_status pj_calibrate_fp64(int fn, int64_t n, int reps, const double* d_in, double* d_out, pj_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,7 +68,7 @@ def _load():
         lib.ora_jvp_cs.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, ctypes.c_double, D]
         lib.ora_source_ld.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D]
         lib.ora_jacobian_ld.argtypes = [P, ctypes.c_int, ctypes.c_long, D, D, D, ctypes.c_int]
-        lib.ora_source_ops.argtypes = [P, ctypes.c_int, D, ctypes.c_double, D]
+        lib.ora_source_ops.argtypes = [P, ctypes.c_int, D, ctypes.c_double, D, D]
         _lib = lib
     return _lib
 
@@ -163,13 +163,18 @@ class Oracle:
         self._lib.ora_jacobian_ld(self._h, _FORMS[form], x.shape[0], _d(x), _d(p), _d(J), int(approx))
         return J
 
-    def source_ops(self, x, p: float, form="conp"):
+    def source_ops(self, x, p: float, form="conp", values: bool = False):
         """Arithmetic operations of one state's source terms as the oracle
-        writes them: dict(flops = + - * / count, exp, log)."""
+        writes them, without the derivatives it forms along the way for the
+        Jacobian and the parameter gradient, a transcendental of a repeated
+        argument counted once: dict(flops = + - * / count, exp, log, log10)
+        (and, with ``values``, the source terms of that evaluation)."""
         x = _f64(x).reshape(-1)
-        out = np.zeros(3)
-        self._lib.ora_source_ops(self._h, _FORMS[form], _d(x), float(p), _d(out))
-        return {"flops": int(out[0]), "exp": int(out[1]), "log": int(out[2])}
+        out = np.zeros(4)
+        f = np.zeros(self.N)
+        self._lib.ora_source_ops(self._h, _FORMS[form], _d(x), float(p), _d(out), _d(f))
+        ops = {"flops": int(out[0]), "exp": int(out[1]), "log": int(out[2]), "log10": int(out[3])}
+        return (ops, f) if values else ops
 
     def jacobian_cs(self, x, p, form="conp", hrel: float = 1e-30, approx: bool = False):
         x = _f64(x).reshape(-1, self.N)

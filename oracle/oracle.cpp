@@ -62,6 +62,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <set>
 #include <sstream>
 #include <string>
 #include <utility>
@@ -149,11 +150,24 @@ inline Err log10(Err a) {
 }
 
 // Operation counting: every + - * / of two values (or a value and a
-// constant) counts one, exp, log and log10 count separately.
+// constant) counts one, exp, log and log10 count separately.  A
+// transcendental of an argument already taken in the same evaluation counts
+// once (a common subexpression: ln T enters every rate constant and every
+// species entropy as written here).
 struct OpCount {
-    double flops = 0, exps = 0, logs = 0;
+    double flops = 0, exps = 0, logs = 0, log10s = 0;
+    std::set<std::pair<int, uint64_t>> seen;
+    bool fresh(int fn, double arg) {
+        uint64_t bits;
+        std::memcpy(&bits, &arg, sizeof bits);
+        return seen.insert({fn, bits}).second;
+    }
 };
 thread_local OpCount g_ops;
+// Set while counting the operations of the source terms alone: the
+// evaluation then skips the derivatives it otherwise forms along the way
+// (for the Jacobian and the parameter gradient).  Values are unchanged.
+thread_local bool g_values_only = false;
 struct Cnt {
     double v;
     Cnt() : v(0) {}
@@ -166,9 +180,9 @@ inline Cnt operator*(Cnt a, Cnt b) { g_ops.flops += 1; return Cnt(a.v * b.v); }
 inline Cnt operator/(Cnt a, Cnt b) { g_ops.flops += 1; return Cnt(a.v / b.v); }
 inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
 inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
-inline Cnt exp(Cnt a) { g_ops.exps += 1; return Cnt(std::exp(a.v)); }
-inline Cnt log(Cnt a) { g_ops.logs += 1; return Cnt(std::log(a.v)); }
-inline Cnt log10(Cnt a) { g_ops.logs += 1; return Cnt(std::log10(a.v)); }
+inline Cnt exp(Cnt a) { if (g_ops.fresh(0, a.v)) g_ops.exps += 1; return Cnt(std::exp(a.v)); }
+inline Cnt log(Cnt a) { if (g_ops.fresh(1, a.v)) g_ops.logs += 1; return Cnt(std::log(a.v)); }
+inline Cnt log10(Cnt a) { if (g_ops.fresh(2, a.v)) g_ops.log10s += 1; return Cnt(std::log10(a.v)); }
 
 inline double re(double x) { return x; }
 inline double re(const std::complex<double>& x) { return x.real(); }
@@ -310,6 +324,7 @@ Thermo<S> species_thermo(const Species& sp, S T) {
           + S(a[4]) * T4 / S(5.0) + S(a[5]) / T;
     t.s = S(a[0]) * log(T) + S(a[1]) * T + S(a[2]) * T2 / S(2.0) + S(a[3]) * T3 / S(3.0)
           + S(a[4]) * T4 / S(4.0) + S(a[6]);
+    if (g_values_only) return t;
     t.dcp = S(a[1]) + S(2.0 * a[2]) * T + S(3.0 * a[3]) * T2 + S(4.0 * a[4]) * T3;
     t.dh = S(a[1]) / S(2.0) + S(2.0 * a[2]) * T / S(3.0) + S(3.0 * a[3]) * T2 / S(4.0)
            + S(4.0 * a[4]) * T3 / S(5.0) - S(a[5]) / T2;
@@ -526,7 +541,7 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
         dka_dT = ka * (bb / T + tt / (T * T));
     } else {
         ka = arrhenius(r.lnA, r.b, r.theta, T);
-        dka_dT = ka * (S(r.b) / T + S(r.theta) / (T * T));
+        if (!g_values_only) dka_dT = ka * (S(r.b) / T + S(r.theta) / (T * T));
     }
     S dlnk_dlnP(0.0);   // pressure dependence of k_f at fixed T (P-Log, Chebyshev)
     e.kf = ka;
@@ -535,7 +550,7 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
         LnK<S> t = r.type == T_PLOG ? plog_lnk(r, T, st.P) : cheb_lnk(r, T, st.P);
         S kt = exp(t.v);
         e.kf = ka * kt;
-        e.dkf_dT = dka_dT * kt + e.kf * t.dT;
+        if (!g_values_only) e.dkf_dT = dka_dT * kt + e.kf * t.dT;
         dlnk_dlnP = t.dlnP;
     }
     // falloff forms: the low-pressure limit; a chemically activated reaction's
@@ -543,7 +558,7 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
     S k0(0.0), dk0_dT(0.0);
     if (r.falloff()) {
         k0 = arrhenius(r.lnA0, r.b0, r.theta0, T);
-        dk0_dT = k0 * (S(r.b0) / T + S(r.theta0) / (T * T));
+        if (!g_values_only) dk0_dT = k0 * (S(r.b0) / T + S(r.theta0) / (T * T));
     }
     if (r.chemact) {
         e.kf = k0;
@@ -556,20 +571,22 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
     int sum_nu = 0;
     for (auto& p : r.reac) {
         sum_nu_g = sum_nu_g - S((double)p.second) * (th[p.first].h - th[p.first].s);
-        sum_nu_dg = sum_nu_dg - S((double)p.second) * (th[p.first].dh - th[p.first].ds);
+        if (!g_values_only) sum_nu_dg = sum_nu_dg - S((double)p.second) * (th[p.first].dh - th[p.first].ds);
         sum_nu -= p.second;
     }
     for (auto& p : r.prod) {
         sum_nu_g = sum_nu_g + S((double)p.second) * (th[p.first].h - th[p.first].s);
-        sum_nu_dg = sum_nu_dg + S((double)p.second) * (th[p.first].dh - th[p.first].ds);
+        if (!g_values_only) sum_nu_dg = sum_nu_dg + S((double)p.second) * (th[p.first].dh - th[p.first].ds);
         sum_nu += p.second;
     }
     if (r.rev) {
         S lnKc = -sum_nu_g + S((double)sum_nu) * log(S(PREF) / (S(RU) * T));
         S Kc = exp(lnKc);
-        S dlnKc_dT = -sum_nu_dg - S((double)sum_nu) / T;
         e.kr = e.kf / Kc;
-        e.dkr_dT = e.dkf_dT / Kc - e.kf * (Kc * dlnKc_dT) / (Kc * Kc);
+        if (!g_values_only) {
+            S dlnKc_dT = -sum_nu_dg - S((double)sum_nu) / T;
+            e.dkr_dT = e.dkf_dT / Kc - e.kf * (Kc * dlnKc_dT) / (Kc * Kc);
+        }
     } else {
         e.kr = S(0.0);
         e.dkr_dT = S(0.0);
@@ -600,18 +617,18 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
         e.c = S(1.0);
     } else if (r.type == T_THREEBODY) {
         e.c = M;
-        for (int k = 0; k < ns; ++k) e.dc_dC[k] = S(alpha[k] - 1.0);
-        e.dc_dCtot = S(1.0);
+        if (!g_values_only) {
+            for (int k = 0; k < ns; ++k) e.dc_dC[k] = S(alpha[k] - 1.0);
+            e.dc_dCtot = S(1.0);
+        }
     } else {
         S Pr = k0 * M / ka;
-        S dPr_dT = M * (dk0_dT * ka - k0 * dka_dT) / (ka * ka);
+        S dPr_dT(0.0);
+        if (!g_values_only) dPr_dT = M * (dk0_dT * ka - k0 * dka_dT) / (ka * ka);
         S F(1.0), dF_dPr(0.0), dF_dT(0.0);
         if (r.type == T_TROE) {
             S Fcent = S(1.0 - r.alpha) * exp(-T / S(r.T3)) + S(r.alpha) * exp(-T / S(r.T1))
                       + exp(-S(r.T2) / T);
-            S dFcent_dT = -S(1.0 - r.alpha) / S(r.T3) * exp(-T / S(r.T3))
-                          - S(r.alpha) / S(r.T1) * exp(-T / S(r.T1))
-                          + S(r.T2) / (T * T) * exp(-S(r.T2) / T);
             S L = log10(Fcent);
             S cc = S(-0.4) - S(0.67) * L;
             S nn = S(0.75) - S(1.27) * L;
@@ -620,6 +637,10 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
             S f = A / B;
             S expo = L / (S(1.0) + f * f);       // log10 F
             F = exp(S(LN10) * expo);
+            if (!g_values_only) {
+            S dFcent_dT = -S(1.0 - r.alpha) / S(r.T3) * exp(-T / S(r.T3))
+                          - S(r.alpha) / S(r.T1) * exp(-T / S(r.T1))
+                          + S(r.T2) / (T * T) * exp(-S(r.T2) / T);
             // d f / d log10(Pr) and d f / d L
             S df_dlP = (B - A * S(-0.14)) / (B * B);
             S dA_dL = S(-0.67);
@@ -631,36 +652,46 @@ RxnEval<S> eval_reaction(const Mech& m, const Reaction& r, const State<S>& st,
             dF_dPr = F * dexpo_df * df_dlP / Pr;
             // dF/dT at fixed Pr, through Fcent: dL/dT = dFcent/dT / (Fcent ln10)
             dF_dT = F * S(LN10) * dexpo_dL * dFcent_dT / (Fcent * S(LN10));
+            }
         } else if (r.type == T_SRI) {
             // SRI: F = d (a exp(-b/T) + exp(-T/c))^X T^e, X = 1 / (1 + (log10 Pr)^2)
             S a(r.sri[0]), b(r.sri[1]), cc(r.sri[2]), d(r.sri[3]), ee(r.sri[4]);
             S lP = log10(Pr);
             S X = S(1.0) / (S(1.0) + lP * lP);
             S base = a * exp(-b / T) + exp(-T / cc);
-            S dbase_dT = a * b / (T * T) * exp(-b / T) - exp(-T / cc) / cc;
             F = d * exp(X * log(base)) * exp(ee * log(T));
-            // dX/dPr = -2 log10(Pr) X^2 / (Pr ln 10)
-            dF_dPr = F * log(base) * (S(-2.0) * lP * X * X) / (Pr * S(LN10));
-            dF_dT = F * (X * dbase_dT / base + ee / T);
+            if (!g_values_only) {
+                S dbase_dT = a * b / (T * T) * exp(-b / T) - exp(-T / cc) / cc;
+                // dX/dPr = -2 log10(Pr) X^2 / (Pr ln 10)
+                dF_dPr = F * log(base) * (S(-2.0) * lP * X * X) / (Pr * S(LN10));
+                dF_dT = F * (X * dbase_dT / base + ee / T);
+            }
         }
         S dc_dPr;
         if (r.chemact) {
             // chemically activated: c = F / (1 + Pr) on the rate with k_0
             e.c = F / (S(1.0) + Pr);
-            dc_dPr = dF_dPr / (S(1.0) + Pr) - F / ((S(1.0) + Pr) * (S(1.0) + Pr));
-            e.dc_dT = dc_dPr * dPr_dT + dF_dT / (S(1.0) + Pr);
+            if (!g_values_only) {
+                dc_dPr = dF_dPr / (S(1.0) + Pr) - F / ((S(1.0) + Pr) * (S(1.0) + Pr));
+                e.dc_dT = dc_dPr * dPr_dT + dF_dT / (S(1.0) + Pr);
+            }
         } else {
             // c = F Pr / (1 + Pr), written as F / (1 + 1/Pr): the same value, but its
             // complex-step derivative carries no cancellation when Pr >> 1
             e.c = F / (S(1.0) + S(1.0) / Pr);
-            dc_dPr = F / ((S(1.0) + Pr) * (S(1.0) + Pr)) + Pr / (S(1.0) + Pr) * dF_dPr;
-            e.dc_dT = dc_dPr * dPr_dT + Pr / (S(1.0) + Pr) * dF_dT;
+            if (!g_values_only) {
+                dc_dPr = F / ((S(1.0) + Pr) * (S(1.0) + Pr)) + Pr / (S(1.0) + Pr) * dF_dPr;
+                e.dc_dT = dc_dPr * dPr_dT + Pr / (S(1.0) + Pr) * dF_dT;
+            }
         }
-        for (int k = 0; k < ns; ++k) e.dc_dC[k] = dc_dPr * k0 * S(alpha[k] - 1.0) / ka;
-        e.dc_dCtot = dc_dPr * k0 / ka;
-        Pr_dc_dPr = Pr * dc_dPr;
+        if (!g_values_only) {
+            for (int k = 0; k < ns; ++k) e.dc_dC[k] = dc_dPr * k0 * S(alpha[k] - 1.0) / ka;
+            e.dc_dCtot = dc_dPr * k0 / ka;
+            Pr_dc_dPr = Pr * dc_dPr;
+        }
     }
     e.q = e.c * (e.Rf - e.Rr);
+    if (g_values_only) return e;
     // R = Rf - Rr is proportional to k_f (k_r = k_f / Kc), and k_f to the main
     // Arrhenius factor except for a chemically activated reaction (k_f = k_0);
     // for falloff forms c also depends on that factor through Pr, with
@@ -1076,18 +1107,24 @@ void ora_jacobian_ld(void* h, int form, long n, const double* x, const double* p
 }
 
 // Arithmetic operations of the source terms of one state as the definitions
-// above write them: out = {+ - * / count, exp count, log and log10 count}.
-void ora_source_ops(void* h, int form, const double* x, double param, double* out) {
+// above write them: out = {+ - * / count, exp count, log count, log10 count}.
+// f: the source terms of that evaluation (N values), which must equal
+// ora_source's.
+void ora_source_ops(void* h, int form, const double* x, double param, double* out, double* f) {
     const Mech& m = *static_cast<Mech*>(h);
     int N = m.ns + 1;
     std::vector<Cnt> xx(N);
     for (int i = 0; i < N; ++i) xx[i] = Cnt(x[i]);
     g_ops = OpCount();
+    g_values_only = true;
     Eval<Cnt> ev = evaluate(m, form, xx.data(), Cnt(param), false);
-    (void)ev;
+    g_values_only = false;
     out[0] = g_ops.flops;
     out[1] = g_ops.exps;
     out[2] = g_ops.logs;
+    out[3] = g_ops.log10s;
+    if (f)
+        for (int i = 0; i < N; ++i) f[i] = ev.f[i].v;
 }
 
 // Complex-step Jacobian: column j = Im f(Phi + i h_j e_j) / h_j with

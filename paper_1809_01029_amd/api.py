@@ -68,6 +68,8 @@ _lib.pj_eval_jacobian_dense.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P
 _lib.pj_eval_jacobian_dense.restype = ctypes.c_int
 _lib.pj_eval_adjoint.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P, _P, _P, _P]
 _lib.pj_eval_adjoint.restype = ctypes.c_int
+_lib.pj_calibrate_fp64.argtypes = [ctypes.c_int, _I64, ctypes.c_int, _P, _P, _P]
+_lib.pj_calibrate_fp64.restype = ctypes.c_int
 _lib.pj_eval_source_arrhenius.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P, _P]
 _lib.pj_eval_source_arrhenius.restype = ctypes.c_int
 _lib.pj_eval_adjoint_arrhenius.argtypes = [_P, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P, _P, _P, _P, _P]
@@ -389,6 +391,20 @@ def eval_adjoint(mech: Mechanism, state: torch.Tensor, param: torch.Tensor, v: t
                                 _ptr(v), _ptr(jtv), _ptr(grad), _ptr(dstate), _stream(stream)),
            "pj_eval_adjoint")
     return jtv, grad
+
+
+def calibrate_fp64(fn: str, x: torch.Tensor, reps: int = 16, out: Optional[torch.Tensor] = None,
+                   stream=None) -> torch.Tensor:
+    """pj_calibrate_fp64: sum over r < reps of f(x + r 1e-3) per element, f
+    one of "exp", "log", "log10" or "none" (the loop alone)."""
+    code = {"exp": 0, "log": 1, "log10": 2, "none": 3}[fn]
+    if out is None:
+        out = torch.empty_like(x)
+    _need(x, (x.numel(),), "x", None)
+    _need(out, (x.numel(),), "out", x.device)
+    _check(_lib.pj_calibrate_fp64(code, x.numel(), int(reps), _ptr(x), _ptr(out), _stream(stream)),
+           "pj_calibrate_fp64")
+    return out
 
 
 class SourceTerms(torch.autograd.Function):

@@ -97,6 +97,8 @@ pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, in
         kmode = pj::MODE_SPARSE_LS;
         S = std::min(S, 4);
     }
+    // a call with its own Arrhenius parameters has kernels of its own
+    if (arr) kmode = mode == pj::MODE_SRC ? pj::MODE_SRC_P : pj::MODE_ADJ_P;
     // a call with its own Arrhenius parameters runs on a copy of the device
     // description that points at them (the mechanism itself is not touched)
     pj::DevMech dm = m.dm;

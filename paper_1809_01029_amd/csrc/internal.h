@@ -206,7 +206,14 @@ pj_status upload_mechanism(Mechanism& m, std::string& err);
 
 // kernels.hip (kernel_body.h)
 enum Mode : int { MODE_SRC = 0, MODE_SPARSE = 1, MODE_DENSE = 2, MODE_ADJ = 3,
-                  MODE_SPARSE_LS = 4 /* sparse with run-time slot search; launch shape of MODE_SPARSE */ };
+                  MODE_SPARSE_LS = 4 /* sparse with run-time slot search; launch shape of MODE_SPARSE */,
+                  // source terms / adjoint with the call's own Arrhenius parameters
+                  // (DevMech::arr); launch shapes of MODE_SRC / MODE_ADJ
+                  MODE_SRC_P = 5, MODE_ADJ_P = 6 };
+// the mode whose computation a kernel mode performs
+__host__ __device__ constexpr int base_mode(int m) {
+    return m == MODE_SRC_P ? MODE_SRC : m == MODE_ADJ_P ? MODE_ADJ : m;
+}
 constexpr int N_MODES = 4;        // modes with a launch shape of their own
 constexpr int MAX_S_ADJ = 4;      // states per workgroup of the adjoint mode
 // grad_in_lds: the adjoint keeps its parameter sums in LDS (mode MODE_ADJ only)

@@ -305,10 +305,12 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                                            double* __restrict__ grad,
                                            const bool gr_lds, double* GR, const long qg) {
     extern __shared__ double lds[];
-    constexpr bool JAC = MODE != MODE_SRC;
-    constexpr bool ADJ = MODE == MODE_ADJ;   // jac receives J^T v (state layout)
-    constexpr bool LS = MODE == MODE_SPARSE_LS;   // sparse, slots found by a row search
-    constexpr bool SPARSE = MODE == MODE_SPARSE || LS;
+    constexpr int M = base_mode(MODE);
+    constexpr bool PAR = MODE != M;          // the call's own Arrhenius parameters
+    constexpr bool JAC = M != MODE_SRC;
+    constexpr bool ADJ = M == MODE_ADJ;      // jac receives J^T v (state layout)
+    constexpr bool LS = M == MODE_SPARSE_LS;   // sparse, slots found by a row search
+    constexpr bool SPARSE = M == MODE_SPARSE || LS;
     const int ns = dm.ns, N = dm.N, bath = dm.bath, nnz = dm.nnz;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, nwave = nthr >> 6;
@@ -426,8 +428,11 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 nu[a] = info_nu(w, a);
             }
             double lnA = rr.lnA, bexp = rr.b, th = rr.theta;
-            if (dm.arr) {
-                // this call's parameters (description order) instead of the tables
+            if (PAR) {
+                // this call's parameters (description order) instead of the
+                // tables; a kernel mode of its own, so that the default kernels
+                // carry none of it (their register count sits at an occupancy
+                // step)
                 const int o = dm.orig[p];
                 lnA = dm.arr[o];
                 bexp = dm.arr[dm.nr + o];
@@ -953,7 +958,7 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const
                                                           double* __restrict__ grad,
                                                           const int grad_in_lds) {
     extern __shared__ double lds[];
-    constexpr bool ADJ = MODE == MODE_ADJ;
+    constexpr bool ADJ = base_mode(MODE) == MODE_ADJ;
     const int tid = threadIdx.x, nthr = blockDim.x;
     double* GR = lds + gr_offset(dm, S, nthr >> 6);
     long q0, q1, qstep;
@@ -1054,10 +1059,11 @@ static hipError_t launch_t(const DevMech& dm, int64_t n, const double* state, co
     const int64_t groups = (n + S - 1) / S;
     // the adjoint's workgroups each add their parameter sums to the output
     // once: a bounded, persistent grid keeps those atomics few
-    const int64_t cap = MODE == MODE_ADJ ? 2048 : (1 << 30);
+    constexpr bool ADJ = base_mode(MODE) == MODE_ADJ;
+    const int64_t cap = ADJ ? 2048 : (1 << 30);
     int64_t grid = groups < cap ? groups : cap;
     if (grid >= 8) grid &= ~(int64_t)7;
-    if (MODE == MODE_ADJ && grad) {
+    if (ADJ && grad) {
         hipError_t e = zero_async(grad, 3 * (int64_t)dm.nr, stream);
         if (e != hipSuccess) return e;
     }
@@ -1104,12 +1110,15 @@ hipError_t launch_impl(const DevMech& dm, int mode, int form, int layout, int S,
     PJ_CASE(F, L, M, 16) PJ_CASE(F, L, M, 32) PJ_CASE(F, L, M, 64)
 #define PJ_SA(F, L) PJ_CASE(F, L, MODE_ADJ, 1) PJ_CASE(F, L, MODE_ADJ, 2) PJ_CASE(F, L, MODE_ADJ, 4)
 #define PJ_SL(F, L) PJ_CASE(F, L, MODE_SPARSE_LS, 1) PJ_CASE(F, L, MODE_SPARSE_LS, 2) PJ_CASE(F, L, MODE_SPARSE_LS, 4)
-#define PJ_MODES(F, L) PJ_S(F, L, MODE_SRC) PJ_S(F, L, MODE_SPARSE) PJ_S(F, L, MODE_DENSE) PJ_SA(F, L) PJ_SL(F, L)
+#define PJ_SAP(F, L) PJ_CASE(F, L, MODE_ADJ_P, 1) PJ_CASE(F, L, MODE_ADJ_P, 2) PJ_CASE(F, L, MODE_ADJ_P, 4)
+#define PJ_MODES(F, L) PJ_S(F, L, MODE_SRC) PJ_S(F, L, MODE_SPARSE) PJ_S(F, L, MODE_DENSE) PJ_SA(F, L) PJ_SL(F, L) \
+    PJ_S(F, L, MODE_SRC_P) PJ_SAP(F, L)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_F)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_C)
     PJ_MODES(PJ_CONV, PJ_LAYOUT_F)
     PJ_MODES(PJ_CONV, PJ_LAYOUT_C)
 #undef PJ_MODES
+#undef PJ_SAP
 #undef PJ_SL
 #undef PJ_SA
 #undef PJ_S

@@ -214,3 +214,91 @@ def test_batch_per_segment_launches(torch_cuda, api, form, mode, layout, mech_di
             ref = api.eval_jacobian_sparse(sg["mech"], sg["xs"], sg["ps"], form, layout, dstate=dref)
             torch.cuda.synchronize()
             assert torch.equal(ref, sg["out"]) and torch.equal(dref, sg["d"]), sg["name"]
+
+
+# The ragged configuration at its stated size: 3,000 / 70,000 / 20,000 states
+# of the 13-, 53- and 111-species mechanisms (state seeds 2013, 2053, 2111),
+# v ~ N(0, 1) with seed 7.
+C5 = [("ns13", 3000, 2013), ("ns53", 70000, 2053), ("ns111", 20000, 2111)]
+
+
+@pytest.mark.parametrize("mode", ["source", "adjoint"])
+def test_ragged_batch_full_counts(torch_cuda, api, mode, mech_dir):
+    """The ragged batch at its stated counts through the captured graph
+    (autotuned strategy), replayed twice: every segment sampled (first and
+    last state included) against the oracle; for the adjoint, each
+    segment's batch-summed parameter derivatives equal the sum of two
+    per-mechanism calls over the two halves of its states, and on 64 sampled
+    states they match the oracle's and central differences of the GPU source
+    terms (step 1e-6 relative)."""
+    torch = torch_cuda
+    b = api.Batch()
+    segs = []
+    rng_v = np.random.default_rng(7)
+    for name, n, seed in C5:
+        m, path = workload_file(name, mech_dir)
+        w = synth.WORKLOADS[name]
+        mech = api.load_mechanism(path)
+        st = synth.make_states(m, n, seed, T_range=w.T_range, P_range_atm=w.P_range_atm)
+        x, p = synth.pack_state(st, "conp", "C")
+        v = rng_v.standard_normal(x.shape)
+        xs, ps, vs = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda(), torch.from_numpy(v).cuda()
+        d = torch.zeros_like(xs)
+        out = torch.zeros_like(xs) if mode == "adjoint" else None
+        grad = torch.zeros((3, mech.n_reactions), dtype=torch.float64, device="cuda") if mode == "adjoint" else None
+        b.add(mech, xs, ps, "C", out=out, dstate=d, v=vs if mode == "adjoint" else None, grad=grad)
+        segs.append(dict(name=name, path=path, mech=mech, x=x, p=p, v=v, xs=xs, ps=ps, vs=vs, d=d, out=out,
+                         grad=grad, n=n))
+    S, W, ms = b.autotune(mode, "conp", "C", reps=1)
+    note(f"ragged {mode} at full counts: autotune S={S} W={W} per_segment={b.strategy(mode)} {ms:.3f} ms")
+    for r in range(2):
+        for sg in segs:
+            sg["d"].zero_()
+            if sg["out"] is not None:
+                sg["out"].fill_(float("nan"))
+        b.eval(mode, "conp", "C", graph=True)
+        torch.cuda.synchronize()
+        note(f"ragged {mode} graph replay {r}")
+    for sg in segs:
+        n = sg["n"]
+        rng = np.random.default_rng(sg["n"])
+        idx = np.sort(np.concatenate([rng.choice(n, 30, replace=False), [0, n - 1]]))
+        o = oracle.Oracle(sg["path"])
+        x, p, v = sg["x"][idx], sg["p"][idx], sg["v"][idx]
+        f_o, f_s = o.source(x, p, "conp", bound=True)
+        check_source(sg["d"].cpu().numpy()[idx], f_o, f_s, f"{sg['name']} source terms (sample)")
+        if mode != "adjoint":
+            continue
+        j_o, _, j_s, _ = o.adjoint(x, p, v, "conp", bound=True)
+        check_jac(sg["out"].cpu().numpy()[idx], j_o, j_s, f"{sg['name']} J^T v (sample)")
+        # batch sums = the sum over two halves, each by a per-mechanism call
+        h = n // 2
+        _, g1 = api.eval_adjoint(sg["mech"], sg["xs"][:h].contiguous(), sg["ps"][:h].contiguous(),
+                                 sg["vs"][:h].contiguous(), "conp", "C")
+        _, g2 = api.eval_adjoint(sg["mech"], sg["xs"][h:].contiguous(), sg["ps"][h:].contiguous(),
+                                 sg["vs"][h:].contiguous(), "conp", "C")
+        g, gs = sg["grad"].cpu().numpy(), (g1 + g2).cpu().numpy()
+        np.testing.assert_allclose(g, gs, rtol=1e-9, atol=1e-12 * np.abs(g).max())
+        # 64 sampled states: the oracle's batch sums and central differences
+        i64 = np.sort(rng.choice(n, 64, replace=False))
+        x, p, v = sg["x"][i64], sg["p"][i64], sg["v"][i64]
+        xs, ps, vs = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda(), torch.from_numpy(v).cuda()
+        _, g64 = api.eval_adjoint(sg["mech"], xs, ps, vs, "conp", "C")
+        _, g_o, _, g_s = o.adjoint(x, p, v, "conp", bound=True)
+        check_jac(g64.cpu().numpy(), g_o, g_s, f"{sg['name']} parameter sums (64 states)")
+        arr = torch.from_numpy(np.stack(sg["mech"].arrhenius())).cuda()
+        g64 = g64.cpu().numpy()
+        for a in range(3):
+            for i in rng.choice(sg["mech"].n_reactions, 8, replace=False):
+                base = float(arr[a, i])
+                h_ = 1e-6 * max(abs(base), 1.0)
+                vals = []
+                for sgn in (1.0, -1.0):
+                    ar = arr.clone()
+                    ar[a, i] = base + sgn * h_
+                    f = api.eval_source(sg["mech"], xs, ps, "conp", "C", arrhenius=ar)
+                    vals.append(float(torch.sum(f * vs)))
+                fd = (vals[0] - vals[1]) / (2 * h_)
+                scale = np.abs(g64[a]).max()
+                assert abs(fd - g64[a, i]) <= 1e-5 * abs(g64[a, i]) + 1e-7 * scale, \
+                    (sg["name"], a, int(i), fd, g64[a, i])

@@ -258,14 +258,17 @@ FULL_SIZE_CASES = [
     ("ns111", "conp", "C", "dense"),
     ("ns111", "conv", "F", "dense"),
     ("ns53", "conp", "C", "sparse"),
+    ("ns360", "conp", "C", "sparse-tuned"),
+    ("ns360", "conv", "F", "sparse"),
 ]
 
 
 @pytest.mark.parametrize("name,form,layout,output", FULL_SIZE_CASES)
 def test_full_size_sampled(torch_cuda, api, name, form, layout, output, mech_dir):
     """Full-size workloads (262,144 states of the 111-species mechanism,
-    1,048,576 of the 53-species one) in the default launch shape, checked
-    against the oracle on sampled states, including the first and last."""
+    1,048,576 of the 53-species one, 16,384 of the 360-species one) in the
+    default or the autotuned launch shape, checked against the oracle on
+    sampled states, including the first and last."""
     torch = torch_cuda
     m, path = workload_file(name, mech_dir)
     w = synth.WORKLOADS[name]

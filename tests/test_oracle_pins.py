@@ -601,3 +601,28 @@ def test_closure_uses_exactly_rounded_sum(tmp_path):
     exact = math.fsum(moles)
     nb = (P * V) / (R * T) - exact
     assert c["C"][3] == nb / V
+
+
+def test_source_operation_count(mech_dir):
+    """The operation count of the source terms (for the FP64 roofline): the
+    counting evaluation gives ora_source's values bit for bit, every rate
+    constant takes one exponential (two for a reversible reaction: k_f and
+    K_c, more for falloff), ln T is counted once, and the count does not
+    depend on the state."""
+    m, path = tiny_file(3, mech_dir)
+    o = oracle.Oracle(path)
+    st, (x, p) = _tiny_states(m, n=3, seed=3, form="conp")
+    ref = o.source(x, p, "conp")
+    counts = []
+    for i in range(x.shape[0]):
+        ops, f = o.source_ops(x[i], p[i], "conp", values=True)
+        assert np.array_equal(f, ref[i])
+        counts.append(ops)
+    assert all(c == counts[0] for c in counts)
+    c = counts[0]
+    n_rev = sum(1 for r in m.reactions if r.rev)
+    n_fall = sum(1 for r in m.reactions if r.type in ("LINDEMANN", "TROE", "SRI"))
+    assert c["exp"] >= len(m.reactions) + n_rev + n_fall
+    # ln T (entropies and rate constants) and ln(P_ref / R T) (equilibrium constants)
+    assert c["log"] <= 2
+    assert c["flops"] > 10 * len(m.reactions)
