@@ -254,6 +254,8 @@ def main():
                     help="run only a plain 1 GiB device copy (traffic-counter reference)")
     ap.add_argument("--fp64-calibration", action="store_true",
                     help="run only the FP64 weight calibration launches of exp, log and log10")
+    ap.add_argument("--source-only", action="store_true",
+                    help="time the source-term kernel alone (for its profiles), not the benchmark step")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -298,6 +300,23 @@ def main():
         S_, W_ = (int(v) for v in args.launch.split(","))
         mech.set_launch(S_, W_)
         args.no_autotune = True
+    if args.source_only:
+        # the source-term kernel alone, in the shape its autotuner picks
+        if not args.no_autotune:
+            api.autotune(mech, xs, ps, args.form, args.layout, mode="source", reps=2, stream=stream)
+        for _ in range(args.warmup):
+            api.eval_source(mech, xs, ps, args.form, args.layout, out=dstate, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            api.eval_source(mech, xs, ps, args.form, args.layout, out=dstate, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / args.steps
+        print(json.dumps({"source_only_ms": round(t, 4), "states_per_s": n / (t * 1e-3), "n_states": n,
+                          "workload": args.workload, "launch_shape": list(mech.launch_shape(0))}), flush=True)
+        return
     if not args.no_autotune:
         # outside the timed region: pick the fastest launch shape for this batch
         t0 = time.time()
