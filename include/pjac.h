@@ -320,6 +320,20 @@ pj_status pj_batch_set_strategy(pj_batch* batch, int mode, int per_segment);
 int pj_batch_strategy(const pj_batch* batch, int mode);
 pj_status pj_batch_eval(pj_batch* batch, int mode, pj_form form, pj_layout layout, pj_stream stream);
 pj_status pj_batch_eval_graph(pj_batch* batch, int mode, pj_form form, pj_layout layout, pj_stream stream);
+/*
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid it): the batch's
+ * persistent launch (whatever pj_batch_set_strategy says) with its segment
+ * table in a fixed device array of the library, at most 64 non-empty
+ * segments (PJ_E_UNSUPPORTED beyond), instead of device memory allocated
+ * on the first call.  No hipMalloc, hipFree or allocating library call:
+ * the table is written by a stream-ordered copy on `stream`, then the
+ * launch.  Every call on one device shares that device's array, which keeps
+ * the last call's table: calls that may overlap on one device (on different
+ * streams, or from different threads) race; calls on one stream do not.
+ * Outputs, modes, shapes and errors as pj_batch_eval.
+ */
+pj_status pj_batch_eval_noalloc(pj_batch* batch, int mode, pj_form form, pj_layout layout, pj_stream stream);
 pj_status pj_batch_autotune(pj_batch* batch, int mode, pj_form form, pj_layout layout, int reps,
                             pj_stream stream, int* states_per_group, int* waves_per_group, float* ms);
 const char* pj_batch_last_error(void);

@@ -95,6 +95,8 @@ _lib.pj_batch_launch_shape.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c
 _lib.pj_batch_launch_shape.restype = ctypes.c_int
 _lib.pj_batch_eval.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P]
 _lib.pj_batch_eval.restype = ctypes.c_int
+_lib.pj_batch_eval_noalloc.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P]
+_lib.pj_batch_eval_noalloc.restype = ctypes.c_int
 _lib.pj_batch_eval_graph.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P]
 _lib.pj_batch_eval_graph.restype = ctypes.c_int
 _lib.pj_batch_autotune.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P,
@@ -528,6 +530,12 @@ class Batch:
         f = _lib.pj_batch_eval_graph if graph else _lib.pj_batch_eval
         self._bcheck(f(self._h, MODES[mode], FORMS[form], LAYOUTS[layout], _stream(stream)),
                      "pj_batch_eval_graph" if graph else "pj_batch_eval")
+
+    def eval_noalloc(self, mode: str, form: str = "conp", layout: str = "F", stream=None):
+        """pj_batch_eval_noalloc: the persistent launch with the segment table
+        in the library's fixed device array (no device allocation)."""
+        self._bcheck(_lib.pj_batch_eval_noalloc(self._h, MODES[mode], FORMS[form], LAYOUTS[layout],
+                                                _stream(stream)), "pj_batch_eval_noalloc")
 
     def autotune(self, mode: str, form: str = "conp", layout: str = "F", reps: int = 2, stream=None):
         """Keep the fastest of every persistent launch shape and one launch per

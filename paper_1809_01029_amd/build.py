@@ -34,7 +34,7 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = []
-    for src in ("mech.cpp", "api.cpp", "batch.cpp", "kernels.hip", "kernels_ext.hip", "calibrate.hip"):
+    for src in ("mech.cpp", "api.cpp", "batch.cpp", "kernels.hip", "kernels_ext.hip", "calibrate.hip", "noalloc.hip"):
         o = os.path.join(BUILD, src + ".o")
         dev = DEVICE if src.endswith(".hip") else []
         jobs.append(([HIPCC] + COMMON + dev + ["-c", os.path.join(CSRC, src), "-o", o], o))

@@ -24,41 +24,6 @@ bool batch_mode(int mode) { return mode == pj::MODE_SRC || mode == pj::MODE_SPAR
 
 }  // namespace
 
-struct pj_batch {
-    struct Seg {
-        const pj_mech* mech;
-        int64_t n;
-        const double* state;
-        const double* param;
-        double* out;
-        double* dstate;
-        const double* v;
-        double* grad;
-    };
-    std::vector<Seg> segs;
-    int device = -1;
-    int user_S[pj::N_MODES] = {0, 0, 0, 0}, user_W[pj::N_MODES] = {0, 0, 0, 0};
-    int per_seg[pj::N_MODES] = {0, 0, 0, 0};   // 1: one launch per segment
-    // device copy of the segment table, for the shape it was built with
-    pj::BatchSeg* d_segs = nullptr;
-    size_t d_cap = 0;
-    int table_S = 0, table_nseg = 0;
-    int64_t table_total = 0;
-    bool table_valid = false;
-    // captured graph and what it was captured for
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int g_mode = -1, g_form = -1, g_layout = -1, g_S = 0, g_W = 0, g_per_seg = 0;
-    hipStream_t capture_stream = nullptr;
-
-    void drop_graph() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
-        g_mode = -1;
-    }
-};
 
 namespace {
 
@@ -213,6 +178,20 @@ pj_status enqueue_mode(pj_batch* b, int mode, pj_form form, pj_layout layout, in
 }
 
 }  // namespace
+
+// the batch internals the allocation-free entry point (noalloc.hip) shares
+namespace pj {
+pj_status batch_fail(pj_status st, const std::string& msg) { return fail(st, msg); }
+void batch_ok() { g_err.clear(); }
+pj_status batch_check(const pj_batch* b, int mode, pj_form form, pj_layout layout) {
+    return check_segments(b, mode, form, layout);
+}
+void batch_shape_of(const pj_batch* b, int mode, int& S, int& W) { batch_shape(b, mode, S, W); }
+int64_t batch_lds_of(const pj_batch* b, int mode, int S, int W, int64_t* gr_off) {
+    return batch_lds(b, mode, S, W, gr_off);
+}
+int batch_lds_limit(const pj_batch* b) { return lds_max_of(b); }
+}  // namespace pj
 
 extern "C" {
 

@@ -245,3 +245,58 @@ void choose_launch(Mechanism& m);
 struct pj_mech {
     pj::Mechanism m;
 };
+
+namespace pj {
+// noalloc.hip: most segments pj_batch_eval_noalloc takes
+constexpr int NOALLOC_MAX_SEGS = 64;
+}  // namespace pj
+
+// A ragged multi-mechanism batch (batch.cpp, noalloc.hip).
+struct pj_batch {
+    struct Seg {
+        const pj_mech* mech;
+        int64_t n;
+        const double* state;
+        const double* param;
+        double* out;
+        double* dstate;
+        const double* v;
+        double* grad;
+    };
+    std::vector<Seg> segs;
+    int device = -1;
+    int user_S[pj::N_MODES] = {0, 0, 0, 0}, user_W[pj::N_MODES] = {0, 0, 0, 0};
+    int per_seg[pj::N_MODES] = {0, 0, 0, 0};   // 1: one launch per segment
+    // device copy of the segment table, for the shape it was built with
+    pj::BatchSeg* d_segs = nullptr;
+    size_t d_cap = 0;
+    int table_S = 0, table_nseg = 0;
+    int64_t table_total = 0;
+    bool table_valid = false;
+    // captured graph and what it was captured for
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int g_mode = -1, g_form = -1, g_layout = -1, g_S = 0, g_W = 0, g_per_seg = 0;
+    hipStream_t capture_stream = nullptr;
+    // host staging of pj_batch_eval_noalloc's segment table
+    pj::BatchSeg noalloc_host[pj::NOALLOC_MAX_SEGS] = {};
+
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        g_mode = -1;
+    }
+};
+
+namespace pj {
+// batch.cpp: the batch's argument checks, launch shape and LDS size, and its
+// error message (pj_batch_last_error)
+pj_status batch_fail(pj_status st, const std::string& msg);
+void batch_ok();
+pj_status batch_check(const pj_batch* b, int mode, pj_form form, pj_layout layout);
+void batch_shape_of(const pj_batch* b, int mode, int& S, int& W);
+int64_t batch_lds_of(const pj_batch* b, int mode, int S, int W, int64_t* gr_off);
+int batch_lds_limit(const pj_batch* b);
+}  // namespace pj

@@ -315,3 +315,19 @@ def test_error_paths_of_further_reaction_types(api, tmp_path):
     assert edited(sri_bad) == 2
     assert edited(eff_on_plog) == 2
     assert _status(api, _write(tmp_path, good.replace(" SRI ", " SRI2 ", 1))) == 2
+
+
+def test_noalloc_and_calibration_argument_checks(api, tmp_path):
+    lib = api.library()
+    assert lib.pj_batch_eval_noalloc(None, 1, 0, 0, None) == 1          # NULL batch
+    b = ctypes.c_void_p()
+    assert lib.pj_batch_create(ctypes.byref(b)) == 0
+    assert lib.pj_batch_eval_noalloc(b, 2, 0, 0, None) == 1             # dense is not a batch mode
+    assert lib.pj_batch_eval_noalloc(b, 1, 0, 0, None) == 0             # empty batch: nothing to do
+    lib.pj_batch_free(b)
+    dummy = ctypes.c_void_p(16)
+    assert lib.pj_calibrate_fp64(4, 8, 1, dummy, dummy, None) == 1        # bad function
+    assert lib.pj_calibrate_fp64(0, -1, 1, dummy, dummy, None) == 1       # negative size
+    assert lib.pj_calibrate_fp64(0, 8, 0, dummy, dummy, None) == 1        # no repetition
+    assert lib.pj_calibrate_fp64(0, 8, 1, None, dummy, None) == 1         # NULL input
+    assert lib.pj_calibrate_fp64(0, 0, 1, None, None, None) == 0          # empty: nothing to do
