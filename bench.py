@@ -417,6 +417,15 @@ def main():
                                                     stream=stream))
         variants[f"layout_{ol}_sparse"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3)}
         del xs3, ps3, jac3, d3
+        # fixed-order accumulation (bitwise reproducible) at the timed launch shape
+        mdet = api.load_mechanism(path, options=api.OPT_DETERMINISTIC)
+        mdet.set_launch(*mech.launch_shape(1))
+        t = timeit(lambda: api.eval_jacobian_sparse(mdet, xs, ps, args.form, args.layout, out=jac,
+                                                    dstate=dstate, stream=stream))
+        variants["deterministic_sparse"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3),
+                                            "cost_vs_default": round(t / ms, 3),
+                                            "launch_shape": list(mdet.launch_shape(1))}
+        del mdet
         if args.workload == "ns111" and not args.n_states:
             # the 53-species configuration at its full size (1,048,576 states)
             w53 = synth.WORKLOADS["ns53"]

@@ -103,8 +103,17 @@ pj_status pj_mech_load(const char* desc_path, pj_mech** out);
  *   PJ_OPT_LINEAR_SEARCH  species-row entries find their CSR slot by
  *       searching the row at run time (the lookup the paper times, Sec. 3.4)
  *       instead of the static slot map: same values, for comparison.
+ *   PJ_OPT_DETERMINISTIC  source terms and the sparse Jacobian (and its fused
+ *       source terms) bitwise reproducible from run to run at any one launch
+ *       shape: the waves of a workgroup add their reactions' contributions to
+ *       the shared sums in turn instead of at once (slower; at most 4 states
+ *       per workgroup).  Results may still differ in the last bits between
+ *       two launch shapes, which split the reactions differently.  Dense,
+ *       adjoint, run-time-search, per-call-parameter and pj_batch_eval
+ *       evaluations are unaffected (a one-wave workgroup is always
+ *       reproducible).
  */
-enum { PJ_OPT_APPROX_JACOBIAN = 1, PJ_OPT_CCS = 2, PJ_OPT_LINEAR_SEARCH = 4 };
+enum { PJ_OPT_APPROX_JACOBIAN = 1, PJ_OPT_CCS = 2, PJ_OPT_LINEAR_SEARCH = 4, PJ_OPT_DETERMINISTIC = 8 };
 pj_status pj_mech_load_ex(const char* desc_path, int options, pj_mech** out);
 pj_status pj_mech_parse_ex(const char* desc_path, int options, pj_mech** out);
 int pj_mech_options(const pj_mech* mech); /* -1 for NULL */

@@ -154,13 +154,13 @@ def library() -> ctypes.CDLL:
     return _lib
 
 
-OPT_APPROX_JACOBIAN, OPT_CCS, OPT_LINEAR_SEARCH = 1, 2, 4
+OPT_APPROX_JACOBIAN, OPT_CCS, OPT_LINEAR_SEARCH, OPT_DETERMINISTIC = 1, 2, 4, 8
 
 
 class Mechanism:
     """A mechanism description loaded by the library (pj_mech_load_ex), or
     only parsed on the host (``upload=False``, pj_mech_parse_ex).  ``options``:
-    OPT_APPROX_JACOBIAN, OPT_CCS, OPT_LINEAR_SEARCH (bitwise or)."""
+    OPT_APPROX_JACOBIAN, OPT_CCS, OPT_LINEAR_SEARCH, OPT_DETERMINISTIC (bitwise or)."""
 
     def __init__(self, path: str, upload: bool = True, options: int = 0):
         h = _P()

@@ -23,6 +23,24 @@ bool pow2_upto(int v, int mx) { return v >= 1 && v <= mx && (v & (v - 1)) == 0; 
 
 constexpr int MAX_S = 64, MAX_WAVES = 8;
 
+// The kernel that evaluates `mode` for a mechanism: the run-time slot search
+// and the fixed-order additions have kernels of their own, and so has a call
+// with its own Arrhenius parameters.
+int kernel_mode(const pj::Mechanism& m, int mode, bool per_call_arrhenius) {
+    if (per_call_arrhenius) return mode == pj::MODE_SRC ? pj::MODE_SRC_P : pj::MODE_ADJ_P;
+    if (mode == pj::MODE_SPARSE && m.dm.lsearch) return pj::MODE_SPARSE_LS;
+    if (m.dm.det && mode == pj::MODE_SRC) return pj::MODE_SRC_DET;
+    if (m.dm.det && mode == pj::MODE_SPARSE) return pj::MODE_SPARSE_DET;
+    return mode;
+}
+
+// the most states per workgroup a kernel mode is built for
+int max_states(int kmode) {
+    if (kmode == pj::MODE_SPARSE_LS || kmode == pj::MODE_SRC_DET || kmode == pj::MODE_SPARSE_DET) return 4;
+    if (pj::base_mode(kmode) == pj::MODE_ADJ) return pj::MAX_S_ADJ;
+    return MAX_S;
+}
+
 }  // namespace
 
 namespace pj {
@@ -53,8 +71,9 @@ void choose_launch(Mechanism& m) {
         int S = 1;
         for (int c = 4; c >= 1; c >>= 1)
             if (L(c, 1) <= m.lds_max) { S = c; break; }
-        const bool user_ok = m.user_S && (mode != MODE_ADJ || m.user_S <= MAX_S_ADJ);
-        if (user_ok && L(m.user_S, m.user_waves ? m.user_waves : 1) <= m.lds_max) S = m.user_S;
+        const int maxS = max_states(kernel_mode(m, mode, false));
+        if (m.user_S && m.user_S <= maxS && L(m.user_S, m.user_waves ? m.user_waves : 1) <= m.lds_max)
+            S = m.user_S;
         int w = m.user_waves ? m.user_waves : default_waves(m, mode, S, gr);
         if (L(S, w) > m.lds_max) w = default_waves(m, mode, S, gr);
         m.S[mode] = S;
@@ -90,15 +109,10 @@ pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, in
     if (lds > m.lds_max)
         return fail(PJ_E_UNSUPPORTED, "per-state working set (" + std::to_string(lds) +
                                           " B) exceeds the LDS of one workgroup");
-    // the run-time slot search is its own kernel (the hot loop of the static
-    // map carries no trace of it), with at most 4 states per workgroup
-    int kmode = mode, S = m.S[mode];
-    if (mode == pj::MODE_SPARSE && m.dm.lsearch) {
-        kmode = pj::MODE_SPARSE_LS;
-        S = std::min(S, 4);
-    }
-    // a call with its own Arrhenius parameters has kernels of its own
-    if (arr) kmode = mode == pj::MODE_SRC ? pj::MODE_SRC_P : pj::MODE_ADJ_P;
+    // the hot loop of the static map carries no trace of the run-time search,
+    // the fixed-order additions or per-call parameters: kernels of their own
+    const int kmode = kernel_mode(m, mode, arr != nullptr);
+    const int S = std::min(m.S[mode], max_states(kmode));
     // a call with its own Arrhenius parameters runs on a copy of the device
     // description that points at them (the mechanism itself is not touched)
     pj::DevMech dm = m.dm;
@@ -119,7 +133,7 @@ pj_status pj_mech_parse_ex(const char* desc_path, int options, pj_mech** out) {
     if (!out) return fail(PJ_E_INVALID, "NULL output handle");
     *out = nullptr;
     if (!desc_path) return fail(PJ_E_INVALID, "NULL path");
-    if (options & ~(PJ_OPT_APPROX_JACOBIAN | PJ_OPT_CCS | PJ_OPT_LINEAR_SEARCH))
+    if (options & ~(PJ_OPT_APPROX_JACOBIAN | PJ_OPT_CCS | PJ_OPT_LINEAR_SEARCH | PJ_OPT_DETERMINISTIC))
         return fail(PJ_E_INVALID, "unknown option bits");
     pj_mech* h = new (std::nothrow) pj_mech();
     if (!h) return fail(PJ_E_NOMEM, "out of host memory");
@@ -354,7 +368,8 @@ pj_status autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int6
     pj_status st = eval(mech, mode, form, layout, n_states, d_state, d_param, dst, jac, stream, vin, grad);
     if (st != PJ_OK) return st;
     const bool gr = mode == pj::MODE_ADJ && m.adj_grad_in_lds;
-    const int maxS = mode == pj::MODE_ADJ ? pj::MAX_S_ADJ : MAX_S;
+    const int kmode = kernel_mode(m, mode, false);
+    const int maxS = max_states(kmode);
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -369,7 +384,7 @@ pj_status autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int6
             const int64_t l = pj::lds_bytes(m.dm, mode, S, w, gr);
             if (l > m.lds_max) continue;
             auto go = [&]() {
-                return pj::launch(m.dm, mode, form, layout, S, n_states, d_state, d_param, dst, jac, vin, grad,
+                return pj::launch(m.dm, kmode, form, layout, S, n_states, d_state, d_param, dst, jac, vin, grad,
                                   gr ? 1 : 0, w, l, hs);
             };
             hipError_t e = go();

@@ -132,6 +132,7 @@ struct DevMech {
     int approx;               // approximate Jacobian (bath gas held against n_j)
     int ext;                  // holds SRI, chemically activated, P-Log or Chebyshev reactions
     int lsearch;              // find CSR slots by a run-time row search
+    int det;                  // every LDS addition in a fixed order (bitwise reproducible)
     const int32_t* orig;      // [nr] description index of each kernel-order reaction
     const uint16_t* col_idx;  // [nnz]
     const int32_t* dense_rows;// [n_dense_rows] species index k of bath-dense rows
@@ -209,10 +210,15 @@ enum Mode : int { MODE_SRC = 0, MODE_SPARSE = 1, MODE_DENSE = 2, MODE_ADJ = 3,
                   MODE_SPARSE_LS = 4 /* sparse with run-time slot search; launch shape of MODE_SPARSE */,
                   // source terms / adjoint with the call's own Arrhenius parameters
                   // (DevMech::arr); launch shapes of MODE_SRC / MODE_ADJ
-                  MODE_SRC_P = 5, MODE_ADJ_P = 6 };
+                  MODE_SRC_P = 5, MODE_ADJ_P = 6,
+                  // source terms / sparse Jacobian with every LDS addition in a fixed
+                  // order (the waves of a workgroup add in turn); shapes of MODE_SRC /
+                  // MODE_SPARSE, at most 4 states per workgroup
+                  MODE_SRC_DET = 7, MODE_SPARSE_DET = 8 };
 // the mode whose computation a kernel mode performs
 __host__ __device__ constexpr int base_mode(int m) {
-    return m == MODE_SRC_P ? MODE_SRC : m == MODE_ADJ_P ? MODE_ADJ : m;
+    return m == MODE_SRC_P || m == MODE_SRC_DET ? MODE_SRC
+           : m == MODE_ADJ_P ? MODE_ADJ : m == MODE_SPARSE_DET ? MODE_SPARSE : m;
 }
 constexpr int N_MODES = 4;        // modes with a launch shape of their own
 constexpr int MAX_S_ADJ = 4;      // states per workgroup of the adjoint mode

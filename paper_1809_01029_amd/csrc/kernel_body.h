@@ -306,7 +306,8 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                                            const bool gr_lds, double* GR, const long qg) {
     extern __shared__ double lds[];
     constexpr int M = base_mode(MODE);
-    constexpr bool PAR = MODE != M;          // the call's own Arrhenius parameters
+    constexpr bool PAR = MODE == MODE_SRC_P || MODE == MODE_ADJ_P;   // the call's own Arrhenius parameters
+    constexpr bool DET = MODE == MODE_SRC_DET || MODE == MODE_SPARSE_DET;   // additions in a fixed order
     constexpr bool JAC = M != MODE_SRC;
     constexpr bool ADJ = M == MODE_ADJ;      // jac receives J^T v (state layout)
     constexpr bool LS = M == MODE_SPARSE_LS;   // sparse, slots found by a row search
@@ -411,7 +412,13 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
 
         // ---- reactions: rates of progress and Jacobian sub-products
         double racc[4] = {0.0, 0.0, 0.0, 0.0};  // TT, TS, ST, SS
-        for (int p = g; p < dm.nr; p += G) {
+        // Deterministic accumulation: every thread runs the same number of
+        // iterations (lanes past the last reaction redo it and add nothing);
+        // each iteration computes in parallel, then the waves add their
+        // contributions one after the other.
+        for (int pb = 0; DET ? pb < dm.nr : g + pb < dm.nr; pb += G) {
+            const bool act = !DET || g + pb < dm.nr;
+            const int p = DET && !act ? dm.nr - 1 : g + pb;
             const RxnRec rr = load_rec(dm.rec + p);
             // slot positions any reaction of this 64-reaction chunk uses
             // (uniform over the wave: a wave's lanes take 64/S consecutive
@@ -559,32 +566,36 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 }
             }
             const double q = c * R;
+            // production rates
+            auto scatter_w = [&]() {
 #pragma unroll
-            for (int a = 0; a < NSLOT; ++a) {
-                if (!((cmask >> a) & 1)) continue;
-                if (nu[a]) atomicAdd(&AT(W, spc[a]), sg[a] * q);
-            }
-            if (!JAC) continue;
-
+                for (int a = 0; a < NSLOT; ++a) {
+                    if (!((cmask >> a) & 1)) continue;
+                    if (nu[a]) atomicAdd(&AT(W, spc[a]), sg[a] * q);
+                }
+            };
+            if constexpr (!DET) scatter_w();
+            // Jacobian sub-products of this reaction (what its scatter adds)
+            double Qs[NSLOT], QM = 0.0, dE = 0.0, dOm = 0.0, Vt = 0.0, Vs = 0.0, bam1 = 0.0;
+            if constexpr (JAC) {
             // concentration partials of q (zero for empty slots and for the
             // products of an irreversible reaction)
             const double dlnkf = (bexp + th * invT) * invT + dlkt_dT;
             const double dlnkr = dlnkf - (dH - dnu) * invT;
             const double ckf = c * kf, ckr = -c * kr;
-            double Qs[NSLOT];
             Qs[0] = ckf * dfr[0] * (fr[1] * fr[2]);
             Qs[1] = ckf * dfr[1] * (fr[0] * fr[2]);
             Qs[2] = ckf * dfr[2] * (fr[0] * fr[1]);
             Qs[3] = ckr * dfr[3] * (fr[4] * fr[5]);
             Qs[4] = ckr * dfr[4] * (fr[3] * fr[5]);
             Qs[5] = ckr * dfr[5] * (fr[3] * fr[4]);
-            const double QM = R * dcdM;
+            QM = R * dcdM;
             const double qT = c * (Rf * dlnkf - Rr * dlnkr) + R * dcdT;
             double Qb = 0.0, sQC = 0.0;
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) sQC += Qs[a] * cf[a];
             sQC += QM * Meff;
-            const double bam1 = rr.bam1;
+            bam1 = rr.bam1;
             if (w & INFO_BATH) {
                 // rates that depend on the bath gas: its partial Q_Ns, taken
                 // out of the sum over the other species
@@ -597,12 +608,14 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             const double dqdT = qT - Ctot * invT * (Qb + QM);
             const double dqdS = FORM == PJ_CONP ? -(sQC - Qb * (nsum * invV)) * invV
                                                 : (Qb + QM) * invRT + q * dlkt_dP;
-            const double dE = FORM == PJ_CONP ? dH : dH - dnu;
-            const double dOm = rr.domega;
-            racc[0] += dE * dqdT;
-            racc[1] += dE * dqdS;
-            racc[2] += dOm * dqdT;
-            racc[3] += dOm * dqdS;
+            dE = FORM == PJ_CONP ? dH : dH - dnu;
+            dOm = rr.domega;
+            if (act) {
+                racc[0] += dE * dqdT;
+                racc[1] += dE * dqdS;
+                racc[2] += dOm * dqdT;
+                racc[3] += dOm * dqdS;
+            }
 
             if (ADJ && grad) {
                 // lambda_i = v . df/dq_i, times dq_i/d ln A; summed over the
@@ -642,6 +655,13 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 }
             }
 
+            Vt = V * dqdT;
+            Vs = V * dqdS;
+            }
+
+            // the Jacobian's LDS additions of this reaction
+            auto scatter_j = [&]() {
+            if constexpr (JAC) {
             // energy / mole weighted partials (T and V/P rows)
 #pragma unroll
             for (int b = 0; b < NSLOT; ++b) {
@@ -669,7 +689,6 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             // species rows; the slot table holds NOSLOT for pairs that do not
             // exist (empty slots, irreversible products, bath-gas columns)
             const JacRec jr = load_rec(dm.jrec + p);
-            const double Vt = V * dqdT, Vs = V * dqdS;
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) {
                 if (!((cmask >> a) & 1)) continue;
@@ -712,6 +731,19 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                         if (spc[b] == bath && nu[b] && (b < MAXSIDE || rev))
                             atomicAdd(&AT(B, spc[a]), sg[a] * Qs[b]);
                     if (bam1 != 0.0) atomicAdd(&AT(B, spc[a]), sg[a] * QM * bam1);
+                }
+            }
+            }
+            };
+            if constexpr (!DET) {
+                scatter_j();
+            } else {
+                for (int ow = 0; ow < nwave; ++ow) {
+                    __syncthreads();
+                    if (wave == ow && act) {
+                        scatter_w();
+                        scatter_j();
+                    }
                 }
             }
         }
@@ -1111,13 +1143,16 @@ hipError_t launch_impl(const DevMech& dm, int mode, int form, int layout, int S,
 #define PJ_SA(F, L) PJ_CASE(F, L, MODE_ADJ, 1) PJ_CASE(F, L, MODE_ADJ, 2) PJ_CASE(F, L, MODE_ADJ, 4)
 #define PJ_SL(F, L) PJ_CASE(F, L, MODE_SPARSE_LS, 1) PJ_CASE(F, L, MODE_SPARSE_LS, 2) PJ_CASE(F, L, MODE_SPARSE_LS, 4)
 #define PJ_SAP(F, L) PJ_CASE(F, L, MODE_ADJ_P, 1) PJ_CASE(F, L, MODE_ADJ_P, 2) PJ_CASE(F, L, MODE_ADJ_P, 4)
+#define PJ_SD(F, L) PJ_CASE(F, L, MODE_SRC_DET, 1) PJ_CASE(F, L, MODE_SRC_DET, 2) PJ_CASE(F, L, MODE_SRC_DET, 4) \
+    PJ_CASE(F, L, MODE_SPARSE_DET, 1) PJ_CASE(F, L, MODE_SPARSE_DET, 2) PJ_CASE(F, L, MODE_SPARSE_DET, 4)
 #define PJ_MODES(F, L) PJ_S(F, L, MODE_SRC) PJ_S(F, L, MODE_SPARSE) PJ_S(F, L, MODE_DENSE) PJ_SA(F, L) PJ_SL(F, L) \
-    PJ_S(F, L, MODE_SRC_P) PJ_SAP(F, L)
+    PJ_S(F, L, MODE_SRC_P) PJ_SAP(F, L) PJ_SD(F, L)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_F)
     PJ_MODES(PJ_CONP, PJ_LAYOUT_C)
     PJ_MODES(PJ_CONV, PJ_LAYOUT_F)
     PJ_MODES(PJ_CONV, PJ_LAYOUT_C)
 #undef PJ_MODES
+#undef PJ_SD
 #undef PJ_SAP
 #undef PJ_SL
 #undef PJ_SA

@@ -629,6 +629,7 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.arr = nullptr;
     dm.approx = (m.opts & PJ_OPT_APPROX_JACOBIAN) ? 1 : 0;
     dm.lsearch = (m.opts & PJ_OPT_LINEAR_SEARCH) ? 1 : 0;
+    dm.det = (m.opts & PJ_OPT_DETERMINISTIC) ? 1 : 0;
     dm.ext = 0;
     for (const auto& r : m.rx)
         if (r.kind == K_SRI || r.chemact || kind_table(r.kind)) dm.ext = 1;

@@ -252,8 +252,10 @@ def test_column_order_arrays_and_options(api, mech_dir, tmp_path):
     np.testing.assert_array_equal(api.sparse_to_dense(mech, vals, "C"), D)
     lib = api.library()
     h = ctypes.c_void_p()
-    assert lib.pj_mech_parse_ex(os.fsencode(path), 8, ctypes.byref(h)) == 1
+    assert lib.pj_mech_parse_ex(os.fsencode(path), 16, ctypes.byref(h)) == 1
     assert b"option" in lib.pj_last_error()
+    det = api.Mechanism(path, upload=False, options=api.OPT_DETERMINISTIC | api.OPT_CCS)
+    assert lib.pj_mech_options(det._h) == api.OPT_DETERMINISTIC | api.OPT_CCS
     assert lib.pj_mech_options(None) == -1
 
 
