@@ -293,9 +293,14 @@ int64_t pj_mech_lds_bytes(const pj_mech* mech, int for_jacobian);
  * values, d_dstate optional fused source terms), 3 adjoint (d_out: J^T v,
  * d_v required, d_grad optional 3*Nr parameter sums of that segment).
  * Buffers are caller-owned device memory in the layout given at evaluation,
- * and must stay valid while the batch (or its graph) may run.  States per
- * workgroup are at most 4 and shared by all segments; the LDS a workgroup
- * gets is that of the largest segment.  Per mode, the batch can instead run
+ * and must stay valid while the batch (or its graph) may run.  The launch
+ * shape S x W (S states per workgroup, a power of two up to 16, the adjoint
+ * at most 4; W waves, 1 to 8) sets the LDS a workgroup gets: that of the
+ * largest working set among the segments at S states.  Each segment then
+ * takes the most states per workgroup (S doubled, up to 16; the adjoint up
+ * to 4) whose working set fits that LDS (pj_batch_segment_states; -1 for a
+ * NULL batch, a bad mode or segment index), so that segments of smaller
+ * mechanisms hold more states at once.  Per mode, the batch can instead run
  * one launch per segment, each at its mechanism's own launch shape for that
  * mode (pj_batch_set_strategy(batch, mode, 1); 0 = the persistent launch,
  * the default); the graph then holds those launches.
@@ -325,6 +330,7 @@ pj_status pj_batch_clear(pj_batch* batch);
 int pj_batch_size(const pj_batch* batch); /* segments, -1 for NULL */
 pj_status pj_batch_set_launch(pj_batch* batch, int mode, int states_per_group, int waves_per_group);
 int pj_batch_launch_shape(const pj_batch* batch, int mode, int* states_per_group, int* waves_per_group);
+int pj_batch_segment_states(const pj_batch* batch, int mode, int segment);
 pj_status pj_batch_set_strategy(pj_batch* batch, int mode, int per_segment);
 int pj_batch_strategy(const pj_batch* batch, int mode);
 pj_status pj_batch_eval(pj_batch* batch, int mode, pj_form form, pj_layout layout, pj_stream stream);

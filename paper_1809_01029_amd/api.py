@@ -93,6 +93,8 @@ _lib.pj_batch_set_launch.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_in
 _lib.pj_batch_set_launch.restype = ctypes.c_int
 _lib.pj_batch_launch_shape.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.pj_batch_launch_shape.restype = ctypes.c_int
+_lib.pj_batch_segment_states.argtypes = [_P, ctypes.c_int, ctypes.c_int]
+_lib.pj_batch_segment_states.restype = ctypes.c_int
 _lib.pj_batch_eval.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P]
 _lib.pj_batch_eval.restype = ctypes.c_int
 _lib.pj_batch_eval_noalloc.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P]
@@ -516,6 +518,17 @@ class Batch:
         if _lib.pj_batch_launch_shape(self._h, MODES[mode], ctypes.byref(a), ctypes.byref(b)) != 0:
             raise PjError(1, "pj_batch_launch_shape")
         return a.value, b.value
+
+    def segment_states(self, mode: str):
+        """States per workgroup each segment takes in the persistent launch
+        (pj_batch_segment_states)."""
+        out = []
+        for i in range(_lib.pj_batch_size(self._h)):
+            v = _lib.pj_batch_segment_states(self._h, MODES[mode], i)
+            if v < 0:
+                raise PjError(1, "pj_batch_segment_states")
+            out.append(v)
+        return out
 
     def set_strategy(self, mode: str, per_segment: bool):
         """One persistent launch (False) or one launch per segment at each

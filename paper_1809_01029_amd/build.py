@@ -36,7 +36,8 @@ def build(verbose: bool = False) -> str:
     jobs = []
     for src in ("mech.cpp", "api.cpp", "batch.cpp", "kernels.hip", "kernels_ext.hip", "calibrate.hip", "noalloc.hip"):
         o = os.path.join(BUILD, src + ".o")
-        dev = DEVICE if src.endswith(".hip") else []
+        # host-only translation units: no device pass
+        dev = DEVICE if src.endswith(".hip") else ["--offload-host-only"]
         jobs.append(([HIPCC] + COMMON + dev + ["-c", os.path.join(CSRC, src), "-o", o], o))
     # the translation units compile in parallel (the two kernel sets dominate)
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(jobs)) as ex:

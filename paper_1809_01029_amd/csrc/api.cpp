@@ -116,7 +116,7 @@ pj_status eval(const pj_mech* mech, int mode, pj_form form, pj_layout layout, in
     // a call with its own Arrhenius parameters runs on a copy of the device
     // description that points at them (the mechanism itself is not touched)
     pj::DevMech dm = m.dm;
-    dm.arr = arr;
+    dm.arr = pj::gptr(arr);
     hipError_t e = pj::launch(dm, kmode, form, layout, S, n, state, param, dstate, jac, vin, grad,
                               m.adj_grad_in_lds ? 1 : 0, m.waves[mode], pj::lds_bytes(m.dm, mode, S, m.waves[mode],
                               m.adj_grad_in_lds), (hipStream_t)stream);

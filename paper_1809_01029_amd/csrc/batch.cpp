@@ -22,6 +22,9 @@ pj_status fail(pj_status st, const std::string& msg) {
 
 bool batch_mode(int mode) { return mode == pj::MODE_SRC || mode == pj::MODE_SPARSE || mode == pj::MODE_ADJ; }
 
+// the most states per group of a batch's launch shape (and of any segment)
+int batch_cap(int mode) { return mode == pj::MODE_ADJ ? pj::MAX_S_ADJ : pj::BATCH_MAX_S; }
+
 }  // namespace
 
 
@@ -33,37 +36,75 @@ int64_t seg_lds(const pj_batch::Seg& sg, int mode, int S, int W) {
 
 int lds_max_of(const pj_batch* b) { return b->segs.empty() ? 0 : b->segs[0].mech->m.lds_max; }
 
-int64_t batch_lds_states(const pj_batch* b, int mode, int S, int W) {
+// bytes of the adjoint's per-reaction parameter sums of one segment in LDS
+int64_t seg_gr(const pj_batch::Seg& sg) { return 3 * (int64_t)sg.mech->m.dm.nr_pad * 8; }
+
+// The persistent launch of a batch at shape S x W for a mode.  The adjoint
+// keeps each segment's parameter sums in LDS after its states' arrays when
+// every segment's fit at S states (else they go to the output per group).
+// need: the largest LDS a segment takes at S states; the workgroups a
+// compute unit then holds, k = LDS / need, set the budget LDS / k, and each
+// segment takes the most states per group (S doubled, at most BATCH_MAX_S,
+// the adjoint MAX_S_ADJ) whose LDS fits it: the largest mechanism keeps S,
+// smaller ones hold more states at the same occupancy.  lds: the launch's
+// LDS per workgroup (the largest segment's at its states).
+struct Plan {
+    int mode = 0, S = 1, W = 1;
+    bool gr = false;
+    int64_t need = 0, budget = 0;
+
+    int64_t tot(const pj_batch::Seg& sg, int s) const { return seg_lds(sg, mode, s, W) + (gr ? seg_gr(sg) : 0); }
+    // states per group of a segment
+    int states(const pj_batch::Seg& sg) const {
+        int s = S;
+        if (sg.n > 0)
+            while (s * 2 <= batch_cap(mode) && tot(sg, s * 2) <= budget) s *= 2;
+        return s;
+    }
+    // LDS offset (doubles) of a segment's parameter sums, or -1
+    int64_t gr_off(const pj_batch::Seg& sg) const { return gr ? seg_lds(sg, mode, states(sg), W) / 8 : -1; }
+};
+
+Plan make_plan(const pj_batch* b, int mode, int S, int W) {
+    Plan pl;
+    pl.mode = mode;
+    pl.S = S;
+    pl.W = W;
+    const int64_t mx = lds_max_of(b);
+    auto need = [&]() {
+        int64_t l = 0;
+        for (auto& sg : b->segs)
+            if (sg.n > 0) l = std::max(l, pl.tot(sg, S));
+        return l;
+    };
+    pl.gr = mode == pj::MODE_ADJ;
+    if (pl.gr && need() > mx) pl.gr = false;
+    pl.need = need();
+    const int64_t k = pl.need > 0 ? std::max<int64_t>(1, mx / pl.need) : 1;
+    pl.budget = std::max(pl.need, mx / k);
+    return pl;
+}
+
+// the launch's LDS per workgroup: the largest segment's at its states
+int64_t plan_lds(const pj_batch* b, const Plan& pl) {
     int64_t l = 0;
-    for (auto& sg : b->segs) l = std::max(l, seg_lds(sg, mode, S, W));
+    for (auto& sg : b->segs)
+        if (sg.n > 0) l = std::max(l, pl.tot(sg, pl.states(sg)));
     return l;
 }
 
-int lds_max_of(const pj_batch* b);
+// the LDS the batch needs at S x W (its largest segment at S states)
+int64_t batch_lds(const pj_batch* b, int mode, int S, int W) { return make_plan(b, mode, S, W).need; }
 
-// adjoint: room for the largest segment's parameter sums after the per-state
-// arrays, when it fits; gr_off receives their offset in doubles, or -1
-int64_t batch_lds(const pj_batch* b, int mode, int S, int W, int64_t* gr_off = nullptr) {
-    const int64_t l = batch_lds_states(b, mode, S, W);
-    if (gr_off) *gr_off = -1;
-    if (mode != pj::MODE_ADJ) return l;
-    int64_t nrp = 0;
-    for (auto& sg : b->segs) nrp = std::max<int64_t>(nrp, sg.mech->m.dm.nr_pad);
-    const int64_t with = l + 3 * nrp * 8;
-    if (with > lds_max_of(b)) return l;
-    if (gr_off) *gr_off = l / 8;
-    return with;
-}
-
-// launch shape of the batch for a mode: the user's if it fits, else the most
-// states per workgroup (<= 4) that fit every segment's working set, with
-// enough waves for about 8 resident waves per compute unit
+// launch shape of the batch for a mode: the user's (or autotuned) if it
+// fits, else the most states per workgroup (<= 4) that fit every segment's
+// working set, with enough waves for about 8 resident waves per compute unit
 void batch_shape(const pj_batch* b, int mode, int& S, int& W) {
     const int mx = lds_max_of(b);
     S = 1;
     for (int c = 4; c >= 1; c >>= 1)
         if (batch_lds(b, mode, c, 1) <= mx) { S = c; break; }
-    if (b->user_S[mode] && b->user_S[mode] <= 4 &&
+    if (b->user_S[mode] && b->user_S[mode] <= batch_cap(mode) &&
         batch_lds(b, mode, b->user_S[mode], b->user_W[mode] ? b->user_W[mode] : 1) <= mx)
         S = b->user_S[mode];
     W = 1;
@@ -96,26 +137,46 @@ pj_status check_segments(const pj_batch* b, int mode, pj_form form, pj_layout la
     return PJ_OK;
 }
 
-// (re)build the device segment table for S states per workgroup
-pj_status upload_table(pj_batch* b, int S) {
-    if (b->table_valid && b->table_S == S) return PJ_OK;
-    std::vector<pj::BatchSeg> t;
+// (re)build the device segment table for the shape S x W of a mode
+// The persistent launch's segment table at S x W (the non-empty segments in
+// order) into t (room for cap entries): the number of entries, or -1 if they
+// exceed cap; *total: the groups of all, *ext: some segment's mechanism holds
+// the further reaction types.
+int fill_table(const pj_batch* b, int mode, int S, int W, pj::BatchSeg* t, int cap, long* total, int* ext) {
+    const Plan pl = make_plan(b, mode, S, W);
     long g0 = 0;
+    int k = 0;
+    *ext = 0;
     for (auto& sg : b->segs) {
         if (sg.n == 0) continue;
-        pj::BatchSeg x{};
+        if (k >= cap) return -1;
+        const int s = pl.states(sg);
+        pj::BatchSeg& x = t[k++];
+        x = pj::BatchSeg{};
         x.dm = sg.mech->m.dm;
         x.n = (long)sg.n;
-        x.state = sg.state;
-        x.param = sg.param;
-        x.dstate = sg.dstate;
-        x.out = sg.out;
-        x.vin = sg.v;
-        x.grad = sg.grad;
+        x.state = pj::gptr(sg.state);
+        x.param = pj::gptr(sg.param);
+        x.dstate = pj::gptr(sg.dstate);
+        x.out = pj::gptr(sg.out);
+        x.vin = pj::gptr(sg.v);
+        x.grad = pj::gptr(sg.grad);
         x.g0 = g0;
-        g0 += (long)((sg.n + S - 1) / S);
-        t.push_back(x);
+        x.S = s;
+        x.gr_off = pl.gr_off(sg);
+        g0 += (long)((sg.n + s - 1) / s);
+        *ext |= sg.mech->m.dm.ext;
     }
+    *total = g0;
+    return k;
+}
+
+pj_status upload_table(pj_batch* b, int mode, int S, int W) {
+    if (b->table_valid && b->table_S == S && b->table_W == W && b->table_mode == mode) return PJ_OK;
+    std::vector<pj::BatchSeg> t(b->segs.size());
+    long g0 = 0;
+    int ext = 0;
+    t.resize((size_t)fill_table(b, mode, S, W, t.data(), (int)t.size(), &g0, &ext));
     const size_t bytes = std::max<size_t>(1, t.size()) * sizeof(pj::BatchSeg);
     if (bytes > b->d_cap) {
         if (b->d_segs) (void)hipFree(b->d_segs);
@@ -127,6 +188,8 @@ pj_status upload_table(pj_batch* b, int S) {
     if (!t.empty() && hipMemcpy(b->d_segs, t.data(), t.size() * sizeof(pj::BatchSeg), hipMemcpyHostToDevice) != hipSuccess)
         return fail(PJ_E_DEVICE, "upload of the segment table failed");
     b->table_S = S;
+    b->table_W = W;
+    b->table_mode = mode;
     b->table_nseg = (int)t.size();
     b->table_total = g0;
     b->table_valid = true;
@@ -135,7 +198,7 @@ pj_status upload_table(pj_batch* b, int S) {
 
 // enqueue the whole batch (zeroing of the adjoint sums, then one launch)
 pj_status enqueue(pj_batch* b, int mode, pj_form form, pj_layout layout, int S, int W, hipStream_t st) {
-    pj_status r = upload_table(b, S);
+    pj_status r = upload_table(b, mode, S, W);
     if (r != PJ_OK) return r;
     if (mode == pj::MODE_ADJ)
         for (auto& sg : b->segs)
@@ -144,12 +207,10 @@ pj_status enqueue(pj_batch* b, int mode, pj_form form, pj_layout layout, int S, 
                 if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("zeroing failed: ") + hipGetErrorString(e));
             }
     if (b->table_total == 0) return PJ_OK;
-    int64_t gr_off = -1;
-    const int64_t lds = batch_lds(b, mode, S, W, &gr_off);
+    const int64_t lds = plan_lds(b, make_plan(b, mode, S, W));
     int ext = 0;   // the further reaction types' kernels if any segment needs them
     for (auto& sg : b->segs) ext |= sg.mech->m.dm.ext;
-    hipError_t e = pj::launch_batch(mode, form, layout, S, W, lds, b->d_segs, b->table_nseg, b->table_total,
-                                    gr_off, ext, st);
+    hipError_t e = pj::launch_batch(mode, form, layout, W, lds, b->d_segs, b->table_nseg, b->table_total, ext, st);
     if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
     return PJ_OK;
 }
@@ -187,10 +248,15 @@ pj_status batch_check(const pj_batch* b, int mode, pj_form form, pj_layout layou
     return check_segments(b, mode, form, layout);
 }
 void batch_shape_of(const pj_batch* b, int mode, int& S, int& W) { batch_shape(b, mode, S, W); }
-int64_t batch_lds_of(const pj_batch* b, int mode, int S, int W, int64_t* gr_off) {
-    return batch_lds(b, mode, S, W, gr_off);
+int64_t batch_lds_of(const pj_batch* b, int mode, int S, int W) { return batch_lds(b, mode, S, W); }
+int64_t batch_launch_lds(const pj_batch* b, int mode, int S, int W) {
+    return plan_lds(b, make_plan(b, mode, S, W));
+}
+int batch_fill_table(const pj_batch* b, int mode, int S, int W, BatchSeg* t, int cap, long* total, int* ext) {
+    return fill_table(b, mode, S, W, t, cap, total, ext);
 }
 int batch_lds_limit(const pj_batch* b) { return lds_max_of(b); }
+
 }  // namespace pj
 
 extern "C" {
@@ -239,8 +305,9 @@ int pj_batch_size(const pj_batch* b) { return b ? (int)b->segs.size() : -1; }
 pj_status pj_batch_set_launch(pj_batch* b, int mode, int states_per_group, int waves_per_group) {
     if (!b) return fail(PJ_E_INVALID, "NULL batch");
     if (!batch_mode(mode)) return fail(PJ_E_INVALID, "bad mode");
-    if (states_per_group != 0 && states_per_group != 1 && states_per_group != 2 && states_per_group != 4)
-        return fail(PJ_E_INVALID, "states_per_group must be 0, 1, 2 or 4");
+    if (states_per_group != 0 && (states_per_group < 1 || states_per_group > pj::BATCH_MAX_S ||
+                                  (states_per_group & (states_per_group - 1))))
+        return fail(PJ_E_INVALID, "states_per_group must be 0 or a power of two up to 16");
     if (waves_per_group < 0 || waves_per_group > 8)
         return fail(PJ_E_INVALID, "waves_per_group must be 0 (automatic) or 1 to 8");
     b->user_S[mode] = states_per_group;
@@ -257,6 +324,13 @@ int pj_batch_launch_shape(const pj_batch* b, int mode, int* states_per_group, in
     if (states_per_group) *states_per_group = S;
     if (waves_per_group) *waves_per_group = W;
     return 0;
+}
+
+int pj_batch_segment_states(const pj_batch* b, int mode, int segment) {
+    if (!b || !batch_mode(mode) || segment < 0 || segment >= (int)b->segs.size()) return -1;
+    int S, W;
+    batch_shape(b, mode, S, W);
+    return make_plan(b, mode, S, W).states(b->segs[(size_t)segment]);
 }
 
 pj_status pj_batch_set_strategy(pj_batch* b, int mode, int per_segment) {
@@ -302,7 +376,7 @@ pj_status pj_batch_eval_graph(pj_batch* b, int mode, pj_form form, pj_layout lay
         b->g_per_seg != ps) {
         b->drop_graph();
         if (!ps) {
-            r = upload_table(b, S);   // synchronous, outside the capture
+            r = upload_table(b, mode, S, W);   // synchronous, outside the capture
             if (r != PJ_OK) return r;
         }
         if (!b->capture_stream && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
@@ -354,11 +428,11 @@ pj_status pj_batch_autotune(pj_batch* b, int mode, pj_form form, pj_layout layou
     float best = -1.0f, bestp = -1.0f;
     pj_status err = PJ_OK;
     // every persistent launch shape that fits (S > 0), then one launch per
-    // segment at each mechanism's current shape (S = 0); the best persistent
-    // shape is kept for the mode either way
-    for (int S = 1; S <= 8 && err == PJ_OK; S *= 2)
+    // segment at each mechanism's current shape (S = 0 below); the best
+    // persistent shape is kept for the mode either way
+    for (int S = 1; S <= 2 * batch_cap(mode) && err == PJ_OK; S *= 2)
         for (int W = 1; W <= 8 && err == PJ_OK; ++W) {
-            const bool segs_each = S == 8;
+            const bool segs_each = S == 2 * batch_cap(mode);
             if (segs_each && W > 1) break;
             if (!segs_each && batch_lds(b, mode, S, W) > mx) continue;
             auto run = [&]() {

@@ -104,6 +104,22 @@ struct alignas(16) ThermoRec {       // 144 B
     double c[TH_N];
 };
 
+// Device pointers held in the table and batch descriptors: in the device
+// pass they are global-memory pointers, so that a descriptor read from
+// device memory (a ragged batch's segment table), like a kernel argument,
+// gives global rather than flat memory instructions; the host pass sees
+// plain pointers of the same size and layout.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PJ_GLOBAL __attribute__((address_space(1)))
+#else
+#define PJ_GLOBAL
+#endif
+// a device pointer as stored in a descriptor
+template <class T>
+inline PJ_GLOBAL T* gptr(T* p) {
+    return (PJ_GLOBAL T*)p;
+}
+
 struct DevMech {
     int ns, nr, nr_pad, N;
     int nnz;            // CSR non-zeros
@@ -111,32 +127,32 @@ struct DevMech {
     int bath;           // ns - 1
 
     // species
-    const ThermoRec* th;      // [ns][2] (low range, high range)
-    const double* tmid;       // [ns]
-    const double* wfac;       // [ns] 1 - W_k / W_Ns (0 for the bath gas)
+    const PJ_GLOBAL ThermoRec* th;      // [ns][2] (low range, high range)
+    const PJ_GLOBAL double* tmid;       // [ns]
+    const PJ_GLOBAL double* wfac;       // [ns] 1 - W_k / W_Ns (0 for the bath gas)
 
     // reactions
-    const RxnRec* rec;        // [nr_pad]
-    const FallRec* fall;      // [nr_pad]
-    const JacRec* jrec;       // [nr_pad]
-    const EffRec* effrec;     // [1 + reactions with third bodies]
-    const TabRec* tab;        // [reactions tabulated in pressure, at least 1]
-    const double* tabd;       // their tables
+    const PJ_GLOBAL RxnRec* rec;        // [nr_pad]
+    const PJ_GLOBAL FallRec* fall;      // [nr_pad]
+    const PJ_GLOBAL JacRec* jrec;       // [nr_pad]
+    const PJ_GLOBAL EffRec* effrec;     // [1 + reactions with third bodies]
+    const PJ_GLOBAL TabRec* tab;        // [reactions tabulated in pressure, at least 1]
+    const PJ_GLOBAL double* tabd;       // their tables
 
     // pattern
-    const int32_t* row_ptr;   // [N + 1]
-    const uint16_t* row_of;   // [nnz] row (state index) of each CSR entry
-    const uint16_t* ccs_pos;  // [nnz] position of CSR entry e in column order, or NULL
-    const uint16_t* dmap_rm;  // [N*N] CSR slot of (i, j) at i*N + j, NOSLOT if none
-    const uint16_t* dmap_cm;  // [N*N] the same at i + N*j; DMAP_SKIP for rows 0 and 1
+    const PJ_GLOBAL int32_t* row_ptr;   // [N + 1]
+    const PJ_GLOBAL uint16_t* row_of;   // [nnz] row (state index) of each CSR entry
+    const PJ_GLOBAL uint16_t* ccs_pos;  // [nnz] position of CSR entry e in column order, or NULL
+    const PJ_GLOBAL uint16_t* dmap_rm;  // [N*N] CSR slot of (i, j) at i*N + j, NOSLOT if none
+    const PJ_GLOBAL uint16_t* dmap_cm;  // [N*N] the same at i + N*j; DMAP_SKIP for rows 0 and 1
     int approx;               // approximate Jacobian (bath gas held against n_j)
     int ext;                  // holds SRI, chemically activated, P-Log or Chebyshev reactions
     int lsearch;              // find CSR slots by a run-time row search
     int det;                  // every LDS addition in a fixed order (bitwise reproducible)
-    const int32_t* orig;      // [nr] description index of each kernel-order reaction
-    const uint16_t* col_idx;  // [nnz]
-    const int32_t* dense_rows;// [n_dense_rows] species index k of bath-dense rows
-    const double* arr;        // NULL, or one call's Arrhenius parameters [ln A (nr), b (nr),
+    const PJ_GLOBAL int32_t* orig;      // [nr] description index of each kernel-order reaction
+    const PJ_GLOBAL uint16_t* col_idx;  // [nnz]
+    const PJ_GLOBAL int32_t* dense_rows;// [n_dense_rows] species index k of bath-dense rows
+    const PJ_GLOBAL double* arr;        // NULL, or one call's Arrhenius parameters [ln A (nr), b (nr),
                               // Ea/R (nr)] in description order, in place of the tables
 };
 
@@ -192,14 +208,21 @@ struct Mechanism {
 struct BatchSeg {
     DevMech dm;
     long n;                    // states of this segment
-    const double* state;
-    const double* param;
-    double* dstate;            // source terms (source mode) or fused source output
-    double* out;               // CSR values (sparse) or J^T v (adjoint)
-    const double* vin;         // adjoint: v
-    double* grad;              // adjoint: parameter sums (3 Nr) or NULL
+    const PJ_GLOBAL double* state;
+    const PJ_GLOBAL double* param;
+    PJ_GLOBAL double* dstate;            // source terms (source mode) or fused source output
+    PJ_GLOBAL double* out;               // CSR values (sparse) or J^T v (adjoint)
+    const PJ_GLOBAL double* vin;         // adjoint: v
+    PJ_GLOBAL double* grad;              // adjoint: parameter sums (3 Nr) or NULL
     long g0;                   // first global group index of this segment
+    int S;                     // states per group of this segment (1 to 16, a power of two)
+    long gr_off;               // adjoint: LDS offset (doubles) of its parameter sums, or -1
 };
+
+// The most states per group a segment of a ragged batch takes (the adjoint:
+// MAX_S_ADJ): segments of smaller mechanisms fill the workgroup LDS that the
+// largest mechanism's states set with more states each.
+constexpr int BATCH_MAX_S = 16;
 
 // mech.cpp
 pj_status build_mechanism(const char* path, Mechanism& m, std::string& err);
@@ -229,20 +252,18 @@ hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int6
                   const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,
                   hipStream_t stream);
 hipError_t zero_async(double* p, int64_t n, hipStream_t stream);
-// batch kernel (modes source, sparse, adjoint; S = 1, 2, 4)
-// gr_off: LDS offset (doubles) of the adjoint's per-segment parameter sums, or -1
+// batch kernel (modes source, sparse, adjoint; each segment's states per
+// group and adjoint parameter-sum placement in its table entry)
 // ext: some segment's mechanism holds the further reaction types
-hipError_t launch_batch(int mode, int form, int layout, int S, int waves, int64_t lds,
-                        const BatchSeg* d_segs, int nseg, int64_t total_groups, int64_t gr_off,
-                        int ext, hipStream_t stream);
+hipError_t launch_batch(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,
+                        int nseg, int64_t total_groups, int ext, hipStream_t stream);
 // kernels_ext.hip: the same launches for mechanisms with the further reaction types
 hipError_t launch_ext(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
                       const double* state, const double* param, double* dstate, double* jac,
                       const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,
                       hipStream_t stream);
-hipError_t launch_batch_ext(int mode, int form, int layout, int S, int waves, int64_t lds,
-                            const BatchSeg* d_segs, int nseg, int64_t total_groups, int64_t gr_off,
-                            hipStream_t stream);
+hipError_t launch_batch_ext(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,
+                            int nseg, int64_t total_groups, hipStream_t stream);
 // api.cpp
 void choose_launch(Mechanism& m);
 
@@ -276,7 +297,7 @@ struct pj_batch {
     // device copy of the segment table, for the shape it was built with
     pj::BatchSeg* d_segs = nullptr;
     size_t d_cap = 0;
-    int table_S = 0, table_nseg = 0;
+    int table_S = 0, table_W = 0, table_mode = -1, table_nseg = 0;
     int64_t table_total = 0;
     bool table_valid = false;
     // captured graph and what it was captured for
@@ -303,6 +324,12 @@ pj_status batch_fail(pj_status st, const std::string& msg);
 void batch_ok();
 pj_status batch_check(const pj_batch* b, int mode, pj_form form, pj_layout layout);
 void batch_shape_of(const pj_batch* b, int mode, int& S, int& W);
-int64_t batch_lds_of(const pj_batch* b, int mode, int S, int W, int64_t* gr_off);
+// the LDS the batch needs at S x W, and its launch's LDS per workgroup
+int64_t batch_lds_of(const pj_batch* b, int mode, int S, int W);
+int64_t batch_launch_lds(const pj_batch* b, int mode, int S, int W);
+// the persistent launch's segment table at S x W into t (room for cap
+// entries): the entry count (-1 beyond cap), the groups of all in *total,
+// whether a mechanism needs the further reaction types' kernels in *ext
+int batch_fill_table(const pj_batch* b, int mode, int S, int W, BatchSeg* t, int cap, long* total, int* ext);
 int batch_lds_limit(const pj_batch* b);
 }  // namespace pj

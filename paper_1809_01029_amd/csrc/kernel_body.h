@@ -121,62 +121,74 @@ __device__ inline dd dd_add(dd a, dd b) {
 // Sum over the lanes of a wave that work for the same state (lanes equal
 // modulo S); every such lane receives the sum.
 template <int S>
-__device__ inline double wave_sum(double v) {
+__device__ inline double wave_sum(double v, int Sr = S) {
+    if constexpr (S > 0) {
 #pragma unroll
-    for (int o = 32; o >= S; o >>= 1) v += __shfl_xor(v, o, 64);
+        for (int o = 32; o >= S; o >>= 1) v += __shfl_xor(v, o, 64);
+    } else {
+        for (int o = 32; o >= Sr; o >>= 1) v += __shfl_xor(v, o, 64);
+    }
     return v;
 }
 
 // Per-state sum of K per-thread values over the workgroup, in a fixed order;
 // every thread receives the totals of its state.  red: LDS scratch of
-// RED_PER_WAVE * nwave * S doubles.
+// RED_PER_WAVE * nwave * S doubles.  S = 0: Sr states per group, known at
+// run time.
 template <int S, int K>
-__device__ inline void block_sum(double (&v)[K], double* red, int wave, int nwave, int s) {
+__device__ inline void block_sum(double (&v)[K], double* red, int wave, int nwave, int s, int Sr = S) {
+    const int SR = S > 0 ? S : Sr;
 #pragma unroll
-    for (int q = 0; q < K; ++q) v[q] = wave_sum<S>(v[q]);
+    for (int q = 0; q < K; ++q) v[q] = wave_sum<S>(v[q], SR);
     if (nwave == 1) return;
-    if ((threadIdx.x & 63) < S) {
+    if ((threadIdx.x & 63) < SR) {
 #pragma unroll
-        for (int q = 0; q < K; ++q) red[(wave * K + q) * S + s] = v[q];
+        for (int q = 0; q < K; ++q) red[(wave * K + q) * SR + s] = v[q];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < K; ++q) {
         double t = 0.0;
-        for (int w = 0; w < nwave; ++w) t += red[(w * K + q) * S + s];
+        for (int w = 0; w < nwave; ++w) t += red[(w * K + q) * SR + s];
         v[q] = t;
     }
     __syncthreads();
 }
 
 template <int S>
-__device__ inline dd block_dd_sum(dd a, double* red, int wave, int nwave, int s) {
-#pragma unroll
-    for (int o = 32; o >= S; o >>= 1) {
+__device__ inline dd block_dd_sum(dd a, double* red, int wave, int nwave, int s, int Sr = S) {
+    const int SR = S > 0 ? S : Sr;
+    auto step = [&](int o) {
         dd b{__shfl_xor(a.hi, o, 64), __shfl_xor(a.lo, o, 64)};
         a = dd_add(a, b);
+    };
+    if constexpr (S > 0) {
+#pragma unroll
+        for (int o = 32; o >= S; o >>= 1) step(o);
+    } else {
+        for (int o = 32; o >= SR; o >>= 1) step(o);
     }
     if (nwave == 1) return a;
-    if ((threadIdx.x & 63) < S) {
-        red[(2 * wave) * S + s] = a.hi;
-        red[(2 * wave + 1) * S + s] = a.lo;
+    if ((threadIdx.x & 63) < SR) {
+        red[(2 * wave) * SR + s] = a.hi;
+        red[(2 * wave + 1) * SR + s] = a.lo;
     }
     __syncthreads();
     dd t{0.0, 0.0};
-    for (int w = 0; w < nwave; ++w) t = dd_add(t, dd{red[(2 * w) * S + s], red[(2 * w + 1) * S + s]});
+    for (int w = 0; w < nwave; ++w) t = dd_add(t, dd{red[(2 * w) * SR + s], red[(2 * w + 1) * SR + s]});
     __syncthreads();
     return t;
 }
 
 // 16-byte vector loads of a table record
 template <class T>
-__device__ inline T load_rec(const T* src) {
+__device__ inline T load_rec(const PJ_GLOBAL T* src) {
     static_assert(sizeof(T) % 16 == 0, "record size");
     union U {
         T t;
         uint4 v[sizeof(T) / 16];
     } u;
-    const uint4* q = reinterpret_cast<const uint4*>(src);
+    const PJ_GLOBAL uint4* q = (const PJ_GLOBAL uint4*)src;
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(T) / 16); ++i) u.v[i] = q[i];
     return u.t;
@@ -293,8 +305,10 @@ __device__ inline void powd(double c, int nu, double& f, double& d) {
 
 // One group of S consecutive states (group index qg of a batch of n): the
 // body shared by the per-mechanism kernel and the ragged multi-mechanism
-// kernel.  GR / gr_lds: the adjoint's per-workgroup parameter sums in LDS (or
-// per-group device atomics when gr_lds is false).
+// kernel.  S = 0: Sr states per group, given at run time (the ragged kernel,
+// whose segments each have their own).  GR / gr_lds: the adjoint's
+// per-workgroup parameter sums in LDS (or per-group device atomics when
+// gr_lds is false).
 template <int FORM, int LAYOUT, int MODE, int S, bool EXT>
 __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                                            const double* __restrict__ state,
@@ -303,8 +317,13 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                                            double* __restrict__ jac,
                                            const double* __restrict__ vin,
                                            double* __restrict__ grad,
-                                           const bool gr_lds, double* GR, const long qg) {
+                                           const bool gr_lds, double* GR, const long qg,
+                                           const int Sr = S) {
     extern __shared__ double lds[];
+    // states per group: S, or Sr (a power of two, 1 to 16) when S = 0;
+    // LG = log2 of it (indexing by shifts also when it is known at run time)
+    const int SR = S > 0 ? S : Sr;
+    const int LG = __builtin_ctz((unsigned)SR);
     constexpr int M = base_mode(MODE);
     constexpr bool PAR = MODE == MODE_SRC_P || MODE == MODE_ADJ_P;   // the call's own Arrhenius parameters
     constexpr bool DET = MODE == MODE_SRC_DET || MODE == MODE_SPARSE_DET;   // additions in a fixed order
@@ -315,29 +334,29 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
     const int ns = dm.ns, N = dm.N, bath = dm.bath, nnz = dm.nnz;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, nwave = nthr >> 6;
-    const int s = tid % S;          // the state of this thread within the group
-    const int g = tid / S;          // its index among the threads of that state
-    const int G = nthr / S;         // threads per state
+    const int s = tid & (SR - 1);    // the state of this thread within the group
+    const int g = tid >> LG;         // its index among the threads of that state
+    const int G = nthr >> LG;        // threads per state
 
     double* C = lds;
-    double* Gg = C + (ns + 1) * S;
-    double* H = Gg + (ns + 1) * S;
-    double* CP = H + (ns + 1) * S;
-    double* W = CP + (ns + 1) * S;
-    double* red = W + (ns + 1) * S;
-    double* J = red + RED_PER_WAVE * nwave * S;
-    double* B = J + (size_t)nnz * S;
-    double* VV = B + (size_t)ns * S;      // adjoint: v, then J^T v
-    double* JTV = VV + (size_t)N * S;
+    double* Gg = C + (ns + 1) * SR;
+    double* H = Gg + (ns + 1) * SR;
+    double* CP = H + (ns + 1) * SR;
+    double* W = CP + (ns + 1) * SR;
+    double* red = W + (ns + 1) * SR;
+    double* J = red + RED_PER_WAVE * nwave * SR;
+    double* B = J + (size_t)nnz * SR;
+    double* VV = B + (size_t)ns * SR;      // adjoint: v, then J^T v
+    double* JTV = VV + (size_t)N * SR;
     // The LDS of the T and V/P rows (the first 2N CSR slots) holds the
     // energy- and mole-weighted partial sums; the finished rows are staged
     // in the G and H arrays.
     double* TQ = J;
-    double* SQ = J + (size_t)N * S;
-#define AT(arr, i) (arr)[(size_t)(i) * S + s]
+    double* SQ = J + (size_t)N * SR;
+#define AT(arr, i) (arr)[((size_t)(i) << LG) + s]
 
     {
-        const long st = qg * S + s;           // this thread's state
+        const long st = qg * SR + s;           // this thread's state
         const bool valid = st < n;
         const long sc = valid ? st : n - 1;   // states past the end compute a copy of the last
         auto X = [&](int i) -> double {
@@ -368,7 +387,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             for (int i = g; i < N; i += G)
                 AT(VV, i) = LAYOUT == PJ_LAYOUT_F ? vin[(long)i * n + sc] : vin[sc * (long)N + i];
         }
-        acc = block_dd_sum<S>(acc, red, wave, nwave, s);
+        acc = block_dd_sum<S>(acc, red, wave, nwave, s, SR);
         const double nsum = acc.hi;
         const double ntot = (P * V) / (RU * T);
         const double nbath = ntot - nsum;
@@ -404,7 +423,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             tsum[0] += ck * ch;
             if (JAC) tsum[1] += ck * (a1 + T * (a(14) + T * (a(15) + T * a(16))));
         }
-        block_sum<S>(tsum, red, wave, nwave, s);
+        block_sum<S>(tsum, red, wave, nwave, s, SR);
         const double Dp = tsum[0];
         const double dDpdT = tsum[1];
         __syncthreads();
@@ -635,11 +654,16 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 // each state's own ln T and 1/T, before the sum over states
                 double g0 = valid ? lam * (q * qA - R * Pr_dcdPr) : 0.0;
                 double g1 = g0 * lnT, g2 = -g0 * invT;
-#pragma unroll
-                for (int o = 1; o < S; o <<= 1) {
+                auto fold = [&](int o) {
                     g0 += __shfl_xor(g0, o, 64);
                     g1 += __shfl_xor(g1, o, 64);
                     g2 += __shfl_xor(g2, o, 64);
+                };
+                if constexpr (S > 0) {
+#pragma unroll
+                    for (int o = 1; o < S; o <<= 1) fold(o);
+                } else {
+                    for (int o = 1; o < SR; o <<= 1) fold(o);
                 }
                 if (s == 0) {
                     if (gr_lds) {
@@ -765,7 +789,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             fsum[1] += dm.wfac[k] * wk;
             if (JAC) fsum[2] += AT(CP, k) * wk;
         }
-        block_sum<S>(fsum, red, wave, nwave, s);
+        block_sum<S>(fsum, red, wave, nwave, s, SR);
         const double Np = fsum[0], Om = fsum[1];
         const double Tdot = -T * Np / Dp;
         const double Sdot = FORM == PJ_CONP ? V * Tdot * invT + V * RU * T * Om / P
@@ -863,7 +887,8 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             // CSR slot e of state s: the T row (e < N) and V/P row (N <= e < 2N)
             // from their staging, the species rows from the accumulator
             auto val = [&](int e, int ss) -> double {
-                return e < N ? Gg[(size_t)e * S + ss] : e < 2 * N ? H[(size_t)(e - N) * S + ss] : J[(size_t)e * S + ss];
+                return e < N ? Gg[((size_t)e << LG) + ss]
+                             : e < 2 * N ? H[((size_t)(e - N) << LG) + ss] : J[((size_t)e << LG) + ss];
             };
             if (LAYOUT == PJ_LAYOUT_F) {
                 // S consecutive states of one slot are contiguous
@@ -886,7 +911,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 // one state's slots are contiguous: threads of one state take
                 // consecutive slots
                 const int s2 = tid / G, g2 = tid % G;
-                const long st2 = qg * S + s2;
+                const long st2 = qg * SR + s2;
                 if (st2 < n) {
                     if (dm.ccs_pos) {
                         int e = g2;
@@ -933,11 +958,11 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 }
             } else {
                 const int s2 = tid / G, g2 = tid % G;
-                const long st2 = qg * S + s2;
+                const long st2 = qg * SR + s2;
                 if (st2 < n) {
                     double* out = jac + st2 * NN;
                     for (int f = g2; f < 2 * N; f += G)
-                        out[f] = f < N ? Gg[(size_t)f * S + s2] : H[(size_t)(f - N) * S + s2];
+                        out[f] = f < N ? Gg[((size_t)f << LG) + s2] : H[((size_t)(f - N) << LG) + s2];
                     long f = 2 * N + g2;
                     for (; f + (DU - 1) * G < NN; f += DU * G) {
                         uint16_t e[DU];
@@ -945,11 +970,11 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                         for (int u = 0; u < DU; ++u) e[u] = dm.dmap_rm[f + u * G];
 #pragma unroll
                         for (int u = 0; u < DU; ++u)
-                            out[f + u * G] = e[u] == NOSLOT ? 0.0 : J[(size_t)e[u] * S + s2];
+                            out[f + u * G] = e[u] == NOSLOT ? 0.0 : J[((size_t)e[u] << LG) + s2];
                     }
                     for (; f < NN; f += G) {
                         const uint16_t e = dm.dmap_rm[f];
-                        out[f] = e == NOSLOT ? 0.0 : J[(size_t)e * S + s2];
+                        out[f] = e == NOSLOT ? 0.0 : J[((size_t)e << LG) + s2];
                     }
                 }
             }
@@ -1032,20 +1057,23 @@ __device__ inline void flush_gr(const BatchSeg& b, const double* GR) {
     __syncthreads();
 }
 
-template <int FORM, int LAYOUT, int MODE, int S, bool EXT>
-__global__ void __launch_bounds__(MAX_THREADS) pj_batch_kernel(const BatchSeg* __restrict__ segs,
-                                                                const int nseg, const long total,
-                                                                const long gr_off) {
+// (source terms: held to the register count of 3 waves per SIMD, as the
+// per-mechanism source kernel is)
+template <int FORM, int LAYOUT, int MODE, bool EXT>
+__global__ void __launch_bounds__(MAX_THREADS) __attribute__((amdgpu_waves_per_eu(MODE == MODE_SRC ? 3 : 1)))
+pj_batch_kernel(const BatchSeg* __restrict__ segs, const int nseg, const long total) {
     extern __shared__ double lds[];
     // Every segment is spread over the whole grid, each XCD taking a
     // contiguous share of it as for a single mechanism, so that segments of
-    // very different cost per group keep all XCDs equally busy.  Adjoint: the
-    // parameter sums of the segment in hand live in LDS at gr_off (gr_off < 0:
-    // added to the output per group) and are flushed once per segment.
-    const bool use_gr = MODE == MODE_ADJ && gr_off >= 0;
-    double* GR = use_gr ? lds + gr_off : nullptr;
+    // very different cost per group keep all XCDs equally busy.  Each segment
+    // has its own states per group (a run-time value of the one group body).
+    // Adjoint: the parameter sums of the segment in hand live in LDS at its
+    // gr_off, after its states' arrays (gr_off < 0: added to the output per
+    // group), and are flushed once per segment.
     for (int k = 0; k < nseg; ++k) {
         const BatchSeg& b = segs[k];
+        const bool use_gr = MODE == MODE_ADJ && b.gr_off >= 0;
+        double* GR = use_gr ? lds + b.gr_off : nullptr;
         const long ng = (k + 1 < nseg ? segs[k + 1].g0 : total) - b.g0;
         long q0, q1, qstep;
         group_range(ng, q0, q1, qstep);
@@ -1054,9 +1082,10 @@ __global__ void __launch_bounds__(MAX_THREADS) pj_batch_kernel(const BatchSeg* _
             for (int i = threadIdx.x; i < 3 * b.dm.nr_pad; i += blockDim.x) GR[i] = 0.0;
             __syncthreads();
         }
+        const int bs = b.S;
         for (long q = q0; q < q1; q += qstep)
-            eval_group<FORM, LAYOUT, MODE, S, EXT>(b.dm, b.n, b.state, b.param, b.dstate, b.out, b.vin,
-                                                   b.grad, use_gr && b.grad, GR, q);
+            eval_group<FORM, LAYOUT, MODE, 0, EXT>(b.dm, b.n, b.state, b.param, b.dstate, b.out, b.vin,
+                                                   b.grad, use_gr && b.grad, GR, q, bs);
         if (use_gr) flush_gr(b, GR);
     }
 }
@@ -1104,10 +1133,10 @@ static hipError_t launch_t(const DevMech& dm, int64_t n, const double* state, co
     return hipGetLastError();
 }
 
-template <int FORM, int LAYOUT, int MODE, int S, bool EXT>
+template <int FORM, int LAYOUT, int MODE, bool EXT>
 static hipError_t launch_batch_t(int waves, int64_t lds, const BatchSeg* segs, int nseg, int64_t total,
-                                 int64_t gr_off, hipStream_t stream) {
-    auto k = pj_batch_kernel<FORM, LAYOUT, MODE, S, EXT>;
+                                 hipStream_t stream) {
+    auto k = pj_batch_kernel<FORM, LAYOUT, MODE, EXT>;
     if (lds > 65536) {
         static std::atomic<uint64_t> done{0};
         hipError_t e = allow_full_lds((const void*)k, done);
@@ -1119,8 +1148,7 @@ static hipError_t launch_batch_t(int waves, int64_t lds, const BatchSeg* segs, i
     const int64_t cap = MODE == MODE_ADJ ? 2048 : 8192;
     int64_t grid = total < cap ? total : cap;
     if (grid >= 8) grid &= ~(int64_t)7;
-    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * waves), (size_t)lds, stream, segs, nseg, (long)total,
-                       (long)gr_off);
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * waves), (size_t)lds, stream, segs, nseg, (long)total);
     return hipGetLastError();
 }
 
@@ -1162,20 +1190,17 @@ hipError_t launch_impl(const DevMech& dm, int mode, int form, int layout, int S,
 }
 
 template <bool EXT>
-hipError_t launch_batch_impl(int mode, int form, int layout, int S, int waves, int64_t lds,
-                             const BatchSeg* d_segs, int nseg, int64_t total, int64_t gr_off,
-                             hipStream_t stream) {
-#define PJ_BCASE(F, L, M, SS)                                                            \
-    if (form == F && layout == L && mode == M && S == SS)                                \
-        return launch_batch_t<F, L, M, SS, EXT>(waves, lds, d_segs, nseg, total, gr_off, stream);
-#define PJ_BS(F, L, M) PJ_BCASE(F, L, M, 1) PJ_BCASE(F, L, M, 2) PJ_BCASE(F, L, M, 4)
-#define PJ_BMODES(F, L) PJ_BS(F, L, MODE_SRC) PJ_BS(F, L, MODE_SPARSE) PJ_BS(F, L, MODE_ADJ)
+hipError_t launch_batch_impl(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,
+                             int nseg, int64_t total, hipStream_t stream) {
+#define PJ_BCASE(F, L, M)                                                                \
+    if (form == F && layout == L && mode == M)                                           \
+        return launch_batch_t<F, L, M, EXT>(waves, lds, d_segs, nseg, total, stream);
+#define PJ_BMODES(F, L) PJ_BCASE(F, L, MODE_SRC) PJ_BCASE(F, L, MODE_SPARSE) PJ_BCASE(F, L, MODE_ADJ)
     PJ_BMODES(PJ_CONP, PJ_LAYOUT_F)
     PJ_BMODES(PJ_CONP, PJ_LAYOUT_C)
     PJ_BMODES(PJ_CONV, PJ_LAYOUT_F)
     PJ_BMODES(PJ_CONV, PJ_LAYOUT_C)
 #undef PJ_BMODES
-#undef PJ_BS
 #undef PJ_BCASE
     return hipErrorInvalidValue;
 }

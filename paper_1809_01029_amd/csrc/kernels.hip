@@ -36,11 +36,10 @@ hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int6
                               grad_in_lds, waves, lds, stream);
 }
 
-hipError_t launch_batch(int mode, int form, int layout, int S, int waves, int64_t lds,
-                        const BatchSeg* d_segs, int nseg, int64_t total, int64_t gr_off, int ext,
-                        hipStream_t stream) {
-    if (ext) return launch_batch_ext(mode, form, layout, S, waves, lds, d_segs, nseg, total, gr_off, stream);
-    return launch_batch_impl<false>(mode, form, layout, S, waves, lds, d_segs, nseg, total, gr_off, stream);
+hipError_t launch_batch(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,
+                        int nseg, int64_t total, int ext, hipStream_t stream) {
+    if (ext) return launch_batch_ext(mode, form, layout, waves, lds, d_segs, nseg, total, stream);
+    return launch_batch_impl<false>(mode, form, layout, waves, lds, d_segs, nseg, total, stream);
 }
 
 }  // namespace pj

@@ -12,10 +12,9 @@ hipError_t launch_ext(const DevMech& dm, int mode, int form, int layout, int S, 
                              grad_in_lds, waves, lds, stream);
 }
 
-hipError_t launch_batch_ext(int mode, int form, int layout, int S, int waves, int64_t lds,
-                            const BatchSeg* d_segs, int nseg, int64_t total, int64_t gr_off,
-                            hipStream_t stream) {
-    return launch_batch_impl<true>(mode, form, layout, S, waves, lds, d_segs, nseg, total, gr_off, stream);
+hipError_t launch_batch_ext(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,
+                            int nseg, int64_t total, hipStream_t stream) {
+    return launch_batch_impl<true>(mode, form, layout, waves, lds, d_segs, nseg, total, stream);
 }
 
 }  // namespace pj

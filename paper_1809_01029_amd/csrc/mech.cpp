@@ -609,23 +609,23 @@ pj_status upload_mechanism(Mechanism& m, std::string& err) {
     dm.nnz = m.nnz;
     dm.n_dense_rows = n_dense;
     dm.bath = bath;
-    dm.th = (const ThermoRec*)P(o_th);
-    dm.tmid = (const double*)P(o_tmid);
-    dm.wfac = (const double*)P(o_wfac);
-    dm.rec = (const RxnRec*)P(o_rec);
-    dm.fall = (const FallRec*)P(o_fall);
-    dm.jrec = (const JacRec*)P(o_jrec);
-    dm.effrec = (const EffRec*)P(o_eff);
-    dm.tab = (const TabRec*)P(o_tab);
-    dm.tabd = (const double*)P(o_tabd);
-    dm.row_ptr = (const int32_t*)P(o_rowp);
-    dm.col_idx = (const uint16_t*)P(o_col);
-    dm.dense_rows = (const int32_t*)P(o_dr);
-    dm.row_of = (const uint16_t*)P(o_rowof);
-    dm.orig = (const int32_t*)P(o_orig);
-    dm.ccs_pos = (m.opts & PJ_OPT_CCS) ? (const uint16_t*)P(o_ccs) : nullptr;
-    dm.dmap_rm = (const uint16_t*)P(o_dmrm);
-    dm.dmap_cm = (const uint16_t*)P(o_dmcm);
+    dm.th = gptr((const ThermoRec*)P(o_th));
+    dm.tmid = gptr((const double*)P(o_tmid));
+    dm.wfac = gptr((const double*)P(o_wfac));
+    dm.rec = gptr((const RxnRec*)P(o_rec));
+    dm.fall = gptr((const FallRec*)P(o_fall));
+    dm.jrec = gptr((const JacRec*)P(o_jrec));
+    dm.effrec = gptr((const EffRec*)P(o_eff));
+    dm.tab = gptr((const TabRec*)P(o_tab));
+    dm.tabd = gptr((const double*)P(o_tabd));
+    dm.row_ptr = gptr((const int32_t*)P(o_rowp));
+    dm.col_idx = gptr((const uint16_t*)P(o_col));
+    dm.dense_rows = gptr((const int32_t*)P(o_dr));
+    dm.row_of = gptr((const uint16_t*)P(o_rowof));
+    dm.orig = gptr((const int32_t*)P(o_orig));
+    dm.ccs_pos = (m.opts & PJ_OPT_CCS) ? gptr((const uint16_t*)P(o_ccs)) : nullptr;
+    dm.dmap_rm = gptr((const uint16_t*)P(o_dmrm));
+    dm.dmap_cm = gptr((const uint16_t*)P(o_dmcm));
     dm.arr = nullptr;
     dm.approx = (m.opts & PJ_OPT_APPROX_JACOBIAN) ? 1 : 0;
     dm.lsearch = (m.opts & PJ_OPT_LINEAR_SEARCH) ? 1 : 0;

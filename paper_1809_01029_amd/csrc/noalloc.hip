@@ -57,10 +57,9 @@ extern "C" pj_status pj_batch_eval_noalloc(pj_batch* b, int mode, pj_form form, 
                                                     " non-empty segments, the batch has " + std::to_string(nseg));
     int S, W;
     pj::batch_shape_of(b, mode, S, W);
-    int64_t gr_off = -1;
-    const int64_t lds = pj::batch_lds_of(b, mode, S, W, &gr_off);
-    if (lds > pj::batch_lds_limit(b))
+    if (pj::batch_lds_of(b, mode, S, W) > pj::batch_lds_limit(b))
         return pj::batch_fail(PJ_E_UNSUPPORTED, "a segment's working set exceeds the LDS of one workgroup");
+    const int64_t lds = pj::batch_launch_lds(b, mode, S, W);
     const hipStream_t st = (hipStream_t)stream;
     // the adjoint's parameter sums start at zero (a fill kernel, as pj_batch_eval)
     if (mode == pj::MODE_ADJ)
@@ -81,30 +80,16 @@ extern "C" pj_status pj_batch_eval_noalloc(pj_batch* b, int mode, pj_form form, 
     if (r != PJ_OK) return r;
     // the table on the host, in the batch's own staging array
     long g0 = 0;
-    int k = 0, ext = 0;
-    for (const auto& sg : b->segs) {
-        if (sg.n == 0) continue;
-        pj::BatchSeg& x = b->noalloc_host[k++];
-        x = pj::BatchSeg{};
-        x.dm = sg.mech->m.dm;
-        x.n = (long)sg.n;
-        x.state = sg.state;
-        x.param = sg.param;
-        x.dstate = sg.dstate;
-        x.out = sg.out;
-        x.vin = sg.v;
-        x.grad = sg.grad;
-        x.g0 = g0;
-        g0 += (long)((sg.n + S - 1) / S);
-        ext |= sg.mech->m.dm.ext;
-    }
+    int ext = 0;
+    if (pj::batch_fill_table(b, mode, S, W, b->noalloc_host, pj::NOALLOC_MAX_SEGS, &g0, &ext) != nseg)
+        return pj::batch_fail(PJ_E_UNSUPPORTED, "segment table does not match the batch");
     // stream-ordered: a call on the same stream waits for the previous one's
     // launch before it overwrites the table
     hipError_t e = hipMemcpyAsync(d_table, b->noalloc_host, (size_t)nseg * sizeof(pj::BatchSeg),
                                   hipMemcpyHostToDevice, st);
     if (e != hipSuccess)
         return pj::batch_fail(PJ_E_DEVICE, std::string("upload of the segment table: ") + hipGetErrorString(e));
-    e = pj::launch_batch(mode, form, layout, S, W, lds, d_table, nseg, g0, gr_off, ext, st);
+    e = pj::launch_batch(mode, form, layout, W, lds, d_table, nseg, g0, ext, st);
     if (e != hipSuccess) return pj::batch_fail(PJ_E_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
     pj::batch_ok();
     return PJ_OK;

@@ -200,10 +200,14 @@ def test_batch_argument_checks(api, tmp_path):
     assert lib.pj_batch_add(b, mech.handle, -1, dummy, dummy, dummy, None, None, None) == 1
     assert lib.pj_batch_add(b, mech.handle, 4, dummy, dummy, dummy, None, None, None) == 0
     assert lib.pj_batch_size(b) == 1
-    for mode, S, W in ((2, 1, 1), (1, 8, 1), (1, 3, 1), (1, 1, 9), (1, 1, -1)):
+    for mode, S, W in ((2, 1, 1), (1, 32, 1), (1, 3, 1), (1, 12, 1), (1, 1, 9), (1, 1, -1)):
         assert lib.pj_batch_set_launch(b, mode, S, W) == 1
     assert lib.pj_batch_set_launch(b, 1, 2, 4) == 0
     assert lib.pj_batch_set_launch(b, 1, 2, 7) == 0
+    # per-segment states: -1 for a NULL batch, a bad mode or segment index
+    assert lib.pj_batch_segment_states(None, 1, 0) == -1
+    assert lib.pj_batch_segment_states(b, 2, 0) == -1
+    assert lib.pj_batch_segment_states(b, 1, 1) == -1 and lib.pj_batch_segment_states(b, 1, -1) == -1
     # strategy: one persistent launch (0, the default) or one per segment (1)
     assert lib.pj_batch_strategy(b, 1) == 0
     assert lib.pj_batch_set_strategy(b, 1, 2) == 1

@@ -104,16 +104,25 @@ def test_batch_matches_oracle(torch_cuda, api, form, mode, layout, mech_dir):
 @pytest.mark.parametrize("mode", ["source", "sparse"])
 def test_batch_equals_per_mechanism_launch(torch_cuda, api, mode, mech_dir):
     """One wave per workgroup: every accumulation in program order, so the
-    batch gives the per-mechanism launch's bits."""
+    batch gives the bits of the per-mechanism launch at each segment's own
+    states per workgroup (the smaller mechanisms take more states in the LDS
+    the largest one sets)."""
     torch = torch_cuda
     b, segs = build(torch, api, mech_dir, "conp", "C", mode)
-    for S in (1, 2):
+    for S in (1, 2, 4):
         b.set_launch(mode, S, 1)
+        seg_S = b.segment_states(mode)
+        note(f"{mode} base S={S}: segment states {seg_S}")
+        assert all(s >= S and s <= 16 and (s & (s - 1)) == 0 for s in seg_S)
+        # the largest mechanism keeps the base shape
+        assert seg_S[-1] == S
+        if S == 1:
+            assert seg_S[0] > seg_S[-1]   # the 13-species segment holds more states
         b.eval(mode, "conp", "C")
-        for sg in segs:
+        for k, sg in enumerate(segs):
             if sg["x"].shape[0] == 0:
                 continue
-            sg["mech"].set_launch(S, 1)
+            sg["mech"].set_launch(seg_S[k], 1)
             if mode == "source":
                 ref = api.eval_source(sg["mech"], sg["xs"], sg["ps"], "conp", "C")
                 torch.cuda.synchronize()
@@ -173,10 +182,10 @@ def test_batch_autotune(torch_cuda, api, mech_dir):
         # one launch per segment won; the best persistent shape is kept
         assert W == 0 and b.strategy("sparse")
         Sp, Wp = b.launch_shape("sparse")
-        assert Sp in (1, 2, 4) and 1 <= Wp <= 8
+        assert Sp in (1, 2, 4, 8, 16) and 1 <= Wp <= 8
     else:
         assert not b.strategy("sparse")
-        assert b.launch_shape("sparse") == (S, W) and S in (1, 2, 4) and 1 <= W <= 8
+        assert b.launch_shape("sparse") == (S, W) and S in (1, 2, 4, 8, 16) and 1 <= W <= 8
     for sg in segs:
         if sg["out"] is not None:
             sg["out"].zero_()
@@ -222,8 +231,9 @@ def test_batch_per_segment_launches(torch_cuda, api, form, mode, layout, mech_di
 C5 = [("ns13", 3000, 2013), ("ns53", 70000, 2053), ("ns111", 20000, 2111)]
 
 
+@pytest.mark.parametrize("strategy", ["auto", "persistent"])
 @pytest.mark.parametrize("mode", ["source", "adjoint"])
-def test_ragged_batch_full_counts(torch_cuda, api, mode, mech_dir):
+def test_ragged_batch_full_counts(torch_cuda, api, mode, strategy, mech_dir):
     """The ragged batch at its stated counts through the captured graph
     (autotuned strategy), replayed twice: every segment sampled (first and
     last state included) against the oracle; for the adjoint, each
@@ -250,7 +260,11 @@ def test_ragged_batch_full_counts(torch_cuda, api, mode, mech_dir):
         segs.append(dict(name=name, path=path, mech=mech, x=x, p=p, v=v, xs=xs, ps=ps, vs=vs, d=d, out=out,
                          grad=grad, n=n))
     S, W, ms = b.autotune(mode, "conp", "C", reps=1)
-    note(f"ragged {mode} at full counts: autotune S={S} W={W} per_segment={b.strategy(mode)} {ms:.3f} ms")
+    if strategy == "persistent":
+        # the one persistent launch at its best shape, whatever won
+        b.set_strategy(mode, False)
+    note(f"ragged {mode} at full counts: autotune S={S} W={W} per_segment={b.strategy(mode)} {ms:.3f} ms, "
+         f"shape {b.launch_shape(mode)}, segment states {b.segment_states(mode)}")
     for r in range(2):
         for sg in segs:
             sg["d"].zero_()
