@@ -88,8 +88,8 @@ namespace pj {
 
 namespace {
 
-// LDS scratch of the workgroup reductions, per state and wave: up to 8 values
-constexpr int RED_PER_WAVE = 8;
+// LDS scratch of the workgroup reductions, per state and wave: up to 10 values
+constexpr int RED_PER_WAVE = 10;
 constexpr int MAX_THREADS = 512;
 
 struct dd {
@@ -137,6 +137,7 @@ __device__ inline double wave_sum(double v, int Sr = S) {
 // run time.
 template <int S, int K>
 __device__ inline void block_sum(double (&v)[K], double* red, int wave, int nwave, int s, int Sr = S) {
+    static_assert(K <= RED_PER_WAVE, "reduction scratch per wave");
     const int SR = S > 0 ? S : Sr;
 #pragma unroll
     for (int q = 0; q < K; ++q) v[q] = wave_sum<S>(v[q], SR);
@@ -345,9 +346,12 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
     double* W = CP + (ns + 1) * SR;
     double* red = W + (ns + 1) * SR;
     double* J = red + RED_PER_WAVE * nwave * SR;
-    double* B = J + (size_t)nnz * SR;
-    double* VV = B + (size_t)ns * SR;      // adjoint: v, then J^T v
-    double* JTV = VV + (size_t)N * SR;
+    // the adjoint forms J^T v without the Jacobian: of J it keeps the T and
+    // V/P rows' partial sums only
+    const int nj = ADJ ? 2 * N : nnz;
+    double* B = J + (size_t)nj * SR;
+    double* VV = B + (size_t)ns * SR;      // adjoint: v
+    double* JTV = VV + (size_t)N * SR;     // adjoint: J^T v (N + 2 entries, the last two never read)
     // The LDS of the T and V/P rows (the first 2N CSR slots) holds the
     // energy- and mole-weighted partial sums; the finished rows are staged
     // in the G and H arrays.
@@ -380,12 +384,13 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
         }
         for (int k = g; k < ns + 1; k += G) AT(W, k) = 0.0;
         if (JAC) {
-            for (int e = g; e < nnz; e += G) AT(J, e) = 0.0;
+            for (int e = g; e < nj; e += G) AT(J, e) = 0.0;
             for (int k = g; k < ns; k += G) AT(B, k) = 0.0;
         }
         if (ADJ) {
             for (int i = g; i < N; i += G)
                 AT(VV, i) = LAYOUT == PJ_LAYOUT_F ? vin[(long)i * n + sc] : vin[sc * (long)N + i];
+            for (int i = g; i < N + 2; i += G) AT(JTV, i) = 0.0;
         }
         acc = block_dd_sum<S>(acc, red, wave, nwave, s, SR);
         const double nsum = acc.hi;
@@ -431,6 +436,10 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
 
         // ---- reactions: rates of progress and Jacobian sub-products
         double racc[4] = {0.0, 0.0, 0.0, 0.0};  // TT, TS, ST, SS
+        // adjoint: sum_i vn_i V dq_i/dT and V dq_i/dS (the T and V/P columns
+        // of J^T v from the species rows), and sum_i vn_i Q_Ns,i (the bath
+        // gas's partial, which the dense rows take out of every species column)
+        double aacc[3] = {0.0, 0.0, 0.0};
         // Deterministic accumulation: every thread runs the same number of
         // iterations (lanes past the last reaction redo it and add nothing);
         // each iteration computes in parallel, then the waves add their
@@ -595,7 +604,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             };
             if constexpr (!DET) scatter_w();
             // Jacobian sub-products of this reaction (what its scatter adds)
-            double Qs[NSLOT], QM = 0.0, dE = 0.0, dOm = 0.0, Vt = 0.0, Vs = 0.0, bam1 = 0.0;
+            double Qs[NSLOT], QM = 0.0, dE = 0.0, dOm = 0.0, Vt = 0.0, Vs = 0.0, bam1 = 0.0, vn = 0.0;
             if constexpr (JAC) {
             // concentration partials of q (zero for empty slots and for the
             // products of an irreversible reaction)
@@ -636,10 +645,9 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 racc[3] += dOm * dqdS;
             }
 
-            if (ADJ && grad) {
-                // lambda_i = v . df/dq_i, times dq_i/d ln A; summed over the
-                // workgroup's states (the S lanes of this reaction are adjacent)
-                double vn = 0.0;
+            // adjoint: vn = sum over the reaction's species rows of nu v, so
+            // that its part of v^T J is vn times the gradient of its rate
+            if constexpr (ADJ) {
 #pragma unroll
                 for (int a = 0; a < NSLOT; ++a) {
                     if (!((cmask >> a) & 1)) continue;
@@ -647,6 +655,10 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                     const double vk = AT(VV, row ? 2 + spc[a] : 0);
                     vn += row ? sg[a] * vk : 0.0;
                 }
+            }
+            if (ADJ && grad) {
+                // lambda_i = v . df/dq_i, times dq_i/d ln A; summed over the
+                // workgroup's states (the S lanes of this reaction are adjacent)
                 const double dTdq = -T * dE / Dp;
                 const double dSdq = FORM == PJ_CONP ? V * invT * dTdq + V * RU * T / P * dOm
                                                     : P * invT * dTdq + RU * T * dOm;
@@ -681,6 +693,11 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
 
             Vt = V * dqdT;
             Vs = V * dqdS;
+            if constexpr (ADJ) {
+                aacc[0] += vn * Vt;
+                aacc[1] += vn * Vs;
+                if ((w & INFO_BATH) && !dm.approx) aacc[2] += vn * Qb;
+            }
             }
 
             // the Jacobian's LDS additions of this reaction
@@ -710,6 +727,21 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                     }
                 }
             }
+            if constexpr (ADJ) {
+            // J^T v: the reaction adds vn Q_b to column b (the bath gas's and
+            // empty slots' go to entries N and N + 1, never read; irreversible
+            // products have Q_b = +-0), vn Q_k (alpha_k - 1) to third body k
+#pragma unroll
+            for (int b = 0; b < NSLOT; ++b) {
+                if (!((cmask >> b) & 1) || (b >= MAXSIDE && !any_rev)) continue;
+                atomicAdd(&AT(JTV, 2 + spc[b]), vn * Qs[b]);
+            }
+            if (neffc) {
+#pragma unroll
+                for (int e = 0; e < MAXEFF; ++e)
+                    if (e < neffc) atomicAdd(&AT(JTV, 2 + eff_species(esp, e)), vn * qe[e]);
+            }
+            } else {
             // species rows; the slot table holds NOSLOT for pairs that do not
             // exist (empty slots, irreversible products, bath-gas columns)
             const JacRec jr = load_rec(dm.jrec + p);
@@ -758,6 +790,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 }
             }
             }
+            }
             };
             if constexpr (!DET) {
                 scatter_j();
@@ -774,13 +807,20 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
         __syncthreads();
 
         // ---- source terms (Sec. 2.2)
-        double fsum[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        fsum[0] = 0.0;  // N' = sum e_k/(RT) wdot_k
-        fsum[1] = 0.0;  // Omega
+        // fsum: N' = sum e_k/(RT) wdot_k, Omega, then (Jacobian) sum chat_k/R
+        // wdot_k and the T and V/P rows' sums, then (adjoint) the T and V/P
+        // columns of J^T v from the species rows and the bath partial sum
+        constexpr int NF = ADJ ? 10 : 7;
+        double fsum[NF];
+#pragma unroll
+        for (int q = 0; q < NF; ++q) fsum[q] = 0.0;
         if (JAC) {
-            fsum[2] = 0.0;  // sum chat_k/R wdot_k
 #pragma unroll
             for (int q = 0; q < 4; ++q) fsum[3 + q] = racc[q];
+        }
+        if constexpr (ADJ) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) fsum[7 + q] = aacc[q];
         }
         for (int k = g; k < ns; k += G) {
             const double wk = AT(W, k);
@@ -788,6 +828,8 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             fsum[0] += ek * wk;
             fsum[1] += dm.wfac[k] * wk;
             if (JAC) fsum[2] += AT(CP, k) * wk;
+            // CONP: d(V wdot_k)/dV = wdot_k + V dwdot_k/dV, row k's V column
+            if (ADJ && FORM == PJ_CONP && k < ns - 1) fsum[8] += AT(VV, 2 + k) * wk;
         }
         block_sum<S>(fsum, red, wave, nwave, s, SR);
         const double Np = fsum[0], Om = fsum[1];
@@ -838,8 +880,11 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                     j1 = FORM == PJ_CONP ? V * invT * j0 + RTP * (AT(SQ, k) - sqb)
                                          : P * invT * j0 + RU * T * (AT(SQ, k) - sqb) * invV;
                 }
-                if (ADJ) {
-                    AT(JTV, j) = vT * j0 + vS * j1;
+                if constexpr (ADJ) {
+                    // the T and V/P rows' part, the species rows' part in the T
+                    // and V/P columns, and the dense rows' bath partial (every
+                    // species column)
+                    AT(JTV, j) += vT * j0 + vS * j1 + (j == 0 ? fsum[7] : j == 1 ? fsum[8] : -fsum[9]);
                 } else {
                     // staged in the g and h arrays (no longer needed) and
                     // written with the species rows, in output order
@@ -847,37 +892,23 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                     AT(H, j) = j1;
                 }
             }
-            // bath-gas dependent rows are dense: subtract their bath partial
-            for (int d = 0; d < dm.n_dense_rows; ++d) {
-                const int k = dm.dense_rows[d];
-                const int r0 = dm.row_ptr[2 + k] + 2, r1 = dm.row_ptr[3 + k];
-                const double bk = AT(B, k);
-                for (int e = r0 + g; e < r1; e += G) AT(J, e) -= bk;
-            }
-            if (FORM == PJ_CONP) {
-                // d(V wdot_k)/dV = wdot_k + V dwdot_k/dV
-                for (int k = g; k < ns - 1; k += G) AT(J, dm.row_ptr[2 + k] + 1) += AT(W, k);
+            if constexpr (!ADJ) {
+                // bath-gas dependent rows are dense: subtract their bath partial
+                for (int d = 0; d < dm.n_dense_rows; ++d) {
+                    const int k = dm.dense_rows[d];
+                    const int r0 = dm.row_ptr[2 + k] + 2, r1 = dm.row_ptr[3 + k];
+                    const double bk = AT(B, k);
+                    for (int e = r0 + g; e < r1; e += G) AT(J, e) -= bk;
+                }
+                if (FORM == PJ_CONP) {
+                    // d(V wdot_k)/dV = wdot_k + V dwdot_k/dV
+                    for (int k = g; k < ns - 1; k += G) AT(J, dm.row_ptr[2 + k] + 1) += AT(W, k);
+                }
             }
         }
         __syncthreads();
 
         if (ADJ) {
-            // species rows: J_kj v_k into column j, with several entries'
-            // (column, row) table reads in flight per lane
-            constexpr int TU = 8;
-            int e = 2 * N + g;
-            for (; e + (TU - 1) * G < nnz; e += TU * G) {
-                uint16_t c[TU], r[TU];
-#pragma unroll
-                for (int u = 0; u < TU; ++u) {
-                    c[u] = dm.col_idx[e + u * G];
-                    r[u] = dm.row_of[e + u * G];
-                }
-#pragma unroll
-                for (int u = 0; u < TU; ++u) atomicAdd(&AT(JTV, c[u]), AT(J, e + u * G) * AT(VV, r[u]));
-            }
-            for (; e < nnz; e += G) atomicAdd(&AT(JTV, dm.col_idx[e]), AT(J, e) * AT(VV, dm.row_of[e]));
-            __syncthreads();
             if (valid)
                 for (int i = g; i < N; i += G) {
                     if (LAYOUT == PJ_LAYOUT_F) jac[(long)i * n + st] = AT(JTV, i);
@@ -986,7 +1017,8 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
 
 // LDS offset (doubles) of the adjoint's per-workgroup parameter sums
 __device__ inline size_t gr_offset(const DevMech& dm, int S, int nwave) {
-    return ((size_t)5 * (dm.ns + 1) + (size_t)RED_PER_WAVE * nwave + dm.nnz + dm.ns + 2 * (size_t)dm.N) * S;
+    return ((size_t)5 * (dm.ns + 1) + (size_t)RED_PER_WAVE * nwave + 2 * (size_t)dm.N + dm.ns +
+            2 * (size_t)dm.N + 2) * S;
 }
 
 // Groups of S consecutive states.  Consecutive groups go to workgroups of

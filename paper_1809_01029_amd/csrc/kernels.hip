@@ -7,8 +7,10 @@ namespace pj {
 
 int64_t lds_bytes(const DevMech& dm, int mode, int S, int waves, bool grad_in_lds) {
     int64_t d = 5 * (int64_t)(dm.ns + 1);
-    if (mode != MODE_SRC) d += dm.nnz + dm.ns;
-    if (mode == MODE_ADJ) d += 2 * (int64_t)dm.N;
+    // Jacobian accumulator (the adjoint: only the T and V/P rows' sums), the
+    // bath-gas sums; the adjoint's v and J^T v (N + 2)
+    if (mode != MODE_SRC) d += (mode == MODE_ADJ ? 2 * (int64_t)dm.N : dm.nnz) + dm.ns;
+    if (mode == MODE_ADJ) d += 2 * (int64_t)dm.N + 2;
     const int64_t per_group = mode == MODE_ADJ && grad_in_lds ? 3 * (int64_t)dm.nr_pad : 0;
     return (d * S + (int64_t)RED_PER_WAVE * waves * S + per_group) * 8;
 }
