@@ -256,6 +256,8 @@ def main():
                     help="run only the FP64 weight calibration launches of exp, log and log10")
     ap.add_argument("--source-only", action="store_true",
                     help="time the source-term kernel alone (for its profiles), not the benchmark step")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time the adjoint kernel alone (J^T v and parameter sums, for its profiles)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -316,6 +318,28 @@ def main():
         t = e0.elapsed_time(e1) / args.steps
         print(json.dumps({"source_only_ms": round(t, 4), "states_per_s": n / (t * 1e-3), "n_states": n,
                           "workload": args.workload, "launch_shape": list(mech.launch_shape(0))}), flush=True)
+        return
+    if args.adjoint_only:
+        # the adjoint kernel alone (v ~ N(0, 1), seed 7), in the shape its
+        # autotuner picks unless --launch gives one
+        g = torch.Generator(device="cpu").manual_seed(7)
+        vs = torch.randn(xs.shape, generator=g, dtype=torch.float64).cuda()
+        jtv = torch.empty_like(xs)
+        grad = torch.empty((3, mech.n_reactions), dtype=torch.float64, device="cuda")
+        if not args.no_autotune:
+            api.autotune(mech, xs, ps, args.form, args.layout, mode="adjoint", reps=2, stream=stream)
+        for _ in range(args.warmup):
+            api.eval_adjoint(mech, xs, ps, vs, args.form, args.layout, jtv=jtv, grad=grad, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            api.eval_adjoint(mech, xs, ps, vs, args.form, args.layout, jtv=jtv, grad=grad, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / args.steps
+        print(json.dumps({"adjoint_ms": round(t, 4), "states_per_s": n / (t * 1e-3), "n_states": n,
+                          "workload": args.workload, "launch_shape": list(mech.launch_shape(3))}), flush=True)
         return
     if not args.no_autotune:
         # outside the timed region: pick the fastest launch shape for this batch
