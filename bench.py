@@ -122,11 +122,12 @@ def ragged_batch(api, synth, torch, tmp, args, stream, timeit):
         # best shape) and one launch per segment (at each mechanism's shape)
         b.autotune(mode, args.form, args.layout, reps=1, stream=stream)
         chosen = b.strategy(mode)
-        t_plain = timeit(plain)
-        t_batch = timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream))
-        t_graph = timeit(lambda: b.eval(mode, args.form, args.layout, graph=True, stream=stream))
+        # medians of 7 timings: the three strategies differ by a few per cent
+        t_plain = timeit(plain, trials=7)
+        t_batch = timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream), trials=7)
+        t_graph = timeit(lambda: b.eval(mode, args.form, args.layout, graph=True, stream=stream), trials=7)
         b.set_strategy(mode, not chosen)
-        t_other = timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream))
+        t_other = timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream), trials=7)
         t_persist, t_perseg = (t_other, t_batch) if chosen else (t_batch, t_other)
         out[mode] = {"per_mechanism_ms": round(t_plain, 4), "batch_ms": round(t_batch, 4),
                      "graph_ms": round(t_graph, 4),
@@ -173,10 +174,11 @@ def many_small_batch(api, synth, torch, tmp, args, stream, timeit, nseg=16, coun
         for sg in segs:
             b.add(me, sg["xs"], sg["ps"], args.layout, out=sg["j"] if mode == "sparse" else None, dstate=sg["d"])
         b.autotune(mode, args.form, args.layout, reps=3, stream=stream)
-        out[mode] = {"per_segment_launches_ms": round(timeit(plain, k=20), 4),
-                     "batch_ms": round(timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream), k=20), 4),
+        out[mode] = {"per_segment_launches_ms": round(timeit(plain, k=20, trials=5), 4),
+                     "batch_ms": round(timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream), k=20,
+                                              trials=5), 4),
                      "graph_ms": round(timeit(lambda: b.eval(mode, args.form, args.layout, graph=True,
-                                                             stream=stream), k=20), 4),
+                                                             stream=stream), k=20, trials=5), 4),
                      "batch_strategy": "per_segment" if b.strategy(mode) else "persistent",
                      "persistent_shape": list(b.launch_shape(mode))}
         b.close()
@@ -378,17 +380,22 @@ def main():
 
     variants = {}
     if not args.no_variants:
-        def timeit(fn, k=5):
+        def timeit(fn, k=5, trials=1):
+            """ms per call of k back-to-back calls after one untimed call;
+            the median over ``trials`` such timings"""
             fn()
             torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(k):
-                fn()
-            b.record(stream)
-            torch.cuda.synchronize()
-            return a.elapsed_time(b) / k
+            ts = []
+            for _ in range(trials):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(k):
+                    fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b) / k)
+            return sorted(ts)[len(ts) // 2]
         out_src = torch.empty_like(xs)
         if not args.no_autotune:
             api.autotune(mech, xs, ps, args.form, args.layout, mode="source", reps=2, stream=stream)

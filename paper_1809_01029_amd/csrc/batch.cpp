@@ -96,6 +96,19 @@ int64_t plan_lds(const pj_batch* b, const Plan& pl) {
 // the LDS the batch needs at S x W (its largest segment at S states)
 int64_t batch_lds(const pj_batch* b, int mode, int S, int W) { return make_plan(b, mode, S, W).need; }
 
+// the states per group shared by every non-empty segment, when 1, 2 or 4
+int uniform_states(const pj_batch* b, int mode, int S, int W) {
+    const Plan pl = make_plan(b, mode, S, W);
+    int u = 0;
+    for (auto& sg : b->segs) {
+        if (sg.n == 0) continue;
+        const int s = pl.states(sg);
+        if (u && s != u) return 0;
+        u = s;
+    }
+    return u == 1 || u == 2 || u == 4 ? u : 0;
+}
+
 // launch shape of the batch for a mode: the user's (or autotuned) if it
 // fits, else the most states per workgroup (<= 4) that fit every segment's
 // working set, with enough waves for about 8 resident waves per compute unit
@@ -210,7 +223,8 @@ pj_status enqueue(pj_batch* b, int mode, pj_form form, pj_layout layout, int S, 
     const int64_t lds = plan_lds(b, make_plan(b, mode, S, W));
     int ext = 0;   // the further reaction types' kernels if any segment needs them
     for (auto& sg : b->segs) ext |= sg.mech->m.dm.ext;
-    hipError_t e = pj::launch_batch(mode, form, layout, W, lds, b->d_segs, b->table_nseg, b->table_total, ext, st);
+    hipError_t e = pj::launch_batch(mode, form, layout, W, lds, b->d_segs, b->table_nseg, b->table_total, ext,
+                                    uniform_states(b, mode, S, W), st);
     if (e != hipSuccess) return fail(PJ_E_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
     return PJ_OK;
 }
@@ -255,6 +269,7 @@ int64_t batch_launch_lds(const pj_batch* b, int mode, int S, int W) {
 int batch_fill_table(const pj_batch* b, int mode, int S, int W, BatchSeg* t, int cap, long* total, int* ext) {
     return fill_table(b, mode, S, W, t, cap, total, ext);
 }
+int batch_uniform_states(const pj_batch* b, int mode, int S, int W) { return uniform_states(b, mode, S, W); }
 int batch_lds_limit(const pj_batch* b) { return lds_max_of(b); }
 
 }  // namespace pj

@@ -255,15 +255,17 @@ hipError_t zero_async(double* p, int64_t n, hipStream_t stream);
 // batch kernel (modes source, sparse, adjoint; each segment's states per
 // group and adjoint parameter-sum placement in its table entry)
 // ext: some segment's mechanism holds the further reaction types
+// su: the states per group every segment takes (1, 2 or 4: a compile-time
+// group body), or 0 (each segment's own, read at run time)
 hipError_t launch_batch(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,
-                        int nseg, int64_t total_groups, int ext, hipStream_t stream);
+                        int nseg, int64_t total_groups, int ext, int su, hipStream_t stream);
 // kernels_ext.hip: the same launches for mechanisms with the further reaction types
 hipError_t launch_ext(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
                       const double* state, const double* param, double* dstate, double* jac,
                       const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,
                       hipStream_t stream);
 hipError_t launch_batch_ext(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,
-                            int nseg, int64_t total_groups, hipStream_t stream);
+                            int nseg, int64_t total_groups, int su, hipStream_t stream);
 // api.cpp
 void choose_launch(Mechanism& m);
 
@@ -331,5 +333,8 @@ int64_t batch_launch_lds(const pj_batch* b, int mode, int S, int W);
 // entries): the entry count (-1 beyond cap), the groups of all in *total,
 // whether a mechanism needs the further reaction types' kernels in *ext
 int batch_fill_table(const pj_batch* b, int mode, int S, int W, BatchSeg* t, int cap, long* total, int* ext);
+// the states per group all non-empty segments share at S x W when it is 1, 2
+// or 4 (the batch kernel then has a compile-time group body), else 0
+int batch_uniform_states(const pj_batch* b, int mode, int S, int W);
 int batch_lds_limit(const pj_batch* b);
 }  // namespace pj

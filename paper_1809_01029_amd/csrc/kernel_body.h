@@ -1037,8 +1037,12 @@ __device__ inline void group_range(long ngroups, long& q0, long& q1, long& qstep
     }
 }
 
+// (source terms: held to the register count of 3 waves per SIMD; the
+// compiler otherwise gives some state counts a few registers more and two
+// waves per SIMD)
 template <int FORM, int LAYOUT, int MODE, int S, bool EXT>
-__global__ void __launch_bounds__(MAX_THREADS) pj_kernel(const DevMech dm, const long n,
+__global__ void __launch_bounds__(MAX_THREADS) __attribute__((amdgpu_waves_per_eu(base_mode(MODE) == MODE_SRC ? 3 : 1)))
+pj_kernel(const DevMech dm, const long n,
                                                           const double* __restrict__ state,
                                                           const double* __restrict__ param,
                                                           double* __restrict__ dstate,
@@ -1090,8 +1094,9 @@ __device__ inline void flush_gr(const BatchSeg& b, const double* GR) {
 }
 
 // (source terms: held to the register count of 3 waves per SIMD, as the
-// per-mechanism source kernel is)
-template <int FORM, int LAYOUT, int MODE, bool EXT>
+// per-mechanism source kernel is).  SU > 0: every segment takes SU states
+// per group, a compile-time body; SU = 0: each its own, read at run time.
+template <int FORM, int LAYOUT, int MODE, bool EXT, int SU>
 __global__ void __launch_bounds__(MAX_THREADS) __attribute__((amdgpu_waves_per_eu(MODE == MODE_SRC ? 3 : 1)))
 pj_batch_kernel(const BatchSeg* __restrict__ segs, const int nseg, const long total) {
     extern __shared__ double lds[];
@@ -1114,9 +1119,9 @@ pj_batch_kernel(const BatchSeg* __restrict__ segs, const int nseg, const long to
             for (int i = threadIdx.x; i < 3 * b.dm.nr_pad; i += blockDim.x) GR[i] = 0.0;
             __syncthreads();
         }
-        const int bs = b.S;
+        const int bs = SU > 0 ? SU : b.S;
         for (long q = q0; q < q1; q += qstep)
-            eval_group<FORM, LAYOUT, MODE, 0, EXT>(b.dm, b.n, b.state, b.param, b.dstate, b.out, b.vin,
+            eval_group<FORM, LAYOUT, MODE, SU, EXT>(b.dm, b.n, b.state, b.param, b.dstate, b.out, b.vin,
                                                    b.grad, use_gr && b.grad, GR, q, bs);
         if (use_gr) flush_gr(b, GR);
     }
@@ -1165,10 +1170,10 @@ static hipError_t launch_t(const DevMech& dm, int64_t n, const double* state, co
     return hipGetLastError();
 }
 
-template <int FORM, int LAYOUT, int MODE, bool EXT>
+template <int FORM, int LAYOUT, int MODE, bool EXT, int SU>
 static hipError_t launch_batch_t(int waves, int64_t lds, const BatchSeg* segs, int nseg, int64_t total,
                                  hipStream_t stream) {
-    auto k = pj_batch_kernel<FORM, LAYOUT, MODE, EXT>;
+    auto k = pj_batch_kernel<FORM, LAYOUT, MODE, EXT, SU>;
     if (lds > 65536) {
         static std::atomic<uint64_t> done{0};
         hipError_t e = allow_full_lds((const void*)k, done);
@@ -1223,10 +1228,14 @@ hipError_t launch_impl(const DevMech& dm, int mode, int form, int layout, int S,
 
 template <bool EXT>
 hipError_t launch_batch_impl(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,
-                             int nseg, int64_t total, hipStream_t stream) {
-#define PJ_BCASE(F, L, M)                                                                \
-    if (form == F && layout == L && mode == M)                                           \
-        return launch_batch_t<F, L, M, EXT>(waves, lds, d_segs, nseg, total, stream);
+                             int nseg, int64_t total, int su, hipStream_t stream) {
+#define PJ_BCASE(F, L, M)                                                                       \
+    if (form == F && layout == L && mode == M) {                                                \
+        if (su == 1) return launch_batch_t<F, L, M, EXT, 1>(waves, lds, d_segs, nseg, total, stream); \
+        if (su == 2) return launch_batch_t<F, L, M, EXT, 2>(waves, lds, d_segs, nseg, total, stream); \
+        if (su == 4) return launch_batch_t<F, L, M, EXT, 4>(waves, lds, d_segs, nseg, total, stream); \
+        return launch_batch_t<F, L, M, EXT, 0>(waves, lds, d_segs, nseg, total, stream);            \
+    }
 #define PJ_BMODES(F, L) PJ_BCASE(F, L, MODE_SRC) PJ_BCASE(F, L, MODE_SPARSE) PJ_BCASE(F, L, MODE_ADJ)
     PJ_BMODES(PJ_CONP, PJ_LAYOUT_F)
     PJ_BMODES(PJ_CONP, PJ_LAYOUT_C)

@@ -39,9 +39,9 @@ hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int6
 }
 
 hipError_t launch_batch(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,
-                        int nseg, int64_t total, int ext, hipStream_t stream) {
-    if (ext) return launch_batch_ext(mode, form, layout, waves, lds, d_segs, nseg, total, stream);
-    return launch_batch_impl<false>(mode, form, layout, waves, lds, d_segs, nseg, total, stream);
+                        int nseg, int64_t total, int ext, int su, hipStream_t stream) {
+    if (ext) return launch_batch_ext(mode, form, layout, waves, lds, d_segs, nseg, total, su, stream);
+    return launch_batch_impl<false>(mode, form, layout, waves, lds, d_segs, nseg, total, su, stream);
 }
 
 }  // namespace pj

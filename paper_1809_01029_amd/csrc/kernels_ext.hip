@@ -13,8 +13,8 @@ hipError_t launch_ext(const DevMech& dm, int mode, int form, int layout, int S, 
 }
 
 hipError_t launch_batch_ext(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,
-                            int nseg, int64_t total, hipStream_t stream) {
-    return launch_batch_impl<true>(mode, form, layout, waves, lds, d_segs, nseg, total, stream);
+                            int nseg, int64_t total, int su, hipStream_t stream) {
+    return launch_batch_impl<true>(mode, form, layout, waves, lds, d_segs, nseg, total, su, stream);
 }
 
 }  // namespace pj

@@ -89,7 +89,8 @@ extern "C" pj_status pj_batch_eval_noalloc(pj_batch* b, int mode, pj_form form, 
                                   hipMemcpyHostToDevice, st);
     if (e != hipSuccess)
         return pj::batch_fail(PJ_E_DEVICE, std::string("upload of the segment table: ") + hipGetErrorString(e));
-    e = pj::launch_batch(mode, form, layout, W, lds, d_table, nseg, g0, ext, st);
+    e = pj::launch_batch(mode, form, layout, W, lds, d_table, nseg, g0, ext,
+                         pj::batch_uniform_states(b, mode, S, W), st);
     if (e != hipSuccess) return pj::batch_fail(PJ_E_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
     pj::batch_ok();
     return PJ_OK;
