@@ -41,7 +41,8 @@ def log(*a):
 # with other versions of them is not reported.
 KERNEL_SOURCES = ["paper_1809_01029_amd/csrc/kernel_body.h", "paper_1809_01029_amd/csrc/kernels.hip",
                   "paper_1809_01029_amd/csrc/kernels_ext.hip", "paper_1809_01029_amd/csrc/internal.h",
-                  "paper_1809_01029_amd/csrc/mech.cpp", "paper_1809_01029_amd/csrc/api.cpp"]
+                  "paper_1809_01029_amd/csrc/mech.cpp", "paper_1809_01029_amd/csrc/api.cpp",
+                  "paper_1809_01029_amd/csrc/kernels_conv.hip", "paper_1809_01029_amd/csrc/kernels_ext_conv.hip"]
 
 
 def kernel_sources_sha256():

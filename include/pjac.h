@@ -257,10 +257,24 @@ int pj_mech_waves_per_state(const pj_mech* mech, int for_jacobian);
 int pj_mech_launch_shape(const pj_mech* mech, int mode, int* states_per_group, int* waves_per_group);
 
 /*
+ * The dense Jacobian's output loop reads the (row, column) -> CSR slot map of
+ * the entries it writes with `entries` reads in flight per lane: 16 (the
+ * default; 0 selects it) pays where a lane writes many entries, 8 where it
+ * writes few (small mechanisms, many states per workgroup); 16 applies at up
+ * to 4 states per workgroup, larger shapes read 8.  The autotuner of mode 2
+ * chooses it with the shape.  The values are identical either way.
+ * PJ_E_INVALID for NULL or another value; pj_mech_dense_unroll: the current
+ * choice, -1 for NULL.
+ */
+pj_status pj_mech_set_dense_unroll(pj_mech* mech, int entries);
+int pj_mech_dense_unroll(const pj_mech* mech);
+
+/*
  * Autotuner: time every launch shape that fits (states per workgroup 1, 2,
- * 4, ..., 64; waves per workgroup 1 to 8) for mode 0 (source), 1 (sparse
- * Jacobian) or 2 (dense Jacobian) on the caller's batch, and keep the fastest
- * for that mode until the next pj_mech_set_launch.  The buffers are those of
+ * 4, ..., 64; waves per workgroup 1 to 8; for mode 2 also the output loop's
+ * 8 or 16 map reads in flight, pj_mech_set_dense_unroll) for mode 0
+ * (source), 1 (sparse Jacobian) or 2 (dense Jacobian) on the caller's batch,
+ * and keep the fastest for that mode until the next pj_mech_set_launch.  The buffers are those of
  * the matching evaluation call (d_out: d_dstate for mode 0, the Jacobian
  * output otherwise; d_dstate_or_null: the fused source output of modes 1 and
  * 2) and are overwritten.  Every shape runs one warm-up launch and `reps`

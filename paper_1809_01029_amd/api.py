@@ -119,6 +119,10 @@ _lib.pj_mech_set_launch.argtypes = [_P, ctypes.c_int, ctypes.c_int]
 _lib.pj_mech_set_launch.restype = ctypes.c_int
 _lib.pj_mech_launch_shape.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.pj_mech_launch_shape.restype = ctypes.c_int
+_lib.pj_mech_set_dense_unroll.argtypes = [_P, ctypes.c_int]
+_lib.pj_mech_set_dense_unroll.restype = ctypes.c_int
+_lib.pj_mech_dense_unroll.argtypes = [_P]
+_lib.pj_mech_dense_unroll.restype = ctypes.c_int
 _lib.pj_mech_autotune.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _P, _P, _P, _P,
                                   ctypes.c_int, _P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(ctypes.c_float)]
@@ -208,6 +212,14 @@ class Mechanism:
     def set_launch(self, states_per_group: int = 0, waves_per_group: int = 0):
         _check(_lib.pj_mech_set_launch(self._h, int(states_per_group), int(waves_per_group)),
                "pj_mech_set_launch")
+
+    def set_dense_unroll(self, entries: int = 0):
+        """Map reads in flight per lane in the dense output (8 or 16; 0: the
+        default, 16), pj_mech_set_dense_unroll."""
+        _check(_lib.pj_mech_set_dense_unroll(self._h, int(entries)), "pj_mech_set_dense_unroll")
+
+    def dense_unroll(self) -> int:
+        return _lib.pj_mech_dense_unroll(self._h)
 
     def launch_shape(self, mode: int = 1):
         """(states per workgroup, waves per workgroup) of mode 0 (source),

@@ -34,7 +34,8 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = []
-    for src in ("mech.cpp", "api.cpp", "batch.cpp", "kernels.hip", "kernels_ext.hip", "calibrate.hip", "noalloc.hip"):
+    for src in ("mech.cpp", "api.cpp", "batch.cpp", "kernels.hip", "kernels_conv.hip", "kernels_ext.hip",
+                "kernels_ext_conv.hip", "calibrate.hip", "noalloc.hip"):
         o = os.path.join(BUILD, src + ".o")
         # host-only translation units: no device pass
         dev = DEVICE if src.endswith(".hip") else ["--offload-host-only"]

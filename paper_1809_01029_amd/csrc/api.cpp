@@ -28,6 +28,7 @@ constexpr int MAX_S = 64, MAX_WAVES = 8;
 // with its own Arrhenius parameters.
 int kernel_mode(const pj::Mechanism& m, int mode, bool per_call_arrhenius) {
     if (per_call_arrhenius) return mode == pj::MODE_SRC ? pj::MODE_SRC_P : pj::MODE_ADJ_P;
+    if (mode == pj::MODE_DENSE && m.dense_unroll == 16 && m.S[mode] <= 4) return pj::MODE_DENSE_U16;
     if (mode == pj::MODE_SPARSE && m.dm.lsearch) return pj::MODE_SPARSE_LS;
     if (m.dm.det && mode == pj::MODE_SRC) return pj::MODE_SRC_DET;
     if (m.dm.det && mode == pj::MODE_SPARSE) return pj::MODE_SPARSE_DET;
@@ -345,6 +346,17 @@ int pj_mech_waves_per_state(const pj_mech* mech, int for_jacobian) {
     return mech->m.S[mode] == 1 ? mech->m.waves[mode] : -1;
 }
 
+pj_status pj_mech_set_dense_unroll(pj_mech* mech, int entries) {
+    if (!mech) return fail(PJ_E_INVALID, "NULL mechanism");
+    if (entries != 0 && entries != 8 && entries != 16)
+        return fail(PJ_E_INVALID, "entries must be 0 (default, 16), 8 or 16");
+    mech->m.dense_unroll = entries == 8 ? 8 : 16;
+    g_err.clear();
+    return PJ_OK;
+}
+
+int pj_mech_dense_unroll(const pj_mech* mech) { return mech ? mech->m.dense_unroll : -1; }
+
 int pj_mech_launch_shape(const pj_mech* mech, int mode, int* states_per_group, int* waves_per_group) {
     if (!mech || mode < 0 || mode >= pj::N_MODES) return -1;
     if (states_per_group) *states_per_group = mech->m.S[mode];
@@ -368,8 +380,11 @@ pj_status autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int6
     pj_status st = eval(mech, mode, form, layout, n_states, d_state, d_param, dst, jac, stream, vin, grad);
     if (st != PJ_OK) return st;
     const bool gr = mode == pj::MODE_ADJ && m.adj_grad_in_lds;
-    const int kmode = kernel_mode(m, mode, false);
-    const int maxS = max_states(kmode);
+    const int kmode0 = kernel_mode(m, mode, false);
+    const int maxS = max_states(kmode0);
+    // the dense output's unroll width is a dimension of the search (8, 16)
+    const int n_du = mode == pj::MODE_DENSE ? 2 : 1;
+    int best_du = m.dense_unroll;
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -380,12 +395,16 @@ pj_status autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int6
     float best = -1.0f;
     std::string err;
     for (int S = 1; S <= maxS && err.empty(); S *= 2) {
-        for (int w = 1; w <= MAX_WAVES; ++w) {
-            const int64_t l = pj::lds_bytes(m.dm, mode, S, w, gr);
+        for (int w = 1; w <= MAX_WAVES * n_du && err.empty(); ++w) {
+            const int du = w > MAX_WAVES ? 8 : 16;
+            const int wv = w > MAX_WAVES ? w - MAX_WAVES : w;
+            const int kmode = n_du == 2 ? (du == 16 ? pj::MODE_DENSE_U16 : pj::MODE_DENSE) : kmode0;
+            if (kmode == pj::MODE_DENSE_U16 && S > 4) continue;   // built for at most 4 states
+            const int64_t l = pj::lds_bytes(m.dm, mode, S, wv, gr);
             if (l > m.lds_max) continue;
             auto go = [&]() {
                 return pj::launch(m.dm, kmode, form, layout, S, n_states, d_state, d_param, dst, jac, vin, grad,
-                                  gr ? 1 : 0, w, l, hs);
+                                  gr ? 1 : 0, wv, l, hs);
             };
             hipError_t e = go();
             if (e == hipSuccess) e = hipEventRecord(e0, hs);
@@ -399,7 +418,12 @@ pj_status autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int6
                 break;
             }
             t /= (float)reps;
-            if (best < 0.0f || t < best) { best = t; best_S = S; best_w = w; }
+            if (best < 0.0f || t < best) {
+                best = t;
+                best_S = S;
+                best_w = wv;
+                best_du = du;
+            }
         }
     }
     (void)hipEventDestroy(e0);
@@ -408,6 +432,7 @@ pj_status autotune(pj_mech* mech, int mode, pj_form form, pj_layout layout, int6
     m.S[mode] = best_S;
     m.waves[mode] = best_w;
     m.lds[mode] = pj::lds_bytes(m.dm, mode, best_S, best_w, gr);
+    if (mode == pj::MODE_DENSE) m.dense_unroll = best_du;
     if (states_per_group) *states_per_group = best_S;
     if (waves_per_group) *waves_per_group = best_w;
     if (ms) *ms = best;

@@ -200,6 +200,7 @@ struct Mechanism {
     std::vector<RxnRec> h_rec;
     size_t off_rec = 0;
     int user_S = 0, user_waves = 0;        // 0 = automatic
+    int dense_unroll = 16;                 // dense output: map entries in flight per lane (8 or 16)
     int lds_max = 0;
 };
 
@@ -237,11 +238,16 @@ enum Mode : int { MODE_SRC = 0, MODE_SPARSE = 1, MODE_DENSE = 2, MODE_ADJ = 3,
                   // source terms / sparse Jacobian with every LDS addition in a fixed
                   // order (the waves of a workgroup add in turn); shapes of MODE_SRC /
                   // MODE_SPARSE, at most 4 states per workgroup
-                  MODE_SRC_DET = 7, MODE_SPARSE_DET = 8 };
+                  MODE_SRC_DET = 7, MODE_SPARSE_DET = 8,
+                  // dense Jacobian writing its output with 16 map entries in flight
+                  // per lane instead of 8; launch shape of MODE_DENSE, at most 4
+                  // states per workgroup (more keep 8)
+                  MODE_DENSE_U16 = 9 };
 // the mode whose computation a kernel mode performs
 __host__ __device__ constexpr int base_mode(int m) {
     return m == MODE_SRC_P || m == MODE_SRC_DET ? MODE_SRC
-           : m == MODE_ADJ_P ? MODE_ADJ : m == MODE_SPARSE_DET ? MODE_SPARSE : m;
+           : m == MODE_ADJ_P ? MODE_ADJ : m == MODE_SPARSE_DET ? MODE_SPARSE
+           : m == MODE_DENSE_U16 ? MODE_DENSE : m;
 }
 constexpr int N_MODES = 4;        // modes with a launch shape of their own
 constexpr int MAX_S_ADJ = 4;      // states per workgroup of the adjoint mode
@@ -259,7 +265,17 @@ hipError_t zero_async(double* p, int64_t n, hipStream_t stream);
 // group body), or 0 (each segment's own, read at run time)
 hipError_t launch_batch(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,
                         int nseg, int64_t total_groups, int ext, int su, hipStream_t stream);
-// kernels_ext.hip: the same launches for mechanisms with the further reaction types
+// kernels_conv.hip, kernels_ext.hip, kernels_ext_conv.hip: the same launches
+// for the CONV form, for mechanisms with the further reaction types (CONP),
+// and for both (CONV)
+hipError_t launch_conv(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
+                       const double* state, const double* param, double* dstate, double* jac,
+                       const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,
+                       hipStream_t stream);
+hipError_t launch_ext_conv(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
+                           const double* state, const double* param, double* dstate, double* jac,
+                           const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,
+                           hipStream_t stream);
 hipError_t launch_ext(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
                       const double* state, const double* param, double* dstate, double* jac,
                       const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,

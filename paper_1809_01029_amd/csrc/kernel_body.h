@@ -963,8 +963,10 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             // accumulator through the (row, column) -> CSR slot maps (0 off
             // the pattern), the T and V/P rows from their staging
             // Each lane keeps DU map entries in flight: the map reads come from
-            // L2, and one at a time they would leave the loop latency-bound.
-            constexpr int DU = 8;
+            // L2, and one at a time they would leave the loop latency-bound
+            // (16 pays where a lane has many entries, 8 where it has few; the
+            // autotuner chooses)
+            constexpr int DU = MODE == MODE_DENSE_U16 ? 16 : 8;
             const long NN = (long)N * N;
             if (LAYOUT == PJ_LAYOUT_F) {
                 if (valid) {
@@ -1190,10 +1192,12 @@ static hipError_t launch_batch_t(int waves, int64_t lds, const BatchSeg* segs, i
 }
 
 
-// Launch of one instantiation set: EXT = false for mechanisms of elementary,
-// third-body, Lindemann and Troe reactions only (none of the further types'
-// code is compiled in), EXT = true otherwise.
-template <bool EXT>
+// Launch of one instantiation set of one form: EXT = false for mechanisms of
+// elementary, third-body, Lindemann and Troe reactions only (none of the
+// further types' code is compiled in), EXT = true otherwise.  The four sets
+// (EXT x form) are instantiated in four translation units, which build in
+// parallel.
+template <bool EXT, int FORM>
 hipError_t launch_impl(const DevMech& dm, int mode, int form, int layout, int S, int64_t n,
                        const double* state, const double* param, double* dstate, double* jac,
                        const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,
@@ -1208,16 +1212,16 @@ hipError_t launch_impl(const DevMech& dm, int mode, int form, int layout, int S,
 #define PJ_SA(F, L) PJ_CASE(F, L, MODE_ADJ, 1) PJ_CASE(F, L, MODE_ADJ, 2) PJ_CASE(F, L, MODE_ADJ, 4)
 #define PJ_SL(F, L) PJ_CASE(F, L, MODE_SPARSE_LS, 1) PJ_CASE(F, L, MODE_SPARSE_LS, 2) PJ_CASE(F, L, MODE_SPARSE_LS, 4)
 #define PJ_SAP(F, L) PJ_CASE(F, L, MODE_ADJ_P, 1) PJ_CASE(F, L, MODE_ADJ_P, 2) PJ_CASE(F, L, MODE_ADJ_P, 4)
+#define PJ_SU(F, L) PJ_CASE(F, L, MODE_DENSE_U16, 1) PJ_CASE(F, L, MODE_DENSE_U16, 2) PJ_CASE(F, L, MODE_DENSE_U16, 4)
 #define PJ_SD(F, L) PJ_CASE(F, L, MODE_SRC_DET, 1) PJ_CASE(F, L, MODE_SRC_DET, 2) PJ_CASE(F, L, MODE_SRC_DET, 4) \
     PJ_CASE(F, L, MODE_SPARSE_DET, 1) PJ_CASE(F, L, MODE_SPARSE_DET, 2) PJ_CASE(F, L, MODE_SPARSE_DET, 4)
 #define PJ_MODES(F, L) PJ_S(F, L, MODE_SRC) PJ_S(F, L, MODE_SPARSE) PJ_S(F, L, MODE_DENSE) PJ_SA(F, L) PJ_SL(F, L) \
-    PJ_S(F, L, MODE_SRC_P) PJ_SAP(F, L) PJ_SD(F, L)
-    PJ_MODES(PJ_CONP, PJ_LAYOUT_F)
-    PJ_MODES(PJ_CONP, PJ_LAYOUT_C)
-    PJ_MODES(PJ_CONV, PJ_LAYOUT_F)
-    PJ_MODES(PJ_CONV, PJ_LAYOUT_C)
+    PJ_S(F, L, MODE_SRC_P) PJ_SAP(F, L) PJ_SD(F, L) PJ_SU(F, L)
+    PJ_MODES(FORM, PJ_LAYOUT_F)
+    PJ_MODES(FORM, PJ_LAYOUT_C)
 #undef PJ_MODES
 #undef PJ_SD
+#undef PJ_SU
 #undef PJ_SAP
 #undef PJ_SL
 #undef PJ_SA

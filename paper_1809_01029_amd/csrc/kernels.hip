@@ -1,6 +1,8 @@
 // Kernel instantiations for mechanisms of the default reaction types
-// (elementary, third-body, Lindemann, Troe), the LDS sizing, the fill kernel
-// and the dispatch to the further types' instantiations (kernels_ext.hip).
+// (elementary, third-body, Lindemann, Troe) in the CONP form, the ragged
+// batch kernels of those types, the LDS sizing, the fill kernel, and the
+// dispatch to the CONV form (kernels_conv.hip) and to the further types'
+// instantiations (kernels_ext.hip, kernels_ext_conv.hip).
 #include "kernel_body.h"
 
 namespace pj {
@@ -31,11 +33,14 @@ hipError_t launch(const DevMech& dm, int mode, int form, int layout, int S, int6
                   const double* state, const double* param, double* dstate, double* jac,
                   const double* vin, double* grad, int grad_in_lds, int waves, int64_t lds,
                   hipStream_t stream) {
+    if (form == PJ_CONV)
+        return (dm.ext ? launch_ext_conv : launch_conv)(dm, mode, form, layout, S, n, state, param, dstate, jac,
+                                                        vin, grad, grad_in_lds, waves, lds, stream);
     if (dm.ext)
         return launch_ext(dm, mode, form, layout, S, n, state, param, dstate, jac, vin, grad, grad_in_lds,
                           waves, lds, stream);
-    return launch_impl<false>(dm, mode, form, layout, S, n, state, param, dstate, jac, vin, grad,
-                              grad_in_lds, waves, lds, stream);
+    return launch_impl<false, PJ_CONP>(dm, mode, form, layout, S, n, state, param, dstate, jac, vin, grad,
+                                       grad_in_lds, waves, lds, stream);
 }
 
 hipError_t launch_batch(int mode, int form, int layout, int waves, int64_t lds, const BatchSeg* d_segs,

@@ -185,6 +185,15 @@ def test_adjoint_and_arrhenius_argument_checks(api, tmp_path):
     # the adjoint mode keeps at most 4 states per workgroup
     mech.set_launch(16, 1)
     assert mech.launch_shape(3)[0] <= 4
+    # the dense output's map reads in flight: 8 or 16 (0: the default, 16)
+    assert mech.dense_unroll() == 16
+    mech.set_dense_unroll(8)
+    assert mech.dense_unroll() == 8
+    mech.set_dense_unroll(0)
+    assert mech.dense_unroll() == 16
+    for bad in (4, 12, 32, -1):
+        assert lib.pj_mech_set_dense_unroll(mech.handle, bad) == 1
+    assert lib.pj_mech_set_dense_unroll(None, 8) == 1 and lib.pj_mech_dense_unroll(None) == -1
 
 
 def test_batch_argument_checks(api, tmp_path):

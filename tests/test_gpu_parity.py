@@ -191,7 +191,8 @@ def test_autotune(torch_cuda, api, mode, mech_dir):
     mech = api.load_mechanism(path)
     xs, ps = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda()
     S, W, ms = api.autotune(mech, xs, ps, "conp", "C", mode=mode, reps=1)
-    note(f"autotune {mode}: S={S} waves={W} {ms:.4f} ms")
+    note(f"autotune {mode}: S={S} waves={W} {ms:.4f} ms, dense unroll {mech.dense_unroll()}")
+    assert mech.dense_unroll() in (8, 16)
     mi = api.MODES[mode]
     assert mech.launch_shape(mi) == (S, W)
     assert S in (1, 2, 4, 8, 16, 32, 64) and 1 <= W <= 8 and ms > 0
@@ -209,6 +210,38 @@ def test_autotune(torch_cuda, api, mode, mech_dir):
         Jg = api.eval_jacobian_dense(mech, xs, ps, "conp", "C", dstate=d).cpu().numpy()
     check_source(d.cpu().numpy(), f_o, f_s, f"autotuned {mode} (source terms)")
     check_jac(Jg, J_o, J_s, f"autotuned {mode}")
+
+
+@pytest.mark.parametrize("layout", ["F", "C"])
+@pytest.mark.parametrize("name,n", [("ns13", 333), ("ns53", 257), ("ns111", 131)])
+def test_dense_unroll_widths_agree(torch_cuda, api, name, n, layout, mech_dir):
+    """The dense output's 8 and 16 map reads in flight write the same bits
+    at one wave per workgroup (every LDS addition in program order; with
+    several waves two runs may differ in the last bits whatever the width),
+    at several states per workgroup and a ragged last group; both widths
+    meet the gates, also at a multi-wave shape."""
+    torch = torch_cuda
+    m, path = workload_file(name, mech_dir)
+    st = synth.make_states(m, n, 4242)
+    x, p = synth.pack_state(st, "conp", layout)
+    xc, pc = synth.pack_state(st, "conp", "C")
+    o = oracle.Oracle(path)
+    J_o, J_s = o.jacobian(xc, pc, "conp", bound=True)
+    mech = api.load_mechanism(path)
+    xs, ps = torch.from_numpy(x).cuda(), torch.from_numpy(p).cuda()
+    for S, w in [(1, 1), (2, 1), (4, 1), (2, 4)]:
+        mech.set_launch(S, w)
+        outs = []
+        for du in (8, 16):
+            mech.set_dense_unroll(du)
+            assert mech.dense_unroll() == du
+            outs.append(api.eval_jacobian_dense(mech, xs, ps, "conp", layout))
+        torch.cuda.synchronize()
+        note(f"dense unroll {name} {layout} shape {mech.launch_shape(2)}")
+        if w == 1:
+            assert torch.equal(outs[0], outs[1])
+        for du, o_ in zip((8, 16), outs):
+            check_jac(api.dense_as_sij(o_, layout).cpu().numpy(), J_o, J_s, f"dense S={S} w={w} unroll {du}")
 
 
 def test_one_wave_per_state_is_bitwise_reproducible(torch_cuda, api, mech_dir):
