@@ -98,7 +98,7 @@ def ragged_batch(api, synth, torch, tmp, args, stream, timeit):
     for mode in ("source", "adjoint"):
         for sg in segs:
             if mode == "source":
-                api.autotune(sg["mech"], sg["xs"], sg["ps"], args.form, args.layout, mode="source", reps=1,
+                api.autotune(sg["mech"], sg["xs"], sg["ps"], args.form, args.layout, mode="source", reps=2,
                              stream=stream)
 
         def plain():
@@ -111,7 +111,7 @@ def ragged_batch(api, synth, torch, tmp, args, stream, timeit):
                                      jtv=sg["jtv"], grad=sg["g"], stream=stream)
         if mode == "adjoint":
             for sg in segs:
-                api.autotune(sg["mech"], sg["xs"], sg["ps"], args.form, args.layout, mode="adjoint", reps=1,
+                api.autotune(sg["mech"], sg["xs"], sg["ps"], args.form, args.layout, mode="adjoint", reps=2,
                              stream=stream)
         b = api.Batch()
         for sg in segs:
@@ -120,8 +120,9 @@ def ragged_batch(api, synth, torch, tmp, args, stream, timeit):
             else:
                 b.add(sg["mech"], sg["xs"], sg["ps"], args.layout, out=sg["jtv"], v=sg["v"], grad=sg["g"])
         # the batch autotuner chooses between one persistent launch (at its
-        # best shape) and one launch per segment (at each mechanism's shape)
-        b.autotune(mode, args.form, args.layout, reps=1, stream=stream)
+        # best shape) and one launch per segment (at each mechanism's shape);
+        # three timed launches per candidate keep the choice above the noise
+        b.autotune(mode, args.form, args.layout, reps=3, stream=stream)
         chosen = b.strategy(mode)
         # medians of 7 timings: the three strategies differ by a few per cent
         t_plain = timeit(plain, trials=7)
