@@ -189,8 +189,10 @@ pj_status pj_eval_jacobian_dense(const pj_mech* mech, pj_form form, pj_layout la
  * Arrhenius parameters ln A, b and Ea/R (Sec. 2.2's rate constants; for
  * falloff and chemically activated reactions those of the high-pressure
  * limit, the low-pressure limit held fixed; for P-Log and Chebyshev reactions
- * those of the Arrhenius factor that multiplies the tabulated rate).  The Jacobian is formed on chip as for
- * pj_eval_jacobian_sparse and never written out.
+ * those of the Arrhenius factor that multiplies the tabulated rate).  J^T v
+ * is accumulated on chip from each reaction's rate gradient weighted by its
+ * stoichiometry and v (the Jacobian itself is never formed), with the same
+ * derivatives as pj_eval_jacobian_sparse.
  * d_v: N*n doubles, same layout as d_state; d_jtv: N*n doubles, same layout;
  * d_grad_or_null: NULL, or 3*Nr doubles [ln A (Nr), b (Nr), Ea/R (Nr)] in the
  * description's reaction order, overwritten with the batch sums (workgroups

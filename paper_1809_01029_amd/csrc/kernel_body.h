@@ -18,13 +18,16 @@
 //     C, G, H, CP, W   [Ns+1] concentrations, g = G/RT, h = H/RT, chat/R,
 //                      production rates; entry Ns is a sentinel (C = 1,
 //                      G = H = 0) that empty reaction slots point at
-//     J                [nnz]  CSR accumulator of the species rows
+//     J                [nnz]  CSR accumulator of the species rows (the
+//                      adjoint: only the 2N slots of TQ and SQ)
 //     B                [Ns]   per-row sum of the bath-gas partials
 //     TQ, SQ           [Ns+1] energy- and mole-weighted concentration
 //                      partials, kept in the space of CSR rows 0 and 1 (the
 //                      finished T and V/P rows are staged in the G and H
 //                      arrays and written out with the species rows)
-//     VV, JTV          [N]    (adjoint) the vector v and J^T v
+//     VV, JTV          [N], [N+2] (adjoint) the vector v and J^T v (two
+//                      entries past N catch the bath gas's and empty slots'
+//                      terms)
 //     GR               [3 Nr] (adjoint, per workgroup, not per state) the
 //                      workgroup's sums of the Arrhenius-parameter derivatives
 // Reactions scatter into these with LDS FP64 atomics (ds_add_f64).  Because
@@ -48,9 +51,15 @@
 // form of dV/dt or dP/dt; both need sum_i dE_i Q_ij and sum_i dOmega_i Q_ij,
 // accumulated in TQ and SQ.
 //
-// Adjoint.  J^T v is formed from the Jacobian as assembled in LDS (never
-// written to HBM): the T and V/P rows contribute v_T J_0j + v_S J_1j per
-// column, every species-row entry J_kj adds J_kj v_k to column j.  The
+// Adjoint.  J^T v is formed without the Jacobian: reaction i enters species
+// row k only as nu_ki times the gradient of q_i, so its part of v^T J is
+// vn_i grad q_i with vn_i = sum_k nu_ki v_k over its species rows.  It adds
+// vn_i Q_ij to column j (third bodies: vn_i Q_M (alpha_j - 1)), and per-thread
+// sums of vn_i V dq_i/dT, vn_i V dq_i/dS (the species rows' T and V/P
+// columns) and vn_i Q_iNs (the bath partial the dense rows take out of every
+// species column) are reduced with the source terms; the T and V/P rows then
+// add v_T J_0j + v_S J_1j to every column, and CONP adds sum_k v_k wdot_k to
+// the V column (d(V wdot_k)/dV = wdot_k + V dwdot_k/dV).  The
 // Arrhenius-parameter derivatives of v . dPhi/dt use that the source terms
 // depend on reaction i's parameters only through q_i:
 //     d(v . f)/d theta_i = lambda_i dq_i/d theta_i,
@@ -376,21 +385,22 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
 
         // ---- concentrations and the bath-gas closure (Sec. 2.2):
         //      n_Ns = P V / (R T) - RN(sum_{k<Ns} n_k)
+        // the accumulators are cleared while the state's loads are in flight
+        for (int k = g; k < ns + 1; k += G) AT(W, k) = 0.0;
+        if (JAC) {
+            for (int e = g; e < nj; e += G) AT(J, e) = 0.0;
+            for (int k = g; k < ns; k += G) AT(B, k) = 0.0;
+        }
+        if (ADJ) for (int i = g; i < N + 2; i += G) AT(JTV, i) = 0.0;
         dd acc{0.0, 0.0};
         for (int k = g; k < ns - 1; k += G) {
             const double nk = X(2 + k);
             acc = dd_add(acc, dd{nk, 0.0});
             AT(C, k) = nk / V;
         }
-        for (int k = g; k < ns + 1; k += G) AT(W, k) = 0.0;
-        if (JAC) {
-            for (int e = g; e < nj; e += G) AT(J, e) = 0.0;
-            for (int k = g; k < ns; k += G) AT(B, k) = 0.0;
-        }
         if (ADJ) {
             for (int i = g; i < N; i += G)
                 AT(VV, i) = LAYOUT == PJ_LAYOUT_F ? vin[(long)i * n + sc] : vin[sc * (long)N + i];
-            for (int i = g; i < N + 2; i += G) AT(JTV, i) = 0.0;
         }
         acc = block_dd_sum<S>(acc, red, wave, nwave, s, SR);
         const double nsum = acc.hi;
