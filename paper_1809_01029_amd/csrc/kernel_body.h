@@ -97,9 +97,13 @@ namespace pj {
 
 namespace {
 
-// LDS scratch of the workgroup reductions, per state and wave: up to 10 values
-constexpr int RED_PER_WAVE = 10;
+// LDS scratch of the workgroup reductions, per state and wave: up to 10
+// values; the last entry of the area (never reached by a reduction) holds the
+// reaction loop's block counter
+constexpr int RED_PER_WAVE = 11;
 constexpr int MAX_THREADS = 512;
+// s_waitcnt lgkmcnt(0) (vmcnt and expcnt at their maxima, gfx9 encoding)
+constexpr int WAIT_LGKM0 = 0xC07F;
 
 struct dd {
     double hi, lo;
@@ -146,7 +150,7 @@ __device__ inline double wave_sum(double v, int Sr = S) {
 // run time.
 template <int S, int K>
 __device__ inline void block_sum(double (&v)[K], double* red, int wave, int nwave, int s, int Sr = S) {
-    static_assert(K <= RED_PER_WAVE, "reduction scratch per wave");
+    static_assert(K <= RED_PER_WAVE - 1, "reduction scratch per wave");
     const int SR = S > 0 ? S : Sr;
 #pragma unroll
     for (int q = 0; q < K; ++q) v[q] = wave_sum<S>(v[q], SR);
@@ -355,6 +359,8 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
     double* W = CP + (ns + 1) * SR;
     double* red = W + (ns + 1) * SR;
     double* J = red + RED_PER_WAVE * nwave * SR;
+    // the reaction loop's block counter: the last entry of the reduction area
+    int* const bctr = reinterpret_cast<int*>(J - 1);
     // the adjoint forms J^T v without the Jacobian: of J it keeps the T and
     // V/P rows' partial sums only
     const int nj = ADJ ? 2 * N : nnz;
@@ -387,6 +393,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
         //      n_Ns = P V / (R T) - RN(sum_{k<Ns} n_k)
         // the accumulators are cleared while the state's loads are in flight
         for (int k = g; k < ns + 1; k += G) AT(W, k) = 0.0;
+        if (JAC && !DET && !ADJ && tid == 0) *bctr = 0;
         if (JAC) {
             for (int e = g; e < nj; e += G) AT(J, e) = 0.0;
             for (int k = g; k < ns; k += G) AT(B, k) = 0.0;
@@ -450,13 +457,43 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
         // of J^T v from the species rows), and sum_i vn_i Q_Ns,i (the bath
         // gas's partial, which the dense rows take out of every species column)
         double aacc[3] = {0.0, 0.0, 0.0};
+        // A wave's lanes take a block of 64/S consecutive reactions (inside
+        // one 64-reaction chunk).  The sparse and dense Jacobian kernels'
+        // waves take the blocks from a counter in LDS, the last-sorted ones
+        // (falloff and third-body reactions, the costliest) first, so that a
+        // wave given costly blocks takes fewer of them and all waves reach
+        // the end of the loop together.  The source-term and adjoint kernels
+        // keep the fixed round-robin order (the counter's code took the
+        // source kernels across their 3-wave register step, and the adjoint
+        // ran slower with it).
         // Deterministic accumulation: every thread runs the same number of
-        // iterations (lanes past the last reaction redo it and add nothing);
-        // each iteration computes in parallel, then the waves add their
-        // contributions one after the other.
-        for (int pb = 0; DET ? pb < dm.nr : g + pb < dm.nr; pb += G) {
-            const bool act = !DET || g + pb < dm.nr;
-            const int p = DET && !act ? dm.nr - 1 : g + pb;
+        // iterations over fixed blocks (lanes past the last reaction redo it
+        // and add nothing); each iteration computes in parallel, then the
+        // waves add their contributions one after the other.
+        constexpr bool QUEUE = JAC && !DET && !ADJ;
+        const int rb_lg = 6 - LG;    // log2 of the reactions per block
+        const int nblk = (dm.nr + (1 << rb_lg) - 1) >> rb_lg;
+        // the counter value of the wave's next block, taken during the block
+        // before it (after its rates, before its LDS additions, so that the
+        // return is not waited for behind them)
+        int cnx = 0;
+        if (QUEUE && (tid & 63) == 0) cnx = atomicAdd(bctr, 1);
+        for (int pb = 0;; pb += G) {
+            bool act;
+            int p;
+            if constexpr (!QUEUE) {
+                if (DET ? pb >= dm.nr : g + pb >= dm.nr) break;
+                act = !DET || g + pb < dm.nr;
+                p = DET && !act ? dm.nr - 1 : g + pb;
+            } else {
+                const int c = __builtin_amdgcn_readfirstlane(cnx);
+                if (c >= nblk) break;
+                p = ((nblk - 1 - c) << rb_lg) + ((tid & 63) >> LG);
+                // lanes past the last reaction redo it and add nothing (no
+                // divergent continue: the wave must reach the counter together)
+                act = p < dm.nr;
+                if (!act) p = dm.nr - 1;
+            }
             const RxnRec rr = load_rec(dm.rec + p);
             // slot positions any reaction of this 64-reaction chunk uses
             // (uniform over the wave: a wave's lanes take 64/S consecutive
@@ -612,7 +649,10 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                     if (nu[a]) atomicAdd(&AT(W, spc[a]), sg[a] * q);
                 }
             };
-            if constexpr (!DET) scatter_w();
+            if (QUEUE && (tid & 63) == 0) cnx = atomicAdd(bctr, 1);
+            if constexpr (!DET) {
+                if (act) scatter_w();
+            }
             // Jacobian sub-products of this reaction (what its scatter adds)
             double Qs[NSLOT], QM = 0.0, dE = 0.0, dOm = 0.0, Vt = 0.0, Vs = 0.0, bam1 = 0.0, vn = 0.0;
             if constexpr (JAC) {
@@ -674,7 +714,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                                                     : P * invT * dTdq + RU * T * dOm;
                 const double lam = vT * dTdq + vS * dSdq + V * vn;
                 // each state's own ln T and 1/T, before the sum over states
-                double g0 = valid ? lam * (q * qA - R * Pr_dcdPr) : 0.0;
+                double g0 = valid && act ? lam * (q * qA - R * Pr_dcdPr) : 0.0;
                 double g1 = g0 * lnT, g2 = -g0 * invT;
                 auto fold = [&](int o) {
                     g0 += __shfl_xor(g0, o, 64);
@@ -687,7 +727,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 } else {
                     for (int o = 1; o < SR; o <<= 1) fold(o);
                 }
-                if (s == 0) {
+                if (s == 0 && act) {
                     if (gr_lds) {
                         GR[p] += g0;
                         GR[dm.nr_pad + p] += g1;
@@ -703,7 +743,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
 
             Vt = V * dqdT;
             Vs = V * dqdS;
-            if constexpr (ADJ) {
+            if (ADJ && act) {
                 aacc[0] += vn * Vt;
                 aacc[1] += vn * Vs;
                 if ((w & INFO_BATH) && !dm.approx) aacc[2] += vn * Qb;
@@ -803,9 +843,14 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             }
             };
             if constexpr (!DET) {
-                scatter_j();
+                if (act) scatter_j();
             } else {
                 for (int ow = 0; ow < nwave; ++ow) {
+                    // the previous turn's LDS additions must be complete before
+                    // the barrier lets the next wave add: an explicit wait (the
+                    // barrier's own fence wait is not kept on this loop's back
+                    // edge, and the order of the turns then slips now and then)
+                    __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
                     __syncthreads();
                     if (wave == ow && act) {
                         scatter_w();
