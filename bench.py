@@ -450,9 +450,10 @@ def main():
                                                     stream=stream))
         variants[f"layout_{ol}_sparse"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3)}
         del xs3, ps3, jac3, d3
-        # fixed-order accumulation (bitwise reproducible) at the timed launch shape
+        # fixed-order accumulation (bitwise reproducible at any one launch
+        # shape), at the shape its own autotuning picks (outside the timing)
         mdet = api.load_mechanism(path, options=api.OPT_DETERMINISTIC)
-        mdet.set_launch(*mech.launch_shape(1))
+        api.autotune(mdet, xs, ps, args.form, args.layout, mode="sparse", reps=1, stream=stream)
         t = timeit(lambda: api.eval_jacobian_sparse(mdet, xs, ps, args.form, args.layout, out=jac,
                                                     dstate=dstate, stream=stream))
         variants["deterministic_sparse"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3),
