@@ -124,12 +124,14 @@ def ragged_batch(api, synth, torch, tmp, args, stream, timeit):
         # three timed launches per candidate keep the choice above the noise
         b.autotune(mode, args.form, args.layout, reps=3, stream=stream)
         chosen = b.strategy(mode)
-        # medians of 7 timings: the three strategies differ by a few per cent
-        t_plain = timeit(plain, trials=7)
-        t_batch = timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream), trials=7)
-        t_graph = timeit(lambda: b.eval(mode, args.form, args.layout, graph=True, stream=stream), trials=7)
+        # medians of 7 timings of 20 back-to-back calls each (the strategies
+        # differ by a few per cent; 20 calls amortise the first launch of a
+        # timing onto an idle GPU, which costs a graph launch more)
+        t_plain = timeit(plain, k=20, trials=7)
+        t_batch = timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream), k=20, trials=7)
+        t_graph = timeit(lambda: b.eval(mode, args.form, args.layout, graph=True, stream=stream), k=20, trials=7)
         b.set_strategy(mode, not chosen)
-        t_other = timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream), trials=7)
+        t_other = timeit(lambda: b.eval(mode, args.form, args.layout, stream=stream), k=20, trials=7)
         t_persist, t_perseg = (t_other, t_batch) if chosen else (t_batch, t_other)
         out[mode] = {"per_mechanism_ms": round(t_plain, 4), "batch_ms": round(t_batch, 4),
                      "graph_ms": round(t_graph, 4),
