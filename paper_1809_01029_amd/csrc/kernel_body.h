@@ -364,7 +364,12 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
     // the adjoint forms J^T v without the Jacobian: of J it keeps the T and
     // V/P rows' partial sums only
     const int nj = ADJ ? 2 * N : nnz;
-    double* B = J + (size_t)nj * SR;
+    // the sparse and dense kernels send the additions of row-column pairs
+    // that do not exist to 64 sink entries past the accumulator (entry
+    // nj + k for lane block k: 64/S per state), so that a scatter needs no
+    // per-lane branch and no two lanes of an instruction meet at a sink
+    constexpr int NSINK = JAC && !ADJ ? 64 : 0;
+    double* B = J + (size_t)nj * SR + NSINK;
     double* VV = B + (size_t)ns * SR;      // adjoint: v
     double* JTV = VV + (size_t)N * SR;     // adjoint: J^T v (N + 2 entries, the last two never read)
     // The LDS of the T and V/P rows (the first 2N CSR slots) holds the
@@ -793,8 +798,10 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
             }
             } else {
             // species rows; the slot table holds NOSLOT for pairs that do not
-            // exist (empty slots, irreversible products, bath-gas columns)
+            // exist (empty slots, irreversible products, bath-gas columns):
+            // their additions go to this lane's sink entry
             const JacRec jr = load_rec(dm.jrec + p);
+            const int sink = nj + ((tid & 63) >> LG);
 #pragma unroll
             for (int a = 0; a < NSLOT; ++a) {
                 if (!((cmask >> a) & 1)) continue;
@@ -809,7 +816,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                     if (LS)
                         sl = nu[b] && (b < MAXSIDE || rev) && spc[b] != bath
                                  ? csr_lookup(dm, 2 + spc[a], 2 + spc[b]) : NOSLOT;
-                    if (sl != NOSLOT) atomicAdd(&AT(J, sl), sg[a] * Qs[b]);
+                    atomicAdd(&AT(J, sl == NOSLOT ? sink : (int)sl), sg[a] * Qs[b]);
                 }
                 if (neffc) {
                     // third-body columns of this row: one 16-byte load
@@ -823,7 +830,7 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                             const int sp = eff_species(esp, e);
                             sl = sp < bath ? csr_lookup(dm, 2 + spc[a], 2 + sp) : NOSLOT;
                         }
-                        if (sl != NOSLOT) atomicAdd(&AT(J, sl), sg[a] * qe[e]);
+                        atomicAdd(&AT(J, sl == NOSLOT ? sink : (int)sl), sg[a] * qe[e]);
                     }
                 }
             }

@@ -13,7 +13,9 @@ int64_t lds_bytes(const DevMech& dm, int mode, int S, int waves, bool grad_in_ld
     // bath-gas sums; the adjoint's v and J^T v (N + 2)
     if (mode != MODE_SRC) d += (mode == MODE_ADJ ? 2 * (int64_t)dm.N : dm.nnz) + dm.ns;
     if (mode == MODE_ADJ) d += 2 * (int64_t)dm.N + 2;
-    const int64_t per_group = mode == MODE_ADJ && grad_in_lds ? 3 * (int64_t)dm.nr_pad : 0;
+    int64_t per_group = mode == MODE_ADJ && grad_in_lds ? 3 * (int64_t)dm.nr_pad : 0;
+    // the sparse and dense kernels' 64 sink entries for pairs that do not exist
+    if (mode == MODE_SPARSE || mode == MODE_DENSE) per_group += 64;
     return (d * S + (int64_t)RED_PER_WAVE * waves * S + per_group) * 8;
 }
 
