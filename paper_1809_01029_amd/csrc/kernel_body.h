@@ -646,12 +646,15 @@ __device__ __forceinline__ void eval_group(const DevMech& dm, const long n,
                 }
             }
             const double q = c * R;
-            // production rates
+            // production rates (the source-term kernels let an empty slot add
+            // 0 to the sentinel entry, never read, instead of branching; the
+            // Jacobian kernels keep the branch: without it and the T and V/P
+            // rows' one they ran 2 % slower)
             auto scatter_w = [&]() {
 #pragma unroll
                 for (int a = 0; a < NSLOT; ++a) {
                     if (!((cmask >> a) & 1)) continue;
-                    if (nu[a]) atomicAdd(&AT(W, spc[a]), sg[a] * q);
+                    if (!JAC || nu[a]) atomicAdd(&AT(W, spc[a]), sg[a] * q);
                 }
             };
             if (QUEUE && (tid & 63) == 0) cnx = atomicAdd(bctr, 1);
