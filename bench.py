@@ -442,6 +442,17 @@ def main():
         t = timeit(lambda: api.eval_jacobian_sparse(mech, xs2, ps2, other, args.layout, out=jac,
                                                     dstate=dstate, stream=stream))
         variants[f"{other}_sparse"] = {"ms": round(t, 4), "states_per_s": n / (t * 1e-3)}
+        if N * N * n * 8 < 60e9:
+            # the dense Jacobian in the other form as well (same layout)
+            dj = torch.empty((N, N, n) if args.layout == "F" else (n, N, N), dtype=torch.float64, device="cuda")
+            t = timeit(lambda: api.eval_jacobian_dense(mech, xs2, ps2, other, args.layout, out=dj,
+                                                       dstate=dstate, stream=stream), k=3)
+            db = (8 * (2 * N + 1) + 8 * N * N) * n
+            variants[f"dense_jacobian_{other}"] = {
+                "ms": round(t, 4), "states_per_s": n / (t * 1e-3), "layout": args.layout,
+                "hbm_GBps": db / (t * 1e-3) / 1e9, "frac": round(db / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "launch_shape": list(mech.launch_shape(2))}
+            del dj
         del xs2, ps2
         ol = "C" if args.layout == "F" else "F"
         x3, p3 = synth.pack_state(st, args.form, ol)
