@@ -106,9 +106,14 @@ def test_no_barrier_with_pending_lds_store(tmp_path):
     sig = ("(const DevMech, const long, const double* __restrict__, const double* __restrict__, "
            "double* __restrict__, double* __restrict__, const double* __restrict__, "
            "double* __restrict__, const int);")
-    inst = [("MODE_SRC_DET", 2), ("MODE_SPARSE_DET", 2), ("MODE_SPARSE", 2)]
+    inst = [("MODE_SRC_DET", 2), ("MODE_SPARSE_DET", 2), ("MODE_SPARSE", 2), ("MODE_DENSE_U16", 2), ("MODE_ADJ", 4)]
+    # the ragged batch kernel with the states per group known at run time (0)
+    # and at compile time (4)
+    batch = [("MODE_SPARSE", 0), ("MODE_ADJ", 4)]
     src = '#include "kernel_body.h"\nnamespace pj {\n' + "".join(
-        f"template __global__ void pj_kernel<PJ_CONP, PJ_LAYOUT_C, {m}, {s}, false>{sig}\n" for m, s in inst) + "}\n"
+        f"template __global__ void pj_kernel<PJ_CONP, PJ_LAYOUT_C, {m}, {s}, false>{sig}\n" for m, s in inst) + "".join(
+        f"template __global__ void pj_batch_kernel<PJ_CONP, PJ_LAYOUT_C, {m}, false, {su}>"
+        "(const BatchSeg* __restrict__, const int, const long);\n" for m, su in batch) + "}\n"
     f = tmp_path / "isa_check.hip"
     f.write_text(src)
     out = tmp_path / "isa_check.s"
